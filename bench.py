@@ -1,0 +1,162 @@
+"""MLFMA-SMR matrix-vector throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--rhs R]
+
+Workload: 40 x 40 dielectric cylinders (diameter 0.3, height 0.6, eps 6.25,
+pitch 0.5 wavelengths, 600-triangle jittered mesh, 15 + 15 static modes per
+current: 96,000 unknowns), FP32 complex product, R seeded random right-hand
+sides resident in HBM.  A step is one full product y = Z x (near blocks,
+leaf projection, aggregation, translation, disaggregation, receive).  The
+GMRES time to a 1e-4 true relative residual for one normal-incidence plane
+wave is reported beside it.
+
+Prints one JSON line.  The cpu_baseline leg times the FP64 oracle on a
+bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP32_VALU_PEAK = 157.3e12  # MI355X FP32 vector
+
+
+def cpu_baseline(wl, M):
+    """Oracle cost of one full dense product of this workload, from a bounded
+    sample: S distinct pair blocks computed by the oracle on all host cores,
+    plus block products timed on one core; extrapolated to the 6,241
+    distinct offset blocks and 1,600^2 block products of one product."""
+    import numpy as np
+
+    from oracle.pmchwt import DenseProblem, ParticleClass
+    cores = len(os.sched_getaffinity(0))
+    v, t, e = wl.meshes[0]
+    pc = ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r, M=M)
+    prob = DenseProblem([pc], wl.centers, wl.class_id)
+    P = wl.n_particles
+    S = max(8, 2 * cores)
+    row = 20 * 40 + 20
+    pairs = [(row, q) for q in range(P) if q != row][:S]
+    t0 = time.perf_counter()
+    prob.prefetch(pairs, workers=cores)
+    t_block = (time.perf_counter() - t0) / S
+    blocks = [prob.block(a, b) for a, b in pairs]
+    x = [np.asarray(b[0]) for b in blocks]
+    nrep = 4000
+    t0 = time.perf_counter()
+    acc = 0
+    for i in range(nrep):
+        acc = acc + blocks[i % S] @ x[(i + 1) % S]
+    t_gemv = (time.perf_counter() - t0) / nrep
+    nx = int(round(wl.centers[:, 0].max() / 0.5)) + 1
+    distinct = (2 * nx - 1) ** 2
+    T = distinct * t_block + P * P * t_gemv
+    unknowns = wl.n_unknowns
+    return {"value": unknowns / T, "unit": "unknowns*RHS/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{S} distinct pair blocks of the 40x40 array by oracle direct quadrature on {cores} "
+                       f"processes ({t_block:.3f} s/block wall) and {nrep} block products "
+                       f"({t_gemv * 1e6:.1f} us each, 1 core), extrapolated to {distinct} blocks + "
+                       f"{P * P} block products = {T:.0f} s per product")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rhs", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gmres", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the product is computed on a single MI355X; "
+              "multi-GPU sharding is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_2407_21724_amd import mlfma
+
+    torch.cuda.set_device(0)
+    wl = w.workload("c2")
+    v, t, e = wl.meshes[0]
+    t0 = time.perf_counter()
+    M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+    ctx = mlfma.Context(wl.centers, wl.class_id, 1, mlfma.default_params(precision=mlfma.C64))
+    ctx.set_static_modes(0, v, t, e, wl.n_perp, wl.n_par, M, wl.eps_r)
+    ctx.prepare()
+    setup_s = time.perf_counter() - t0
+    info = ctx.info()
+    R = args.rhs
+    P, n = wl.n_particles, 2 * (wl.n_perp + wl.n_par)
+    x = torch.as_tensor(w.random_complex((R, P, n), 1)).to("cuda", torch.complex64).contiguous()
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        ctx.matvec(x, out=y)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        ctx.matvec(x, out=y)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    stages = ctx.profile_read()
+    ctx.profile(False)
+    value = wl.n_unknowns * R / (ms * 1e-3)
+
+    # roofline of the dominant kernel (largest share of the timed region)
+    dom = max(stages, key=lambda s: s["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    if dom["name"].startswith(("translate", "aggregate", "disaggregate")):
+        achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    else:
+        achieved = dom["flops_per_launch"] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": achieved * 1e12 / FP32_VALU_PEAK, "traffic": None}
+    roof["kernel"] = dom["name"]
+    roof["avg_launch_us"] = avg_ms * 1e3
+
+    out = {
+        "metric": "MLFMA-SMR matvec throughput (unknowns*RHS/s); GMRES time-to-1e-4 reported beside it",
+        "value": value, "unit": "unknowns*RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "40x40 dielectric cylinders D0.3 H0.6 eps6.25 pitch0.5, 600-tri mesh, "
+                               "15+15 static modes, 96000 unknowns, FP32 matvec",
+                   "rhs": R, "levels": info["n_levels"], "L": info["L"], "K": info["K"]},
+        "roofline": roof,
+        "stages_us": {s["name"]: round(1e3 * s["total_ms"] / s["launches"], 2) for s in stages},
+        "setup_s": setup_s,
+    }
+    if not args.no_gmres:
+        inc = w.normal_incidence_x()
+        b = ctx.plane_wave_rhs(inc.khat[None], inc.pol[None])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=2000, restart=100)
+        torch.cuda.synchronize()
+        out["gmres"] = {"time_to_1e-4_s": time.perf_counter() - t0, "iterations": st[0]["iterations"],
+                        "true_rel_res": st[0]["true_rel_res"], "converged": st[0]["converged"],
+                        "restart": 100, "rhs": 1, "initial_guess": "zero"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, M)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * mlfma.h -- C ABI of the MI355X (gfx950) MLFMA-SMR library.
+ *
+ * The library applies and solves the static-mode PMCHWT system of
+ * Corsaro et al., "Multilevel Fast Multipole Algorithm for Electromagnetic
+ * Scattering by Large Metasurfaces using Static Mode Representation":
+ *
+ *   Z J = V   (Sec. II, eqs. PMCHWT_finite / Zpq_delta)
+ *
+ * for p particles, each carrying N = N_perp + N_par static modes (Sec. III)
+ * for its electric and for its magnetic equivalent current, i.e. 2N unknowns
+ * per particle.  The product Z x is computed by the multilevel fast multipole
+ * algorithm of Sec. IV: near blocks (self and adjacent particles) applied
+ * directly; far interactions by leaf radiation patterns (eq. kspace_Rap),
+ * aggregation with Lagrange interpolation and phase shifts, diagonal
+ * translation (eqs. addition_th / translation_fun), disaggregation
+ * (anterpolation) and receiving patterns (eqs. Tmn_fmm / Kmn_fmm).
+ *
+ * Conventions
+ *  - Time dependence exp(+j w t).  Lengths are in wavelengths of the
+ *    background medium, so k- = 2 pi; the background impedance is the unit
+ *    of impedance (zeta- = 1); mu = 1 everywhere.
+ *  - Unknown layout: [R][P][2][N] complex, interleaved (re, im), in the
+ *    context precision (complex float for MLFMA_C64, complex double for
+ *    MLFMA_C128): for right-hand side r and particle p, first the N
+ *    electric-current coefficients J_e (transverse modes first), then the N
+ *    magnetic ones J_m (Sec. II.A eq. galerkin ordering).
+ *  - Galerkin entries: T_mn = <psi_m, L psi_n> with L the field operator of
+ *    an electric current over zeta, K_mn = <psi_m, int psi_n x grad g>;
+ *    blocks [[z-T- + z+T+, K- + K+], [-(K- + K+), T-/z- + T+/z+]] (eq.
+ *    Zpq_delta), exterior only between distinct particles.  Right-hand side
+ *    V = -[<psi, E_inc>; <psi, H_inc>].
+ *
+ * Status codes: 0 success, < 0 error, > 0 warning.  Every call that takes a
+ * context records a message readable with mlfma_last_error().  No call
+ * throws across the ABI or terminates the process.  A context is not
+ * thread-safe: calls on one context must be serialised by the caller.
+ */
+#ifndef MLFMA_H
+#define MLFMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MLFMA_OK = 0,
+  MLFMA_EINVAL = -1,     /* invalid argument, size or layout              */
+  MLFMA_ENOMEM = -2,     /* host or device allocation failed              */
+  MLFMA_EHIP = -3,       /* a HIP runtime call failed (no GPU, fault)      */
+  MLFMA_ENOTREADY = -4,  /* a particle class in use has no static modes    */
+  MLFMA_ENONFINITE = -5, /* NaN/Inf in an input or a breakdown             */
+  MLFMA_NOT_CONVERGED = 1
+};
+
+enum { MLFMA_C64 = 0, MLFMA_C128 = 1 };
+
+/* Parts of the operator applied by mlfma_matvec_parts(). */
+enum { MLFMA_PART_NEAR = 1, MLFMA_PART_FAR = 2, MLFMA_PART_ALL = 3 };
+
+typedef struct mlfma_ctx mlfma_ctx;
+
+/* Particle array (Sec. II problem statement; Sec. IV grouping: every
+ * particle is a finest-level group).  Centres must lie on one plane z = z0
+ * at the sites origin + (i, j) * leaf_size of a square lattice, at most one
+ * particle per site (empty sites are allowed). */
+typedef struct {
+  int32_t n_particles;      /* P >= 1                                     */
+  const double* centers;    /* [P][3], background wavelengths             */
+  const int32_t* class_id;  /* [P], 0 <= class_id < n_classes             */
+  int32_t n_classes;        /* number of particle shapes/materials        */
+} mlfma_problem;
+
+/* Tree and accuracy parameters (Sec. IV; Sec. V: L = 10 at the finest
+ * level, K = 2 L^2 directions, 4 x 4 Lagrange interpolation). */
+typedef struct {
+  double leaf_size;      /* finest box edge = lattice pitch (0.5)           */
+  int32_t L_leaf;        /* truncation at the finest level (10)             */
+  int32_t L_rule;        /* coarser levels: 0 = excess-bandwidth rule
+                            L = kd + 1.8 d0^(2/3) (kd)^(1/3), d = sqrt2 a;
+                            1 = doubling per level                          */
+  double digits;         /* d0 of the excess-bandwidth rule (3)             */
+  int32_t interp_order;  /* points per direction of the Lagrange stencil
+                            (4 = the paper's 4 x 4; 6 allowed)              */
+  int32_t precision;     /* MLFMA_C64 or MLFMA_C128                         */
+  int32_t outer_levels;  /* subdivision levels of the outer triangle in the
+                            singular (touching-pair) quadrature (2)         */
+} mlfma_tree_params;
+
+typedef struct {
+  int32_t n_levels;          /* levels with translations                   */
+  int32_t L[16];             /* truncation per level (leaf first)          */
+  int32_t K[16];             /* directions per level = 2 L^2               */
+  int32_t nx[16], ny[16];    /* boxes per level                            */
+  int64_t n_unknowns;        /* 2 N P                                      */
+  int32_t n_modes;           /* N                                          */
+  int64_t device_bytes;      /* device memory held by the context          */
+} mlfma_info_t;
+
+typedef struct {
+  int32_t iterations;    /* GMRES iterations (matrix-vector products)      */
+  double true_rel_res;   /* ||V - Z x|| / ||V|| recomputed at exit         */
+  double time_s;         /* wall time of the solve                         */
+  int32_t converged;     /* 1 if true_rel_res <= rtol                      */
+} mlfma_solve_stats;
+
+/* Fill *tp with the defaults above. */
+void mlfma_default_params(mlfma_tree_params* tp);
+
+/* Build the quadtree, interaction lists and sphere grids for a particle
+ * array.  Host-only: makes no HIP call.  The library copies every input;
+ * the caller keeps ownership of pb's arrays.  On success *out owns a new
+ * context, released with mlfma_destroy().
+ * Errors: EINVAL (null pointers, P < 1, class ids out of range, centres not
+ * on one lattice plane, two particles on one site, bad parameters). */
+int mlfma_build_tree(const mlfma_problem* pb, const mlfma_tree_params* tp, mlfma_ctx** out);
+
+/* Static modes of one closed particle surface (Sec. III): the N_perp
+ * transverse modes of eq. AuxProb_Tt (loop functions, largest eigenvalues)
+ * followed by the N_par longitudinal modes of eq. AuxProb_Tl (star
+ * functions, smallest eigenvalues).  Host-only, FP64.
+ *  verts [nv][3], tris [nt][3] (counter-clockwise seen from outside),
+ *  edges [ne][4] = (v0, v1, t_plus, t_minus): t_plus has the directed edge
+ *  v0 -> v1, t_minus has v1 -> v0.  RWG f_e is +(l/2A)(r - p) on t_plus and
+ *  -(l/2A)(r - p) on t_minus, p the vertex opposite the edge.
+ * Output: M_out [(n_perp+n_par)][ne] RWG coefficients (caller-allocated),
+ * each mode with unit norm <psi, psi> = 1 and its largest-magnitude
+ * coefficient positive; gamma_out [(n_perp+n_par)] eigenvalues (may be
+ * NULL).  Errors: EINVAL (inconsistent mesh, too many modes), ENONFINITE. */
+int mlfma_static_modes(int32_t nv, const double* verts, int32_t nt, const int32_t* tris, int32_t ne,
+                       const int32_t* edges, int32_t n_perp, int32_t n_par, double* M_out,
+                       double* gamma_out);
+
+/* Attach the mesh, static modes and permittivity of particle class
+ * `class_id` (mesh in particle-local coordinates, centred on the particle
+ * centre).  M is [(n_perp+n_par)][ne] as produced by mlfma_static_modes.
+ * Computes in FP64 on the host: the leaf radiation/receiving patterns of
+ * eq. kspace_Rap, the self block Z_s of eq. Zpq_delta (singular quadrature
+ * on touching triangle pairs), and its inverse for the block-diagonal
+ * preconditioner.  Host-only; copies every input.  All classes must share
+ * the same n_perp + n_par.  Errors: EINVAL, ENONFINITE. */
+int mlfma_set_static_modes(mlfma_ctx* ctx, int32_t class_id, int32_t nv, const double* verts, int32_t nt,
+                           const int32_t* tris, int32_t ne, const int32_t* edges, int32_t n_perp,
+                           int32_t n_par, const double* M, double eps_re, double eps_im);
+
+/* Compute the neighbour blocks and translation tables and upload every
+ * table to the current HIP device.  Called implicitly by the first
+ * mlfma_matvec / mlfma_gmres_solve / mlfma_plane_wave_rhs.
+ * Errors: ENOTREADY (a class in use has no modes), EHIP, ENOMEM. */
+int mlfma_prepare(mlfma_ctx* ctx);
+
+/* Right-hand side of a plane wave E = pol exp(-j k khat . r) (Sec. II:
+ * e0 = -n x n x E_inc tested with the modes), H = khat x E / zeta-:
+ * b = -[<psi, E_inc>; <psi, H_inc>] for R incidences.
+ *  khat [R][3] unit vectors; pol [R][3] complex interleaved (re, im);
+ *  b_dev: device buffer [R][P][2][N] complex in the context precision.
+ * Asynchronous on `stream` (hipStream_t, NULL = default stream). */
+int mlfma_plane_wave_rhs(mlfma_ctx* ctx, int32_t R, const double* khat, const double* pol, void* b_dev,
+                         void* stream);
+
+/* y = Z x for R right-hand sides (the hot path, Sec. IV).  x_dev, y_dev:
+ * caller-owned device buffers [R][P][2][N] in the context precision; they
+ * must not overlap (EINVAL).  Asynchronous on `stream`; no host
+ * synchronisation.  Scratch pattern buffers are held by the context and
+ * grow to the largest R seen. */
+int mlfma_matvec(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream);
+
+/* As mlfma_matvec, restricted to the near part (self + adjacent blocks),
+ * the far part (multilevel expansion), or both (MLFMA_PART_*). */
+int mlfma_matvec_parts(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, int32_t parts,
+                       void* stream);
+
+/* Block-diagonal preconditioner y_p = Z_s^-1 x_p (Sec. V stage v), same
+ * layout and precision as mlfma_matvec. */
+int mlfma_precondition(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream);
+
+#define MLFMA_SOLVE_USE_X0 1
+
+/* Right-preconditioned restarted GMRES (Sec. V stage v; preconditioner
+ * blockdiag(Z_s)) for R right-hand sides solved in lock-step.  Arnoldi
+ * (classical Gram-Schmidt, applied twice), Givens rotations and the Krylov
+ * basis are FP64; the matrix-vector products run in the context precision.
+ *  b_dev, x_dev: device [R][P][2][N] in the context precision.  x_dev holds
+ *  the initial guess if flags & MLFMA_SOLVE_USE_X0 (else zero is used) and
+ *  the best iterate on return.  rtol: relative tolerance on the true
+ *  residual; max_iter: total matrix-vector products per RHS; restart: Krylov
+ *  dimension m.  stats [R] (may be NULL).  Synchronous: returns after the
+ *  solution is in x_dev.  Returns MLFMA_NOT_CONVERGED (1) if some RHS did
+ *  not reach rtol within max_iter. */
+int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R, double rtol,
+                      int32_t max_iter, int32_t restart, int32_t flags, mlfma_solve_stats* stats,
+                      void* stream);
+
+/* Per-kernel timing: while enabled, every kernel launch of mlfma_matvec is
+ * bracketed by HIP events recorded on the launch stream.  Enabling clears
+ * the accumulated table. */
+typedef struct {
+  char name[32];               /* kernel and level, e.g. "translate_l0"    */
+  double total_ms;             /* summed event time over the launches      */
+  int64_t launches;
+  double bytes_per_launch;     /* algorithmic HBM bytes of one launch      */
+  double flops_per_launch;     /* algorithmic real floating-point ops      */
+} mlfma_stage_time;
+
+int mlfma_profile(mlfma_ctx* ctx, int32_t enable);
+/* Synchronises the recorded events and returns up to `max` rows. */
+int mlfma_profile_read(mlfma_ctx* ctx, int32_t max, mlfma_stage_time* out, int32_t* count);
+
+int mlfma_info(const mlfma_ctx* ctx, mlfma_info_t* info);
+void mlfma_destroy(mlfma_ctx* ctx);
+const char* mlfma_last_error(const mlfma_ctx* ctx);
+
+/* Diagnostic accessors of host-side setup tables (FP64, interleaved
+ * complex), for tests.  Host-only.
+ *  near_block: Z^{mu nu} for a particle of class cp observing one of class
+ *    cq displaced by (dx, dy) lattice steps (dx = dy = 0 and cp == cq: the
+ *    self block); out [2N][2N] row-major.  Computed on demand.
+ *  leaf_pattern: receiving pattern psi_hat of class c at the finest-level
+ *    directions, out [K0][2 (theta, phi)][N].
+ *  level_grid: directions khat [K][3] and quadrature weights w [K] of level l.
+ *  translation: T_L of eq. translation_fun at level l for the source box
+ *    displaced by (dx, dy) boxes, out [K]. */
+int mlfma_debug_near_block(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_t dx, int32_t dy, double* out);
+int mlfma_debug_leaf_pattern(mlfma_ctx* ctx, int32_t c, double* out);
+int mlfma_debug_level_grid(mlfma_ctx* ctx, int32_t level, double* khat, double* w);
+int mlfma_debug_translation(mlfma_ctx* ctx, int32_t level, int32_t dx, int32_t dy, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLFMA_H */

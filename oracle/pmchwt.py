@@ -81,13 +81,41 @@ class DenseProblem:
     def block(self, mu, nu):
         cm, cn = self.class_id[mu], self.class_id[nu]
         off = self.centers[nu] - self.centers[mu]
-        key = (cm, cn, tuple(np.round(off, 9)))
+        key = self._key(mu, nu)
         if key not in self._cache:
             if mu == nu:
                 self._cache[key] = self_block(self.classes[cm], self.k0)
             else:
                 self._cache[key] = pair_block(self.classes[cm], self.classes[cn], off, self.k0)
         return self._cache[key]
+
+    def _key(self, mu, nu):
+        off = self.centers[nu] - self.centers[mu]
+        return (self.class_id[mu], self.class_id[nu], tuple(np.round(off, 9)))
+
+    def prefetch(self, pairs, workers: int = 0):
+        """Compute the blocks of the (mu, nu) pairs in parallel worker
+        processes (fork; one BLAS thread each).  Pure speed-up of ``block``."""
+        import multiprocessing as mp
+        todo = {}
+        for mu, nu in pairs:
+            k = self._key(mu, nu)
+            if k not in self._cache and k not in todo:
+                todo[k] = (mu, nu)
+        if not todo:
+            return
+        workers = workers or min(len(todo), len(__import__("os").sched_getaffinity(0)))
+        global _PREFETCH_PROB
+        _PREFETCH_PROB = self
+        items = list(todo.items())
+        if workers <= 1:
+            for k, (mu, nu) in items:
+                self.block(mu, nu)
+            return
+        ctx = mp.get_context("fork")
+        with ctx.Pool(workers, initializer=_limit_threads) as pool:
+            for k, blk in zip([k for k, _ in items], pool.map(_prefetch_one, [v for _, v in items], chunksize=1)):
+                self._cache[k] = blk
 
     def dense(self):
         P = self.n_particles
@@ -125,6 +153,22 @@ class DenseProblem:
             Hv = sum(pc.bs.Psi[c] @ (ph * hpol[c]) for c in range(3))
             out.append(-np.concatenate([Ev, Hv]))
         return np.array(out)
+
+
+_PREFETCH_PROB = None
+
+
+def _limit_threads():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _prefetch_one(pair):
+    mu, nu = pair
+    return _PREFETCH_PROB.block(mu, nu)
 
 
 def solve_dense(prob: DenseProblem, V):

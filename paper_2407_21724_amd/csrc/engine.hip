@@ -1,0 +1,1136 @@
+// Device engine for gfx950: device tables, the matrix-vector product
+// kernels of the MLFMA (Sec. IV) and the GMRES driver (Sec. V stage v).
+//
+// Data layout in HBM (box-major, sample-contiguous):
+//   x, y        [R][P][n]            n = 2N unknowns per particle
+//   S_l, G_l    [R][box_l][2][K_l]   outgoing / incoming transverse pattern
+//                                     (theta, phi components) per box;
+//                                     sample s = it * np + ip
+//   TL_l        [49][K_l]            translation function per box offset
+// Every kernel writes each output element once (no atomics), so repeated
+// products are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+
+namespace mlfma {
+
+namespace {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ void cfma(C2<T>& acc, C2<T> a, C2<T> b) {
+  acc.x += a.x * b.x - a.y * b.y;
+  acc.y += a.x * b.y + a.y * b.x;
+}
+template <typename T>
+__device__ __forceinline__ void cfma_conj_a(C2<T>& acc, C2<T> a, C2<T> b) {  // conj(a) * b
+  acc.x += a.x * b.x + a.y * b.y;
+  acc.y += a.x * b.y - a.y * b.x;
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cmul_conj_a(C2<T> a, C2<T> b) {
+  return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+
+constexpr int kBlock = 256;
+
+#define HIP_TRY(expr)                                                     \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      err = std::string(#expr " failed: ") + hipGetErrorString(e_);       \
+      return -3;                                                          \
+    }                                                                     \
+  } while (0)
+
+// ------------------------------------------------------------ near field --
+// y[r][p] = sum over the 9 neighbour slots of M_slot x[r][nbr].  One wave
+// per particle, lane = output row (rows lane and lane + 64).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_near(int n, int P, const C2<T>* __restrict__ x, C2<T>* __restrict__ y,
+                                                  const C2<T>* __restrict__ mats, const int* __restrict__ nbr,
+                                                  const int* __restrict__ slot, int nslot_per_p, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + wave);
+  const int r = blockIdx.y;
+  if (p >= P) return;
+  C2<T> a0{0, 0}, a1{0, 0};
+  const int j0 = lane, j1 = lane + 64;
+  for (int o = 0; o < nslot_per_p; ++o) {
+    const int q = nbr[p * nslot_per_p + o];
+    if (q < 0) continue;
+    const C2<T>* __restrict__ M = mats + (size_t)slot[p * nslot_per_p + o] * n * n;
+    const C2<T>* __restrict__ xq = x + ((size_t)r * P + q) * n;
+    for (int k = 0; k < n; ++k) {
+      const C2<T> xv = xq[k];
+      if (j0 < n) cfma(a0, M[(size_t)k * n + j0], xv);
+      if (j1 < n) cfma(a1, M[(size_t)k * n + j1], xv);
+    }
+  }
+  C2<T>* yp = y + ((size_t)r * P + p) * n;
+  if (accumulate) {
+    if (j0 < n) { C2<T> v = yp[j0]; yp[j0] = {v.x + a0.x, v.y + a0.y}; }
+    if (j1 < n) { C2<T> v = yp[j1]; yp[j1] = {v.x + a1.x, v.y + a1.y}; }
+  } else {
+    if (j0 < n) yp[j0] = a0;
+    if (j1 < n) yp[j1] = a1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill_zero(C2<T>* __restrict__ y, size_t count) {
+  size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (; i < count; i += stride) y[i] = {0, 0};
+}
+
+// ------------------------------------------------------- leaf projection --
+// U[r][box(p)][m] = sum_j Rm[class][j][m] x[r][p][j] for a tile of up to TP
+// particles of one class; m over the 2 K0 pattern samples.
+template <typename T, int TP>
+__global__ __launch_bounds__(kBlock) void k_project(int n, int P, int M2, int nbox, const C2<T>* __restrict__ x,
+                                                     C2<T>* __restrict__ U, const C2<T>* __restrict__ Rm_all,
+                                                     const int* __restrict__ rm_off, const int* __restrict__ order,
+                                                     const int* __restrict__ tile_start, const int* __restrict__ tile_count,
+                                                     const int* __restrict__ tile_class, const int* __restrict__ box_of) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* xs = reinterpret_cast<C2<T>*>(smem_raw);  // [TP][n]
+  const int tile = blockIdx.x, r = blockIdx.y;
+  const int cnt = tile_count[tile], st = tile_start[tile];
+  const C2<T>* __restrict__ Rm = Rm_all + rm_off[tile_class[tile]];
+  for (int i = threadIdx.x; i < TP * n; i += kBlock) {
+    const int t = i / n, j = i - t * n;
+    xs[i] = t < cnt ? x[((size_t)r * P + order[st + t]) * n + j] : C2<T>{0, 0};
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < M2; m += kBlock) {
+    C2<T> acc[TP];
+#pragma unroll
+    for (int t = 0; t < TP; ++t) acc[t] = {0, 0};
+    for (int j = 0; j < n; ++j) {
+      const C2<T> z = Rm[(size_t)j * M2 + m];
+#pragma unroll
+      for (int t = 0; t < TP; ++t) cfma(acc[t], z, xs[t * n + j]);
+    }
+#pragma unroll
+    for (int t = 0; t < TP; ++t)
+      if (t < cnt) U[((size_t)r * nbox + box_of[order[st + t]]) * M2 + m] = acc[t];
+  }
+}
+
+// ---------------------------------------------------------------- receive --
+// y[r][p][j] += sum_m Qm[class][m][j] G0[r][box(p)][m].  The tile's pattern
+// samples are staged through LDS in chunks of MC; wave w handles particles
+// w, w+4, ... of the tile; lane = output row (rows lane and lane + 64).
+template <typename T, int TP>
+__global__ __launch_bounds__(kBlock) void k_receive(int n, int P, int M2, int nbox, C2<T>* __restrict__ y,
+                                                     const C2<T>* __restrict__ G, const C2<T>* __restrict__ Qm_all,
+                                                     const int* __restrict__ qm_off, const int* __restrict__ order,
+                                                     const int* __restrict__ tile_start, const int* __restrict__ tile_count,
+                                                     const int* __restrict__ tile_class, const int* __restrict__ box_of) {
+  constexpr int MC = 128;
+  __shared__ C2<T> gs[TP * MC];
+  const int tile = blockIdx.x, r = blockIdx.y;
+  const int cnt = tile_count[tile], st = tile_start[tile];
+  const C2<T>* __restrict__ Qm = Qm_all + qm_off[tile_class[tile]];
+  constexpr int PW = TP / (kBlock / 64);  // particles per wave
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  C2<T> a0[PW], a1[PW];
+#pragma unroll
+  for (int u = 0; u < PW; ++u) a0[u] = a1[u] = {0, 0};
+  const int j0 = lane, j1 = lane + 64;
+  for (int m0 = 0; m0 < M2; m0 += MC) {
+    const int mc = min(MC, M2 - m0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < TP * MC; i += kBlock) {
+      const int t = i / MC, m = i - t * MC;
+      gs[i] = (t < cnt && m < mc) ? G[((size_t)r * nbox + box_of[order[st + t]]) * M2 + m0 + m] : C2<T>{0, 0};
+    }
+    __syncthreads();
+    for (int m = 0; m < mc; ++m) {
+      const C2<T> q0 = j0 < n ? Qm[(size_t)(m0 + m) * n + j0] : C2<T>{0, 0};
+      const C2<T> q1 = j1 < n ? Qm[(size_t)(m0 + m) * n + j1] : C2<T>{0, 0};
+#pragma unroll
+      for (int u = 0; u < PW; ++u) {
+        const C2<T> g = gs[(wave + u * (kBlock / 64)) * MC + m];
+        cfma(a0[u], q0, g);
+        cfma(a1[u], q1, g);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PW; ++u) {
+    const int t = wave + u * (kBlock / 64);
+    if (t >= cnt) continue;
+    C2<T>* yp = y + ((size_t)r * P + order[st + t]) * n;
+    if (j0 < n) { C2<T> v = yp[j0]; yp[j0] = {v.x + a0[u].x, v.y + a0[u].y}; }
+    if (j1 < n) { C2<T> v = yp[j1]; yp[j1] = {v.x + a1[u].x, v.y + a1[u].y}; }
+  }
+}
+
+// -------------------------------------------------------------- aggregate --
+// S_p[r][P][c][s] = sum over children q: phase_q(s) * (Phi Theta S_child)(s)
+// Parent rows [r0, r0 + ts) per block.  tmp: theta-interpolated child rows
+// [ts][np_c]; acc: parent strip [ts][np_p].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_aggregate(
+    int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts,
+    const C2<T>* __restrict__ Sc, C2<T>* __restrict__ Sp, const int* __restrict__ th_row,
+    const T* __restrict__ th_w, const int* __restrict__ th_flip, const int* __restrict__ ph_col,
+    const T* __restrict__ ph_w, const C2<T>* __restrict__ phase) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* tmp = reinterpret_cast<C2<T>*>(smem_raw);
+  C2<T>* acc = tmp + (size_t)ts * npc;
+  const int pb = blockIdx.x, r = blockIdx.y;
+  const int r0 = blockIdx.z * ts;
+  const int nrow = min(ts, ntp - r0);
+  const int PI = pb % nxp, PJ = pb / nxp;
+  const int Kc = ntc * npc, Kp = ntp * npp;
+  const int nbc = nxc * nyc, nbp = nxp * nyp;
+  const int half = npc / 2;
+  for (int comp = 0; comp < 2; ++comp) {
+    for (int i = threadIdx.x; i < nrow * npp; i += kBlock) acc[i] = {0, 0};
+    for (int q = 0; q < 4; ++q) {
+      const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
+      if (ci >= nxc || cj >= nyc) continue;
+      const C2<T>* __restrict__ src = Sc + (((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc;
+      __syncthreads();
+      for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
+        const int row = i / npc, col = i - row * npc;
+        const int it = r0 + row;
+        C2<T> v{0, 0};
+        for (int a = 0; a < order; ++a) {
+          const int e = it * order + a;
+          const int cc = th_flip[e] ? (col + half) % npc : col;
+          const C2<T> s = src[th_row[e] * npc + cc];
+          const T w = th_w[e];
+          v.x += w * s.x;
+          v.y += w * s.y;
+        }
+        tmp[i] = v;
+      }
+      __syncthreads();
+      const C2<T>* __restrict__ ph = phase + (size_t)q * Kp;
+      for (int i = threadIdx.x; i < nrow * npp; i += kBlock) {
+        const int row = i / npp, ip = i - row * npp;
+        C2<T> v{0, 0};
+        for (int b = 0; b < order; ++b) {
+          const T w = ph_w[ip * order + b];
+          const C2<T> s = tmp[row * npc + ph_col[ip * order + b]];
+          v.x += w * s.x;
+          v.y += w * s.y;
+        }
+        cfma(acc[i], ph[(r0 + row) * npp + ip], v);
+      }
+    }
+    __syncthreads();
+    C2<T>* __restrict__ dst = Sp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)r0 * npp;
+    for (int i = threadIdx.x; i < nrow * npp; i += kBlock) dst[i] = acc[i];
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------------------------- translate --
+// G[r][p][c][s] = sum over the interaction list of TL[offset][s] S[r][q][c][s]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_translate(int nx, int ny, int K, const C2<T>* __restrict__ S,
+                                                       C2<T>* __restrict__ G, const C2<T>* __restrict__ TL) {
+  const int p = blockIdx.x, r = blockIdx.y;
+  const int s = blockIdx.z * kBlock + threadIdx.x;
+  if (s >= K) return;
+  const int I = p % nx, J = p / nx;
+  const int nb = nx * ny;
+  C2<T> g0{0, 0}, g1{0, 0};
+  for (int dy = -3; dy <= 3; ++dy) {
+    const int J2 = J + dy;
+    if (J2 < 0 || J2 >= ny || abs((J2 >> 1) - (J >> 1)) > 1) continue;
+    for (int dx = -3; dx <= 3; ++dx) {
+      if (abs(dx) <= 1 && abs(dy) <= 1) continue;
+      const int I2 = I + dx;
+      if (I2 < 0 || I2 >= nx || abs((I2 >> 1) - (I >> 1)) > 1) continue;
+      const C2<T> t = TL[(size_t)((dy + 3) * 7 + dx + 3) * K + s];
+      const C2<T>* src = S + ((size_t)r * nb + J2 * nx + I2) * 2 * K;
+      cfma(g0, t, src[s]);
+      cfma(g1, t, src[K + s]);
+    }
+  }
+  C2<T>* dst = G + ((size_t)r * nb + p) * 2 * K;
+  dst[s] = g0;
+  dst[K + s] = g1;
+}
+
+// ----------------------------------------------------------- disaggregate --
+// G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), anterpolation as gathers
+// over the transposed stencils.  Child rows [c0, c0 + ts) per block.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_disaggregate(
+    int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int tmax, int pmax,
+    const C2<T>* __restrict__ Gp, C2<T>* __restrict__ Gc, const int* __restrict__ tth_row,
+    const T* __restrict__ tth_w, const int* __restrict__ tth_flip, const int* __restrict__ tth_lo,
+    const int* __restrict__ tth_hi, const int* __restrict__ tph_col, const T* __restrict__ tph_w,
+    const C2<T>* __restrict__ phase) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* tmp = reinterpret_cast<C2<T>*>(smem_raw);
+  const int cb = blockIdx.x, r = blockIdx.y;
+  const int c0 = blockIdx.z * ts;
+  const int nrow = min(ts, ntc - c0);
+  const int ci = cb % nxc, cj = cb / nxc;
+  const int pb = (cj >> 1) * nxp + (ci >> 1);
+  const int q = (cj & 1) * 2 + (ci & 1);
+  const int Kc = ntc * npc, Kp = ntp * npp;
+  const int nbc = nxc * nyc, nbp = nxp * nyp;
+  const int half = npc / 2;
+  int plo = ntp, phi = -1;
+  for (int rr = c0; rr < c0 + nrow; ++rr) {
+    plo = min(plo, tth_lo[rr]);
+    phi = max(phi, tth_hi[rr]);
+  }
+  const int np_rows = phi - plo + 1;
+  const C2<T>* __restrict__ ph = phase + (size_t)q * Kp;
+  for (int comp = 0; comp < 2; ++comp) {
+    const C2<T>* __restrict__ src = Gp + (((size_t)r * nbp + pb) * 2 + comp) * Kp;
+    __syncthreads();
+    for (int i = threadIdx.x; i < np_rows * npc; i += kBlock) {
+      const int row = i / npc, col = i - row * npc;
+      const int prow = plo + row;
+      C2<T> v{0, 0};
+      for (int e = 0; e < pmax; ++e) {
+        const T w = tph_w[col * pmax + e];
+        const int pc = tph_col[col * pmax + e];
+        const int sidx = prow * npp + pc;
+        const C2<T> t = cmul_conj_a(ph[sidx], src[sidx]);
+        v.x += w * t.x;
+        v.y += w * t.y;
+      }
+      tmp[i] = v;
+    }
+    __syncthreads();
+    C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc;
+    for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
+      const int row = i / npc, col = i - row * npc;
+      const int it = c0 + row;
+      C2<T> v{0, 0};
+      for (int e = 0; e < tmax; ++e) {
+        const int idx = it * tmax + e;
+        const int cc = tth_flip[idx] ? (col + half) % npc : col;
+        const C2<T> s = tmp[(tth_row[idx] - plo) * npc + cc];
+        const T w = tth_w[idx];
+        v.x += w * s.x;
+        v.y += w * s.y;
+      }
+      C2<T> o = dst[it * npc + col];
+      dst[it * npc + col] = {o.x + v.x, o.y + v.y};
+    }
+  }
+}
+
+// -------------------------------------------------------------------- rhs --
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rhs(int n, int P, int R, const C2<T>* __restrict__ pat,
+                                                 const int* __restrict__ class_of, const C2<T>* __restrict__ phase,
+                                                 C2<T>* __restrict__ b) {
+  const size_t total = (size_t)R * P * n;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
+    const int j = (int)(i % n);
+    const size_t rp = i / n;
+    const int p = (int)(rp % P), r = (int)(rp / P);
+    const C2<T> v = cmul(phase[rp], pat[((size_t)class_of[p] * R + r) * n + j]);
+    b[i] = {-v.x, -v.y};
+  }
+}
+
+// ------------------------------------------------ FP64 GMRES vector kernels --
+using Z = C2<double>;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_z(const C2<T>* __restrict__ a, Z* __restrict__ b, size_t cnt) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
+    b[i] = {(double)a[i].x, (double)a[i].y};
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_from_z(const Z* __restrict__ a, C2<T>* __restrict__ b, size_t cnt) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
+    b[i] = {(T)a[i].x, (T)a[i].y};
+}
+
+// partial[r][blk][i] = sum over this block's chunk of conj(V[i][r][k]) w[r][k]
+// for i < nv; also (i = nv) the squared norm of w when want_norm.
+__global__ __launch_bounds__(kBlock) void k_multidot(int nv, int ld_r, size_t Nt, size_t vstride, const Z* __restrict__ V,
+                                                      const Z* __restrict__ w, Z* __restrict__ partial, int nblk) {
+  __shared__ Z red[kBlock];
+  const int r = blockIdx.y, blk = blockIdx.x;
+  const size_t chunk = (Nt + nblk - 1) / nblk;
+  const size_t k0 = blk * chunk, k1 = min(Nt, k0 + chunk);
+  const Z* wr = w + (size_t)r * Nt;
+  for (int i = 0; i < nv; ++i) {
+    const Z* vi = V + i * vstride + (size_t)r * Nt;
+    Z acc{0, 0};
+    for (size_t k = k0 + threadIdx.x; k < k1; k += kBlock) cfma_conj_a(acc, vi[k], wr[k]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        red[threadIdx.x].x += red[threadIdx.x + s].x;
+        red[threadIdx.x].y += red[threadIdx.x + s].y;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[((size_t)r * nblk + blk) * ld_r + i] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(int nv, int ld_r, int nblk, const Z* __restrict__ partial,
+                                                             Z* __restrict__ out) {
+  const int r = blockIdx.x;
+  for (int i = threadIdx.x; i < nv; i += kBlock) {
+    Z acc{0, 0};
+    for (int b = 0; b < nblk; ++b) {
+      const Z v = partial[((size_t)r * nblk + b) * ld_r + i];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    out[(size_t)r * ld_r + i] = acc;
+  }
+}
+
+// w[r] -= sum_{i<nv} V[i][r] h[r][i]
+__global__ __launch_bounds__(kBlock) void k_subtract_proj(int nv, int ld_r, size_t Nt, size_t vstride, const Z* __restrict__ V,
+                                                           const Z* __restrict__ h, Z* __restrict__ w) {
+  const int r = blockIdx.y;
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
+    Z acc = w[(size_t)r * Nt + k];
+    for (int i = 0; i < nv; ++i) {
+      const Z v = V[i * vstride + (size_t)r * Nt + k];
+      const Z c = h[(size_t)r * ld_r + i];
+      acc.x -= v.x * c.x - v.y * c.y;
+      acc.y -= v.x * c.y + v.y * c.x;
+    }
+    w[(size_t)r * Nt + k] = acc;
+  }
+}
+
+// out[r] = a[r] * s[r] (+ out[r] if accumulate); s is a per-RHS complex scalar
+__global__ __launch_bounds__(kBlock) void k_scale(size_t Nt, const Z* __restrict__ a, const Z* __restrict__ s,
+                                                   int ld_s, Z* __restrict__ out, int accumulate) {
+  const int r = blockIdx.y;
+  const Z c = s[(size_t)r * ld_s];
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
+    const Z v = a[(size_t)r * Nt + k];
+    Z o = {v.x * c.x - v.y * c.y, v.x * c.y + v.y * c.x};
+    if (accumulate) {
+      const Z prev = out[(size_t)r * Nt + k];
+      o.x += prev.x;
+      o.y += prev.y;
+    }
+    out[(size_t)r * Nt + k] = o;
+  }
+}
+
+// out = a - b
+__global__ __launch_bounds__(kBlock) void k_sub(size_t cnt, const Z* __restrict__ a, const Z* __restrict__ b, Z* __restrict__ out) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
+    out[i] = {a[i].x - b[i].x, a[i].y - b[i].y};
+}
+
+// out[r] = sum_i V[i][r] y[r][i] (+ out if accumulate)
+__global__ __launch_bounds__(kBlock) void k_combine(int nv, int ld_r, size_t Nt, size_t vstride, const Z* __restrict__ V,
+                                                     const Z* __restrict__ yv, Z* __restrict__ out, int accumulate) {
+  const int r = blockIdx.y;
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
+    Z acc = accumulate ? out[(size_t)r * Nt + k] : Z{0, 0};
+    for (int i = 0; i < nv; ++i) {
+      const Z v = V[i * vstride + (size_t)r * Nt + k];
+      const Z c = yv[(size_t)r * ld_r + i];
+      acc.x += v.x * c.x - v.y * c.y;
+      acc.y += v.x * c.y + v.y * c.x;
+    }
+    out[(size_t)r * Nt + k] = acc;
+  }
+}
+
+// --------------------------------------------------------------- buffers --
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevMem() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t b) {
+    release();
+    if (b == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  template <typename U>
+  U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+int grid1d(size_t work) {
+  size_t b = (work + kBlock - 1) / kBlock;
+  return (int)std::max<size_t>(1, std::min<size_t>(b, 65535));
+}
+
+template <typename T>
+class EngineT final : public Engine {
+  using CT = C2<T>;
+  struct Lvl {
+    int nx, ny, nt, np, K;
+    DevMem TL;
+    DevMem S, G;  // pattern buffers, sized for R_alloc
+  };
+  struct Itp {
+    int order, tmax, pmax, ts_agg, ts_dis;
+    DevMem th_row, th_w, th_flip, ph_col, ph_w, tth_row, tth_w, tth_flip, tth_lo, tth_hi, tph_col, tph_w, phase;
+  };
+
+ public:
+  int upload(const Upload& u, std::string& err) override {
+    N_ = u.N;
+    n_ = u.n;
+    P_ = u.P;
+    nc_ = u.n_classes;
+    const Tree& tr = *u.tree;
+    ntl_ = tr.ntl;
+    lv_.clear();
+    lv_.resize(ntl_);
+    it_.clear();
+    it_.resize(std::max(ntl_, 1));
+    for (int l = 0; l < ntl_; ++l) {
+      const LevelGrid& g = tr.lv[l];
+      Lvl& L = lv_[l];
+      L.nx = g.nx;
+      L.ny = g.ny;
+      L.nt = g.nt;
+      L.np = g.np;
+      L.K = g.K;
+      if (int rc = put_c(L.TL, tr.TL[l], err)) return rc;
+    }
+    for (int l = 1; l < ntl_; ++l) {
+      const InterpTables& T0 = tr.it[l];
+      Itp& I = it_[l];
+      I.order = T0.order;
+      I.tmax = T0.tmax;
+      I.pmax = T0.pmax;
+      if (int rc = put_i(I.th_row, T0.th_row, err)) return rc;
+      if (int rc = put_r(I.th_w, T0.th_w, err)) return rc;
+      if (int rc = put_u8(I.th_flip, T0.th_flip, err)) return rc;
+      if (int rc = put_i(I.ph_col, T0.ph_col, err)) return rc;
+      if (int rc = put_r(I.ph_w, T0.ph_w, err)) return rc;
+      if (int rc = put_i(I.tth_row, T0.tth_row, err)) return rc;
+      if (int rc = put_r(I.tth_w, T0.tth_w, err)) return rc;
+      if (int rc = put_u8(I.tth_flip, T0.tth_flip, err)) return rc;
+      if (int rc = put_i(I.tth_lo, T0.tth_lo, err)) return rc;
+      if (int rc = put_i(I.tth_hi, T0.tth_hi, err)) return rc;
+      if (int rc = put_i(I.tph_col, T0.tph_col, err)) return rc;
+      if (int rc = put_r(I.tph_w, T0.tph_w, err)) return rc;
+      if (int rc = put_c(I.phase, T0.phase, err)) return rc;
+      // strip heights so that the LDS tiles stay within the budget
+      const Lvl &C = lv_[l - 1], &Pp = lv_[l];
+      const size_t row_agg = (size_t)(C.np + Pp.np) * sizeof(CT);
+      I.ts_agg = (int)std::max<size_t>(1, std::min<size_t>(Pp.nt, kLdsBudget / row_agg));
+      // disaggregation: largest child strip whose parent-row range fits
+      int ts = C.nt;
+      while (ts > 1) {
+        size_t worst = 0;
+        for (int c0 = 0; c0 < C.nt; c0 += ts) {
+          int lo = Pp.nt, hi = -1;
+          for (int rr = c0; rr < std::min(C.nt, c0 + ts); ++rr) {
+            lo = std::min(lo, T0.tth_lo[rr]);
+            hi = std::max(hi, T0.tth_hi[rr]);
+          }
+          worst = std::max<size_t>(worst, (size_t)(hi - lo + 1));
+        }
+        if (worst * C.np * sizeof(CT) <= kLdsBudget) break;
+        ts = (ts + 1) / 2;
+      }
+      {
+        size_t worst = 0;
+        for (int c0 = 0; c0 < C.nt; c0 += ts) {
+          int lo = Pp.nt, hi = -1;
+          for (int rr = c0; rr < std::min(C.nt, c0 + ts); ++rr) {
+            lo = std::min(lo, T0.tth_lo[rr]);
+            hi = std::max(hi, T0.tth_hi[rr]);
+          }
+          worst = std::max<size_t>(worst, (size_t)(hi - lo + 1));
+        }
+        if (worst * C.np * sizeof(CT) > kLdsBudget) {
+          err = "disaggregation tile exceeds the LDS budget at level " + std::to_string(l);
+          return -1;
+        }
+      }
+      I.ts_dis = ts;
+    }
+    // leaf data
+    nx0_ = u.nx0;
+    ny0_ = u.ny0;
+    if (int rc = put_i(box_of_, u.box_of, err)) return rc;
+    if (int rc = put_i(class_of_, u.class_of, err)) return rc;
+    if (int rc = put_i(order_, u.order, err)) return rc;
+    if (int rc = put_i(tile_start_, u.tile_start, err)) return rc;
+    if (int rc = put_i(tile_count_, u.tile_count, err)) return rc;
+    if (int rc = put_i(tile_class_, u.tile_class, err)) return rc;
+    ntiles_ = (int)u.tile_start.size();
+    tp_ = u.tile_count.empty() ? 0 : *std::max_element(u.tile_count.begin(), u.tile_count.end());
+    M2_ = ntl_ > 0 ? 2 * lv_[0].K : 0;
+    {
+      std::vector<cd> rm, qm;
+      std::vector<int> ro, qo;
+      for (int c = 0; c < nc_; ++c) {
+        ro.push_back((int)rm.size());
+        qo.push_back((int)qm.size());
+        rm.insert(rm.end(), u.Rm[c].begin(), u.Rm[c].end());
+        qm.insert(qm.end(), u.Qm[c].begin(), u.Qm[c].end());
+      }
+      if (int rc = put_c(Rm_, rm, err)) return rc;
+      if (int rc = put_c(Qm_, qm, err)) return rc;
+      if (int rc = put_i(rm_off_, ro, err)) return rc;
+      if (int rc = put_i(qm_off_, qo, err)) return rc;
+    }
+    {
+      std::vector<cd> all;
+      for (auto& m : u.near_mats) all.insert(all.end(), m.begin(), m.end());
+      if (int rc = put_c(near_mats_, all, err)) return rc;
+      if (int rc = put_i(near_nbr_, u.near_nbr, err)) return rc;
+      if (int rc = put_i(near_slot_, u.near_slot, err)) return rc;
+      std::vector<cd> zi;
+      for (auto& m : u.Zinv) zi.insert(zi.end(), m.begin(), m.end());
+      if (int rc = put_c(zinv_, zi, err)) return rc;
+      std::vector<int> self_nbr(P_), self_slot(P_);
+      for (int p = 0; p < P_; ++p) {
+        self_nbr[p] = p;
+        self_slot[p] = u.class_of[p];
+      }
+      if (int rc = put_i(self_nbr_, self_nbr, err)) return rc;
+      if (int rc = put_i(self_slot_, self_slot, err)) return rc;
+    }
+    centers_ = u.centers;
+    nslots_ = (int)u.near_mats.size();
+    nnear_ = 0;
+    for (int q : u.near_nbr) nnear_ += q >= 0;
+    pairs_.assign(ntl_, 0);
+    for (int l = 0; l < ntl_; ++l) {
+      const Lvl& L = lv_[l];
+      for (int J = 0; J < L.ny; ++J)
+        for (int I = 0; I < L.nx; ++I)
+          for (int dy = -3; dy <= 3; ++dy)
+            for (int dx = -3; dx <= 3; ++dx) {
+              if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+              const int I2 = I + dx, J2 = J + dy;
+              if (I2 < 0 || J2 < 0 || I2 >= L.nx || J2 >= L.ny) continue;
+              if (std::abs((I2 >> 1) - (I >> 1)) > 1 || std::abs((J2 >> 1) - (J >> 1)) > 1) continue;
+              pairs_[l]++;
+            }
+    }
+    R_alloc_ = 0;
+    return 0;
+  }
+
+  int ensure(int R, std::string& err) {
+    if (R <= R_alloc_) return 0;
+    for (int l = 0; l < ntl_; ++l) {
+      Lvl& L = lv_[l];
+      const size_t bytes = (size_t)R * L.nx * L.ny * 2 * L.K * sizeof(CT);
+      HIP_TRY(L.S.alloc(bytes));
+      HIP_TRY(L.G.alloc(bytes));
+      HIP_TRY(hipMemset(L.S.p, 0, bytes));  // empty leaf boxes stay zero
+      HIP_TRY(hipMemset(L.G.p, 0, bytes));
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    R_alloc_ = R;
+    return 0;
+  }
+
+  int matvec(const void* xv, void* yv, int R, int parts, void* stream, std::string& err) override {
+    if (int rc = ensure(R, err)) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const CT* x = reinterpret_cast<const CT*>(xv);
+    CT* y = reinterpret_cast<CT*>(yv);
+    const dim3 blk(kBlock);
+    const double cb = sizeof(CT);
+    if (parts & 1) {
+      dim3 grid((P_ + 3) / 4, R);
+      begin("near", cb * ((double)2 * R * P_ * n_ + (double)nslots_ * n_ * n_), 8.0 * R * nnear_ * (double)n_ * n_, st);
+      hipLaunchKernelGGL(k_near<T>, grid, blk, 0, st, n_, P_, x, y, near_mats_.template as<CT>(),
+                         near_nbr_.template as<int>(), near_slot_.template as<int>(), 9, 0);
+      end(st);
+    } else {
+      const size_t cnt = (size_t)R * P_ * n_;
+      hipLaunchKernelGGL(k_fill_zero<T>, dim3(grid1d(cnt)), blk, 0, st, y, cnt);
+    }
+    if ((parts & 2) && ntl_ > 0) {
+      const Lvl& L0 = lv_[0];
+      const int nb0 = L0.nx * L0.ny;
+      {
+        dim3 grid(ntiles_, R);
+        size_t sh = (size_t)kTP * n_ * sizeof(CT);
+        begin("project", cb * ((double)R * P_ * n_ + (double)R * P_ * M2_ + (double)nc_ * n_ * M2_),
+              8.0 * R * P_ * (double)n_ * M2_, st);
+        hipLaunchKernelGGL((k_project<T, kTP>), grid, blk, sh, st, n_, P_, M2_, nb0, x, L0.S.template as<CT>(),
+                           Rm_.template as<CT>(), rm_off_.template as<int>(), order_.template as<int>(),
+                           tile_start_.template as<int>(), tile_count_.template as<int>(),
+                           tile_class_.template as<int>(), box_of_.template as<int>());
+        end(st);
+      }
+      for (int l = 1; l < ntl_; ++l) {
+        const Lvl &C = lv_[l - 1], &Pp = lv_[l];
+        const Itp& I = it_[l];
+        dim3 grid(Pp.nx * Pp.ny, R, (Pp.nt + I.ts_agg - 1) / I.ts_agg);
+        size_t sh = (size_t)I.ts_agg * (C.np + Pp.np) * sizeof(CT);
+        begin("aggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
+              2.0 * R * (double)C.nx * C.ny * 2 * (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K), st);
+        hipLaunchKernelGGL(k_aggregate<T>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
+                           Pp.np, I.ts_agg, C.S.template as<CT>(), Pp.S.template as<CT>(), I.th_row.template as<int>(),
+                           I.th_w.template as<T>(), I.th_flip.template as<int>(), I.ph_col.template as<int>(),
+                           I.ph_w.template as<T>(), I.phase.template as<CT>());
+        end(st);
+      }
+      for (int l = ntl_ - 1; l >= 0; --l) {
+        const Lvl& L = lv_[l];
+        dim3 grid(L.nx * L.ny, R, (L.K + kBlock - 1) / kBlock);
+        begin("translate_l" + std::to_string(l), cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K),
+              16.0 * R * (double)pairs_[l] * L.K, st);
+        hipLaunchKernelGGL(k_translate<T>, grid, blk, 0, st, L.nx, L.ny, L.K, L.S.template as<CT>(),
+                           L.G.template as<CT>(), L.TL.template as<CT>());
+        end(st);
+        if (l + 1 < ntl_) {
+          const Lvl& Pp = lv_[l + 1];
+          const Itp& I = it_[l + 1];
+          dim3 g2(L.nx * L.ny, R, (L.nt + I.ts_dis - 1) / I.ts_dis);
+          // LDS: the largest parent-row range of any strip
+          size_t sh = kLdsBudget;
+          begin("disaggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
+                2.0 * R * (double)L.nx * L.ny * 2 * (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K), st);
+          hipLaunchKernelGGL(k_disaggregate<T>, g2, blk, sh, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.ny, Pp.nt, Pp.np,
+                             I.ts_dis, I.tmax, I.pmax, Pp.G.template as<CT>(), L.G.template as<CT>(),
+                             I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
+                             I.tth_lo.template as<int>(), I.tth_hi.template as<int>(), I.tph_col.template as<int>(),
+                             I.tph_w.template as<T>(), I.phase.template as<CT>());
+          end(st);
+        }
+      }
+      {
+        dim3 grid(ntiles_, R);
+        size_t sh = 0;
+        begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
+              8.0 * R * P_ * (double)n_ * M2_, st);
+        hipLaunchKernelGGL((k_receive<T, kTP>), grid, blk, sh, st, n_, P_, M2_, nb0, y, L0.G.template as<CT>(),
+                           Qm_.template as<CT>(), qm_off_.template as<int>(), order_.template as<int>(),
+                           tile_start_.template as<int>(), tile_count_.template as<int>(),
+                           tile_class_.template as<int>(), box_of_.template as<int>());
+        end(st);
+      }
+    }
+    HIP_TRY(hipGetLastError());
+    return 0;
+  }
+
+  int precondition(const void* xv, void* yv, int R, void* stream, std::string& err) override {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    dim3 grid((P_ + 3) / 4, R);
+    hipLaunchKernelGGL(k_near<T>, grid, dim3(kBlock), 0, st, n_, P_, reinterpret_cast<const CT*>(xv),
+                       reinterpret_cast<CT*>(yv), zinv_.template as<CT>(), self_nbr_.template as<int>(),
+                       self_slot_.template as<int>(), 1, 0);
+    HIP_TRY(hipGetLastError());
+    return 0;
+  }
+
+  int rhs(const std::vector<cd>& pat, const std::vector<V3>& khat, int R, void* b, void* stream,
+          std::string& err) override {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const double k = 2.0 * kPi;
+    std::vector<cd> phase((size_t)R * P_);
+    for (int r = 0; r < R; ++r)
+      for (int p = 0; p < P_; ++p) {
+        const double a = -k * dot(khat[r], centers_[p]);
+        phase[(size_t)r * P_ + p] = cd(std::cos(a), std::sin(a));
+      }
+    DevMem dpat, dph;
+    if (int rc = put_c(dpat, pat, err)) return rc;
+    if (int rc = put_c(dph, phase, err)) return rc;
+    const size_t cnt = (size_t)R * P_ * n_;
+    hipLaunchKernelGGL(k_rhs<T>, dim3(grid1d(cnt)), dim3(kBlock), 0, st, n_, P_, R, dpat.template as<CT>(),
+                       class_of_.template as<int>(), dph.template as<CT>(), reinterpret_cast<CT*>(b));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));  // dpat/dph are released on return
+    return 0;
+  }
+
+  int gmres(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0,
+            std::vector<GmresResult>& res, void* stream, std::string& err) override;
+
+  void profile(bool enable) override {
+    prof_on_ = enable;
+    for (auto& r : rec_) pool_.push_back(r.a), pool_.push_back(r.b);
+    rec_.clear();
+    table_.clear();
+    stage_index_.clear();
+  }
+
+  int profile_read(std::vector<StageTime>& out, std::string& err) override {
+    for (auto& r : rec_) {
+      HIP_TRY(hipEventSynchronize(r.b));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+      table_[r.stage].total_ms += ms;
+      table_[r.stage].launches += 1;
+      pool_.push_back(r.a);
+      pool_.push_back(r.b);
+    }
+    rec_.clear();
+    out = table_;
+    return 0;
+  }
+
+  long long device_bytes() const override {
+    long long s = 0;
+    for (auto& L : lv_) s += L.TL.bytes + L.S.bytes + L.G.bytes;
+    for (auto& I : it_)
+      s += I.th_row.bytes + I.th_w.bytes + I.th_flip.bytes + I.ph_col.bytes + I.ph_w.bytes + I.tth_row.bytes +
+           I.tth_w.bytes + I.tth_flip.bytes + I.tth_lo.bytes + I.tth_hi.bytes + I.tph_col.bytes + I.tph_w.bytes +
+           I.phase.bytes;
+    s += Rm_.bytes + Qm_.bytes + near_mats_.bytes + zinv_.bytes + box_of_.bytes + order_.bytes + near_nbr_.bytes +
+         near_slot_.bytes;
+    return s;
+  }
+
+ private:
+  static constexpr int kTP = sizeof(T) == 4 ? 16 : 8;
+  static constexpr size_t kLdsBudget = 48 * 1024;
+
+  template <typename U>
+  static int put_raw(DevMem& d, const U* h, size_t count, std::string& err) {
+    HIP_TRY(d.alloc(count * sizeof(U)));
+    if (count) HIP_TRY(hipMemcpy(d.p, h, count * sizeof(U), hipMemcpyHostToDevice));
+    return 0;
+  }
+  static int put_i(DevMem& d, const std::vector<int>& v, std::string& err) { return put_raw(d, v.data(), v.size(), err); }
+  static int put_u8(DevMem& d, const std::vector<uint8_t>& v, std::string& err) {
+    std::vector<int> w(v.begin(), v.end());
+    return put_raw(d, w.data(), w.size(), err);
+  }
+  static int put_r(DevMem& d, const std::vector<double>& v, std::string& err) {
+    std::vector<T> w(v.begin(), v.end());
+    return put_raw(d, w.data(), w.size(), err);
+  }
+  static int put_c(DevMem& d, const std::vector<cd>& v, std::string& err) {
+    std::vector<CT> w(v.size());
+    for (size_t i = 0; i < v.size(); ++i) w[i] = {(T)v[i].real(), (T)v[i].imag()};
+    return put_raw(d, w.data(), w.size(), err);
+  }
+
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  bool prof_on_ = false;
+  std::vector<hipEvent_t> pool_;
+  std::vector<Rec> rec_;
+  std::vector<StageTime> table_;
+  std::map<std::string, int> stage_index_;
+  int cur_stage_ = -1;
+  hipEvent_t cur_a_{};
+
+  hipEvent_t take_event() {
+    if (!pool_.empty()) {
+      hipEvent_t e = pool_.back();
+      pool_.pop_back();
+      return e;
+    }
+    hipEvent_t e{};
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(const std::string& name, double bytes, double flops, hipStream_t st) {
+    if (!prof_on_) return;
+    auto it = stage_index_.find(name);
+    if (it == stage_index_.end()) {
+      StageTime t;
+      t.name = name;
+      t.bytes = bytes;
+      t.flops = flops;
+      table_.push_back(t);
+      it = stage_index_.emplace(name, (int)table_.size() - 1).first;
+    }
+    cur_stage_ = it->second;
+    cur_a_ = take_event();
+    (void)hipEventRecord(cur_a_, st);
+  }
+  void end(hipStream_t st) {
+    if (!prof_on_) return;
+    hipEvent_t b = take_event();
+    (void)hipEventRecord(b, st);
+    rec_.push_back({cur_stage_, cur_a_, b});
+  }
+
+  int N_ = 0, n_ = 0, P_ = 0, nc_ = 0, ntl_ = 0, nx0_ = 0, ny0_ = 0, ntiles_ = 0, tp_ = 0, M2_ = 0, R_alloc_ = 0;
+  std::vector<Lvl> lv_;
+  std::vector<Itp> it_;
+  DevMem box_of_, class_of_, order_, tile_start_, tile_count_, tile_class_;
+  DevMem Rm_, Qm_, rm_off_, qm_off_;
+  DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_;
+  std::vector<V3> centers_;
+  int nslots_ = 0;
+  long long nnear_ = 0;
+  std::vector<long long> pairs_;
+  // GMRES workspace
+  DevMem gV_, gw_, gx_, gb_, gtmp_, gtmpT_, gtmpT2_, gpart_, gh_, gh2_;
+};
+
+// Right-preconditioned restarted GMRES with CGS2 Arnoldi in FP64.  Each RHS
+// has its own Krylov space; all RHS advance in lock-step and converged ones
+// are frozen (their columns are no longer updated).
+template <typename T>
+int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0,
+                      std::vector<GmresResult>& res, void* stream, std::string& err) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const size_t Nt = (size_t)P_ * n_;
+  const size_t tot = (size_t)R * Nt;
+  const size_t vstride = tot;  // V[i] is [R][Nt]
+  const int ld = m + 2;        // leading dimension for per-RHS coefficient arrays
+  const int nblk = (int)std::min<size_t>(256, (Nt + kBlock - 1) / kBlock);
+  HIP_TRY(gV_.alloc((size_t)(m + 1) * tot * sizeof(Z)));
+  HIP_TRY(gw_.alloc(tot * sizeof(Z)));
+  HIP_TRY(gx_.alloc(tot * sizeof(Z)));
+  HIP_TRY(gb_.alloc(tot * sizeof(Z)));
+  HIP_TRY(gtmp_.alloc(tot * sizeof(Z)));
+  HIP_TRY(gtmpT_.alloc(tot * sizeof(CT)));
+  HIP_TRY(gtmpT2_.alloc(tot * sizeof(CT)));
+  HIP_TRY(gpart_.alloc((size_t)R * nblk * ld * sizeof(Z)));
+  HIP_TRY(gh_.alloc((size_t)R * ld * sizeof(Z)));
+  HIP_TRY(gh2_.alloc((size_t)R * ld * sizeof(Z)));
+  Z* V = gV_.as<Z>();
+  Z* w = gw_.as<Z>();
+  Z* x = gx_.as<Z>();
+  Z* b = gb_.as<Z>();
+  Z* tmp = gtmp_.as<Z>();
+  CT* tT = gtmpT_.as<CT>();
+  CT* tT2 = gtmpT2_.as<CT>();
+  Z* part = gpart_.as<Z>();
+  Z* h = gh_.as<Z>();
+  Z* h2 = gh2_.as<Z>();
+  const dim3 blk(kBlock);
+  const dim3 gv(grid1d(Nt) > 1024 ? 1024 : grid1d(Nt), R);
+  auto launch_multidot = [&](int nv, const Z* vecs, const Z* ww, Z* out) {
+    hipLaunchKernelGGL(k_multidot, dim3(nblk, R), blk, 0, st, nv, ld, Nt, vstride, vecs, ww, part, nblk);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(R), blk, 0, st, nv, ld, nblk, part, out);
+  };
+  // operator A z = Z (P^-1 z), z FP64 -> result FP64 in `out`
+  auto apply_A = [&](const Z* z, Z* out, bool precond) -> int {
+    hipLaunchKernelGGL(k_from_z<T>, dim3(grid1d(tot)), blk, 0, st, z, tT, tot);
+    const CT* src = tT;
+    if (precond) {
+      if (int rc = precondition(tT, tT2, R, stream, err)) return rc;
+      src = tT2;
+    }
+    CT* dst = precond ? tT : tT2;
+    if (int rc = matvec(src, dst, R, 3, stream, err)) return rc;
+    hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, dst, out, tot);
+    return 0;
+  };
+  std::vector<Z> hh((size_t)R * ld), hnorm((size_t)R * ld);
+  auto norms = [&](const Z* vec, std::vector<double>& out) -> int {
+    launch_multidot(1, vec, vec, h2);
+    HIP_TRY(hipMemcpyAsync(hnorm.data(), h2, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out.resize(R);
+    for (int r = 0; r < R; ++r) out[r] = std::sqrt(std::max(0.0, hnorm[(size_t)r * ld].x));
+    return 0;
+  };
+  hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, reinterpret_cast<const CT*>(bv), b, tot);
+  if (use_x0)
+    hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, reinterpret_cast<const CT*>(xv), x, tot);
+  else
+    HIP_TRY(hipMemsetAsync(x, 0, tot * sizeof(Z), st));
+  std::vector<double> bnorm, rnorm;
+  if (int rc = norms(b, bnorm)) return rc;
+  res.assign(R, GmresResult{});
+  // residual r = b - Z x
+  auto residual = [&](Z* out) -> int {
+    if (int rc = apply_A(x, tmp, false)) return rc;
+    hipLaunchKernelGGL(k_sub, dim3(grid1d(tot)), blk, 0, st, tot, b, tmp, out);
+    return 0;
+  };
+  if (int rc = residual(w)) return rc;
+  if (int rc = norms(w, rnorm)) return rc;
+  if (use_x0) {
+    // fall back to a zero start where the guess is worse than zero
+    bool any = false;
+    for (int r = 0; r < R; ++r) any |= rnorm[r] > bnorm[r];
+    if (any) {
+      HIP_TRY(hipMemsetAsync(x, 0, tot * sizeof(Z), st));
+      if (int rc = residual(w)) return rc;
+      if (int rc = norms(w, rnorm)) return rc;
+    }
+  }
+  std::vector<char> done(R, 0);
+  std::vector<int> iters(R, 0);
+  for (int r = 0; r < R; ++r) {
+    if (bnorm[r] == 0.0 || rnorm[r] <= rtol * bnorm[r]) done[r] = 1;
+  }
+  int total_it = 0;
+  std::vector<std::vector<cd>> H(R), cs(R), sn(R), g(R);
+  while (true) {
+    bool all_done = true;
+    for (int r = 0; r < R; ++r) all_done &= (bool)done[r];
+    if (all_done || total_it >= max_iter) break;
+    // V0 = r / |r| (zero for finished RHS so they stay frozen)
+    for (int r = 0; r < R; ++r) {
+      hh[(size_t)r * ld] = done[r] || rnorm[r] == 0.0 ? Z{0, 0} : Z{1.0 / rnorm[r], 0};
+      H[r].assign((size_t)(m + 1) * m, 0.0);
+      cs[r].assign(m, 0.0);
+      sn[r].assign(m, 0.0);
+      g[r].assign(m + 1, 0.0);
+      g[r][0] = rnorm[r];
+    }
+    HIP_TRY(hipMemcpyAsync(h, hh.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_scale, gv, blk, 0, st, Nt, w, h, ld, V, 0);
+    int j = 0;
+    std::vector<char> active(R);
+    for (int r = 0; r < R; ++r) active[r] = !done[r];
+    for (; j < m && total_it < max_iter; ++j) {
+      Z* vj1 = V + (size_t)(j + 1) * vstride;
+      if (int rc = apply_A(V + (size_t)j * vstride, w, true)) return rc;
+      ++total_it;
+      // CGS2
+      launch_multidot(j + 1, V, w, h);
+      hipLaunchKernelGGL(k_subtract_proj, gv, blk, 0, st, j + 1, ld, Nt, vstride, V, h, w);
+      launch_multidot(j + 1, V, w, h2);
+      hipLaunchKernelGGL(k_subtract_proj, gv, blk, 0, st, j + 1, ld, Nt, vstride, V, h2, w);
+      HIP_TRY(hipMemcpyAsync(hh.data(), h, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
+      std::vector<Z> hh2((size_t)R * ld);
+      HIP_TRY(hipMemcpyAsync(hh2.data(), h2, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
+      std::vector<double> wn;
+      if (int rc = norms(w, wn)) return rc;
+      bool any_active = false;
+      for (int r = 0; r < R; ++r) {
+        if (!active[r]) {
+          hh[(size_t)r * ld] = Z{0, 0};
+          continue;
+        }
+        iters[r]++;
+        std::vector<cd>& Hr = H[r];
+        for (int i = 0; i <= j; ++i)
+          Hr[(size_t)i * m + j] = cd(hh[(size_t)r * ld + i].x + hh2[(size_t)r * ld + i].x,
+                                     hh[(size_t)r * ld + i].y + hh2[(size_t)r * ld + i].y);
+        Hr[(size_t)(j + 1) * m + j] = wn[r];
+        for (int i = 0; i < j; ++i) {  // previous rotations
+          cd a = Hr[(size_t)i * m + j], bb = Hr[(size_t)(i + 1) * m + j];
+          Hr[(size_t)i * m + j] = std::conj(cs[r][i]) * a + std::conj(sn[r][i]) * bb;
+          Hr[(size_t)(i + 1) * m + j] = -sn[r][i] * a + cs[r][i] * bb;
+        }
+        cd a = Hr[(size_t)j * m + j], bb = Hr[(size_t)(j + 1) * m + j];
+        double den = std::sqrt(std::norm(a) + std::norm(bb));
+        if (den == 0.0) {
+          cs[r][j] = 1.0;
+          sn[r][j] = 0.0;
+        } else {
+          cs[r][j] = a / den;
+          sn[r][j] = bb / den;
+        }
+        Hr[(size_t)j * m + j] = den;
+        Hr[(size_t)(j + 1) * m + j] = 0.0;
+        g[r][j + 1] = -sn[r][j] * g[r][j];
+        g[r][j] = std::conj(cs[r][j]) * g[r][j];
+        const double est = std::abs(g[r][j + 1]);
+        if (est <= rtol * bnorm[r] || wn[r] == 0.0) active[r] = 0;
+        any_active |= (bool)active[r];
+        hh[(size_t)r * ld] = wn[r] > 0 ? Z{1.0 / wn[r], 0} : Z{0, 0};
+      }
+      HIP_TRY(hipMemcpyAsync(h, hh.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_scale, gv, blk, 0, st, Nt, w, h, ld, vj1, 0);
+      if (!any_active) {
+        ++j;
+        break;
+      }
+    }
+    // x += P^-1 V y with H y = g (upper triangular, per RHS, size j)
+    std::vector<Z> yv((size_t)R * ld, Z{0, 0});
+    for (int r = 0; r < R; ++r) {
+      if (done[r]) continue;
+      const int jr = std::min(j, iters[r] - (total_it - j > 0 ? 0 : 0));
+      std::vector<cd> yy(j, 0.0);
+      for (int i = j - 1; i >= 0; --i) {
+        cd s = g[r][i];
+        for (int k2 = i + 1; k2 < j; ++k2) s -= H[r][(size_t)i * m + k2] * yy[k2];
+        cd d = H[r][(size_t)i * m + i];
+        yy[i] = d == 0.0 ? 0.0 : s / d;
+      }
+      (void)jr;
+      for (int i = 0; i < j; ++i) yv[(size_t)r * ld + i] = Z{yy[i].real(), yy[i].imag()};
+    }
+    HIP_TRY(hipMemcpyAsync(h, yv.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_combine, gv, blk, 0, st, j, ld, Nt, vstride, V, h, tmp, 0);
+    // x += P^-1 tmp (in FP64 through the context precision)
+    hipLaunchKernelGGL(k_from_z<T>, dim3(grid1d(tot)), blk, 0, st, tmp, tT, tot);
+    if (int rc = precondition(tT, tT2, R, stream, err)) return rc;
+    hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, tT2, tmp, tot);
+    {
+      std::vector<Z> one((size_t)R * ld, Z{0, 0});
+      for (int r = 0; r < R; ++r) one[(size_t)r * ld] = done[r] ? Z{0, 0} : Z{1, 0};
+      HIP_TRY(hipMemcpyAsync(h2, one.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_scale, gv, blk, 0, st, Nt, tmp, h2, ld, x, 1);
+    }
+    // true residual
+    if (int rc = residual(w)) return rc;
+    if (int rc = norms(w, rnorm)) return rc;
+    for (int r = 0; r < R; ++r)
+      if (!done[r] && rnorm[r] <= rtol * bnorm[r]) done[r] = 1;
+  }
+  hipLaunchKernelGGL(k_from_z<T>, dim3(grid1d(tot)), blk, 0, st, x, reinterpret_cast<CT*>(xv), tot);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < R; ++r) {
+    res[r].iterations = iters[r];
+    res[r].true_rel_res = bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0;
+    res[r].converged = res[r].true_rel_res <= rtol;
+    res[r].time_s = secs;
+  }
+  return 0;
+}
+
+}  // namespace
+
+Engine* make_engine(int precision) {
+  if (precision == 1) return new EngineT<double>();
+  return new EngineT<float>();
+}
+
+}  // namespace mlfma

@@ -1,0 +1,71 @@
+// Interface between the host-side context (api.cpp, plain C++) and the
+// device engine (engine.hip: HIP memory, kernels and the GMRES driver).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "host_math.hpp"
+#include "host_tree.hpp"
+
+namespace mlfma {
+
+// Everything the device path needs, assembled on the host in FP64.
+struct Upload {
+  int precision = 0;  // 0 = complex float, 1 = complex double
+  int N = 0, n = 0;   // modes per current, unknowns per particle (2N)
+  int P = 0;
+  int n_classes = 0;
+  int nx0 = 0, ny0 = 0;  // leaf grid
+  const Tree* tree = nullptr;
+  std::vector<int> box_of;     // [P] leaf box of each particle
+  std::vector<int> class_of;   // [P]
+  // particle tiles of one class: particles order[tile_start[t] ..
+  // tile_start[t] + tile_count[t]) share class tile_class[t]
+  std::vector<int> order, tile_start, tile_count, tile_class;
+  // per class, radiation matrix Rm [n][2 K0] (column m = comp*K0 + sample)
+  // and receiving matrix Qm [2 K0][n] (quadrature weight and -jk folded in)
+  std::vector<std::vector<cd>> Rm, Qm;
+  // near blocks: slot matrices stored transposed [k][j] (n x n), and per
+  // particle the 9 (neighbour particle, slot) pairs (-1 = none), offset
+  // index o = (dy+1)*3 + (dx+1)
+  std::vector<std::vector<cd>> near_mats;
+  std::vector<int> near_nbr, near_slot;
+  // per class inverse self block, transposed [k][j]
+  std::vector<std::vector<cd>> Zinv;
+  std::vector<V3> centers;
+};
+
+struct GmresResult {
+  int iterations = 0;
+  double true_rel_res = 0;
+  double time_s = 0;
+  int converged = 0;
+};
+
+struct StageTime {
+  std::string name;
+  double total_ms = 0;
+  long long launches = 0;
+  double bytes = 0, flops = 0;
+};
+
+class Engine {
+ public:
+  virtual void profile(bool enable) = 0;
+  virtual int profile_read(std::vector<StageTime>& out, std::string& err) = 0;
+  virtual ~Engine() = default;
+  virtual int upload(const Upload& u, std::string& err) = 0;
+  virtual int matvec(const void* x, void* y, int R, int parts, void* stream, std::string& err) = 0;
+  virtual int precondition(const void* x, void* y, int R, void* stream, std::string& err) = 0;
+  // b[r][p] = -exp(-j k khat_r . r_p) * pat[class_p][r] with pat [C][R][n]
+  virtual int rhs(const std::vector<cd>& pat, const std::vector<V3>& khat, int R, void* b, void* stream,
+                  std::string& err) = 0;
+  virtual int gmres(const void* b, void* x, int R, double rtol, int max_iter, int restart, bool use_x0,
+                    std::vector<GmresResult>& res, void* stream, std::string& err) = 0;
+  virtual long long device_bytes() const = 0;
+};
+
+Engine* make_engine(int precision);
+
+}  // namespace mlfma

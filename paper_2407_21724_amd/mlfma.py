@@ -1,0 +1,311 @@
+"""Python binding of libmlfma.so (argument marshalling only).
+
+Every entry point has the name of the C function it calls (without the
+``mlfma_`` prefix).  Device buffers are torch tensors (complex64 for the
+MLFMA_C64 context precision, complex128 for MLFMA_C128) of shape
+[R, P, 2N], contiguous, on the current HIP device; streams are torch
+streams.  Nothing here computes any part of the method: if the library is
+missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libmlfma.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENONFINITE, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
+C64, C128 = 0, 1
+PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
+SOLVE_USE_X0 = 1
+
+
+class MlfmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mlfma error {code}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_particles", C.c_int32), ("centers", C.POINTER(C.c_double)),
+                ("class_id", C.POINTER(C.c_int32)), ("n_classes", C.c_int32)]
+
+
+class TreeParams(C.Structure):
+    _fields_ = [("leaf_size", C.c_double), ("L_leaf", C.c_int32), ("L_rule", C.c_int32),
+                ("digits", C.c_double), ("interp_order", C.c_int32), ("precision", C.c_int32),
+                ("outer_levels", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("L", C.c_int32 * 16), ("K", C.c_int32 * 16),
+                ("nx", C.c_int32 * 16), ("ny", C.c_int32 * 16), ("n_unknowns", C.c_int64),
+                ("n_modes", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class StageTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("total_ms", C.c_double), ("launches", C.c_int64),
+                ("bytes_per_launch", C.c_double), ("flops_per_launch", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("true_rel_res", C.c_double), ("time_s", C.c_double),
+                ("converged", C.c_int32)]
+
+
+EXPORTS = [
+    "mlfma_default_params", "mlfma_build_tree", "mlfma_static_modes", "mlfma_set_static_modes",
+    "mlfma_prepare", "mlfma_plane_wave_rhs", "mlfma_matvec", "mlfma_matvec_parts",
+    "mlfma_precondition", "mlfma_gmres_solve", "mlfma_info", "mlfma_destroy", "mlfma_last_error",
+    "mlfma_debug_near_block", "mlfma_debug_leaf_pattern", "mlfma_debug_level_grid",
+    "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read",
+]
+
+
+def load_library(path: str = _LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2407_21724_amd.build`")
+    lib = C.CDLL(path)
+    dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p
+    ctxp = C.c_void_p
+    sig = {
+        "mlfma_default_params": (None, [C.POINTER(TreeParams)]),
+        "mlfma_build_tree": (C.c_int, [C.POINTER(Problem), C.POINTER(TreeParams), C.POINTER(C.c_void_p)]),
+        "mlfma_static_modes": (C.c_int, [C.c_int32, dp, C.c_int32, ip, C.c_int32, ip, C.c_int32, C.c_int32, dp, dp]),
+        "mlfma_set_static_modes": (C.c_int, [ctxp, C.c_int32, C.c_int32, dp, C.c_int32, ip, C.c_int32, ip,
+                                             C.c_int32, C.c_int32, dp, C.c_double, C.c_double]),
+        "mlfma_prepare": (C.c_int, [ctxp]),
+        "mlfma_plane_wave_rhs": (C.c_int, [ctxp, C.c_int32, dp, dp, vp, vp]),
+        "mlfma_matvec": (C.c_int, [ctxp, vp, vp, C.c_int32, vp]),
+        "mlfma_matvec_parts": (C.c_int, [ctxp, vp, vp, C.c_int32, C.c_int32, vp]),
+        "mlfma_precondition": (C.c_int, [ctxp, vp, vp, C.c_int32, vp]),
+        "mlfma_gmres_solve": (C.c_int, [ctxp, vp, vp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                        C.POINTER(SolveStats), vp]),
+        "mlfma_info": (C.c_int, [ctxp, C.POINTER(Info)]),
+        "mlfma_profile": (C.c_int, [ctxp, C.c_int32]),
+        "mlfma_profile_read": (C.c_int, [ctxp, C.c_int32, C.POINTER(StageTime), C.POINTER(C.c_int32)]),
+        "mlfma_destroy": (None, [ctxp]),
+        "mlfma_last_error": (C.c_char_p, [ctxp]),
+        "mlfma_debug_near_block": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp]),
+        "mlfma_debug_leaf_pattern": (C.c_int, [ctxp, C.c_int32, dp]),
+        "mlfma_debug_level_grid": (C.c_int, [ctxp, C.c_int32, dp, dp]),
+        "mlfma_debug_translation": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def default_params(**kw) -> TreeParams:
+    tp = TreeParams()
+    lib().mlfma_default_params(C.byref(tp))
+    for k, v in kw.items():
+        setattr(tp, k, v)
+    return tp
+
+
+def static_modes(verts, tris, edges, n_perp: int, n_par: int):
+    """mlfma_static_modes: returns (M [(n_perp+n_par)][ne], gamma)."""
+    v = np.ascontiguousarray(verts, np.float64)
+    t = np.ascontiguousarray(tris, np.int32)
+    e = np.ascontiguousarray(edges, np.int32)
+    N = n_perp + n_par
+    M = np.zeros((N, len(e)))
+    g = np.zeros(N)
+    rc = lib().mlfma_static_modes(len(v), _dptr(v), len(t), _iptr(t), len(e), _iptr(e), n_perp, n_par,
+                                  _dptr(M), _dptr(g))
+    if rc != OK:
+        raise MlfmaError(rc, "static_modes failed")
+    return M, g
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Context:
+    """An mlfma_ctx: tree, classes and device tables of one particle array."""
+
+    def __init__(self, centers, class_id, n_classes: int, params: TreeParams | None = None):
+        self._centers = np.ascontiguousarray(centers, np.float64)
+        self._cls = np.ascontiguousarray(class_id, np.int32)
+        pb = Problem(len(self._centers), _dptr(self._centers), _iptr(self._cls), n_classes)
+        self.params = params or default_params()
+        h = C.c_void_p()
+        rc = lib().mlfma_build_tree(C.byref(pb), C.byref(self.params), C.byref(h))
+        if rc != OK:
+            raise MlfmaError(rc, "build_tree rejected the problem")
+        self._h = h
+        self.n_particles = len(self._centers)
+        self.n_modes = None
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex128 if self.params.precision == C128 else torch.complex64
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise MlfmaError(rc, f"{what}: {lib().mlfma_last_error(self._h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mlfma_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_static_modes(self, class_id, verts, tris, edges, n_perp, n_par, M, eps):
+        v = np.ascontiguousarray(verts, np.float64)
+        t = np.ascontiguousarray(tris, np.int32)
+        e = np.ascontiguousarray(edges, np.int32)
+        Mm = np.ascontiguousarray(M, np.float64)
+        eps = complex(eps)
+        self._check(lib().mlfma_set_static_modes(self._h, class_id, len(v), _dptr(v), len(t), _iptr(t), len(e),
+                                                 _iptr(e), n_perp, n_par, _dptr(Mm), eps.real, eps.imag),
+                    "set_static_modes")
+        self.n_modes = n_perp + n_par
+
+    def prepare(self):
+        self._check(lib().mlfma_prepare(self._h), "prepare")
+
+    def _shape(self, R):
+        return (R, self.n_particles, 2 * self.n_modes)
+
+    def _dev(self, t, R):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == self.dtype and t.is_contiguous()
+                and tuple(t.shape) == self._shape(R)):
+            raise ValueError(f"expected a contiguous {self.dtype} device tensor of shape {self._shape(R)}")
+        return C.c_void_p(t.data_ptr())
+
+    def plane_wave_rhs(self, khat, pol, out=None, stream=None):
+        import torch
+        khat = np.ascontiguousarray(np.atleast_2d(khat), np.float64)
+        pol = np.atleast_2d(np.asarray(pol, complex))
+        R = len(khat)
+        polri = np.ascontiguousarray(np.stack([pol.real, pol.imag], -1).reshape(R, 6), np.float64)
+        if out is None:
+            out = torch.empty(self._shape(R), dtype=self.dtype, device="cuda")
+        self._check(lib().mlfma_plane_wave_rhs(self._h, R, _dptr(khat), _dptr(polri), self._dev(out, R),
+                                               _stream_ptr(stream)), "plane_wave_rhs")
+        return out
+
+    def matvec_parts(self, x, parts=PART_ALL, out=None, stream=None):
+        import torch
+        R = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(lib().mlfma_matvec_parts(self._h, self._dev(x, R), self._dev(out, R), R, parts,
+                                             _stream_ptr(stream)), "matvec")
+        return out
+
+    def matvec(self, x, out=None, stream=None):
+        import torch
+        R = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(lib().mlfma_matvec(self._h, self._dev(x, R), self._dev(out, R), R, _stream_ptr(stream)),
+                    "matvec")
+        return out
+
+    def precondition(self, x, out=None, stream=None):
+        import torch
+        R = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(lib().mlfma_precondition(self._h, self._dev(x, R), self._dev(out, R), R, _stream_ptr(stream)),
+                    "precondition")
+        return out
+
+    def gmres_solve(self, b, x=None, rtol=1e-4, max_iter=1000, restart=100, use_x0=False, stream=None):
+        import torch
+        R = b.shape[0]
+        if x is None:
+            x = torch.zeros_like(b)
+        stats = (SolveStats * R)()
+        rc = self._check(lib().mlfma_gmres_solve(self._h, self._dev(b, R), self._dev(x, R), R, rtol, max_iter,
+                                                 restart, SOLVE_USE_X0 if use_x0 else 0, stats,
+                                                 _stream_ptr(stream)), "gmres_solve")
+        out = [dict(iterations=s.iterations, true_rel_res=s.true_rel_res, time_s=s.time_s,
+                    converged=bool(s.converged)) for s in stats]
+        return x, out, rc
+
+    def profile(self, enable: bool):
+        self._check(lib().mlfma_profile(self._h, 1 if enable else 0), "profile")
+
+    def profile_read(self):
+        arr = (StageTime * 128)()
+        cnt = C.c_int32()
+        self._check(lib().mlfma_profile_read(self._h, 128, arr, C.byref(cnt)), "profile_read")
+        return [dict(name=a.name.decode(), total_ms=a.total_ms, launches=a.launches,
+                     bytes_per_launch=a.bytes_per_launch, flops_per_launch=a.flops_per_launch)
+                for a in arr[: cnt.value]]
+
+    def info(self) -> dict:
+        inf = Info()
+        self._check(lib().mlfma_info(self._h, C.byref(inf)), "info")
+        n = inf.n_levels
+        return dict(n_levels=n, L=list(inf.L[:n]), K=list(inf.K[:n]), nx=list(inf.nx[:n]), ny=list(inf.ny[:n]),
+                    n_unknowns=inf.n_unknowns, n_modes=inf.n_modes, device_bytes=inf.device_bytes)
+
+    # ---- diagnostics (host-side tables) ----
+    def debug_near_block(self, cp, cq, dx, dy):
+        if self.n_modes is None:
+            raise MlfmaError(ENOTREADY, "no class has static modes")
+        n = 2 * self.n_modes
+        out = np.zeros((n, n), complex)
+        self._check(lib().mlfma_debug_near_block(self._h, cp, cq, dx, dy, out.ctypes.data_as(C.POINTER(C.c_double))),
+                    "debug_near_block")
+        return out
+
+    def debug_leaf_pattern(self, c):
+        K = self.info()["K"][0]
+        out = np.zeros((K, 2, self.n_modes), complex)
+        self._check(lib().mlfma_debug_leaf_pattern(self._h, c, out.ctypes.data_as(C.POINTER(C.c_double))),
+                    "debug_leaf_pattern")
+        return out
+
+    def debug_level_grid(self, level):
+        K = self.info()["K"][level]
+        kh = np.zeros((K, 3))
+        w = np.zeros(K)
+        self._check(lib().mlfma_debug_level_grid(self._h, level, _dptr(kh), _dptr(w)), "debug_level_grid")
+        return kh, w
+
+    def debug_translation(self, level, dx, dy):
+        K = self.info()["K"][level]
+        out = np.zeros(K, complex)
+        self._check(lib().mlfma_debug_translation(self._h, level, dx, dy, out.ctypes.data_as(C.POINTER(C.c_double))),
+                    "debug_translation")
+        return out

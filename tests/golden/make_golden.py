@@ -1,0 +1,73 @@
+"""Write the oracle's expected values used by the GPU parity tests.
+
+Calls only ``oracle`` and the shared seeded input generators in
+``workloads``; nothing here touches the library.
+
+    python tests/golden/make_golden.py [c2_6x6 c2_12x12 c2_40x40_rows ...]
+
+Each file holds the oracle's static modes M of the cylinder class (the basis
+both sides are given), the workload description and the dense products
+y = Z x for the seeded x = workloads.random_complex((P, 2N), seed=1):
+  c2_6x6.npz        all 36 particles (two translation levels)
+  c2_12x12.npz      all 144 particles (three translation levels)
+  c2_40x40_rows.npz rows of 4 interior particles of the full 40 x 40
+                    array (the bench workload; all six levels contribute)
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as w  # noqa: E402
+from oracle.pmchwt import DenseProblem, ParticleClass  # noqa: E402
+
+SEED = 1
+
+
+def _cylinder_class(wl):
+    v, t, e = wl.meshes[0]
+    return ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r)
+
+
+def make(name: str):
+    t0 = time.time()
+    if name in ("c2_6x6", "c2_12x12"):
+        nx = 6 if name == "c2_6x6" else 12
+        wl = w.workload("c2", nx, nx)
+        rows = np.arange(wl.n_particles)
+    elif name == "c2_40x40_rows":
+        wl = w.workload("c2")
+        rows = np.array([19 * 40 + 19, 19 * 40 + 20, 20 * 40 + 19, 20 * 40 + 20])
+    else:
+        raise ValueError(name)
+    pc = _cylinder_class(wl)
+    prob = DenseProblem([pc], wl.centers, wl.class_id)
+    P, n = wl.n_particles, pc.n
+    x = w.random_complex((P, n), SEED)
+    prob.prefetch([(mu, nu) for mu in rows for nu in range(P)])
+    y = prob.matvec_rows(x, rows)
+    # near-field part (self + 8 neighbours) for the same rows
+    ix, iy = np.round(wl.centers[:, 0] / 0.5).astype(int), np.round(wl.centers[:, 1] / 0.5).astype(int)
+    ynear = []
+    for mu in rows:
+        acc = np.zeros(n, complex)
+        for nu in range(P):
+            if abs(ix[nu] - ix[mu]) <= 1 and abs(iy[nu] - iy[mu]) <= 1:
+                acc += prob.block(mu, nu) @ x[nu]
+        ynear.append(acc)
+    out = os.path.join(HERE, name + ".npz")
+    np.savez_compressed(out, M=pc.M, rows=rows, y=y, ynear=np.array(ynear), seed=SEED,
+                        eps_r=wl.eps_r, n_perp=wl.n_perp, n_par=wl.n_par, nx=int(ix.max() + 1),
+                        ny=int(iy.max() + 1))
+    print(f"{name}: {len(rows)} rows in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
+if __name__ == "__main__":
+    for nm in sys.argv[1:] or ["c2_6x6", "c2_12x12", "c2_40x40_rows"]:
+        make(nm)

@@ -1,0 +1,91 @@
+"""GPU GMRES (right block-diagonal preconditioner, FP64 Arnoldi) against the
+oracle's dense solve; solutions compared in the unknowns and in the
+scattered far and near fields (tolerance 1e-2 in the fields)."""
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_helpers import make_ctx, note, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle.fields import far_amplitude, near_field, scattering_cross_section, sphere_grid  # noqa: E402
+from oracle.pmchwt import DenseProblem, ParticleClass, solve_dense  # noqa: E402
+from paper_2407_21724_amd import mlfma  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c1_solution():
+    wl = w.workload("c1")
+    v, t, e = wl.meshes[0]
+    pc = ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r)
+    prob = DenseProblem([pc], wl.centers, wl.class_id)
+    P = wl.n_particles
+    prob.prefetch([(a, b) for a in range(P) for b in range(P)])
+    inc = wl.incidences[0]
+    V = prob.rhs(inc.khat, inc.pol)
+    J = solve_dense(prob, V)
+    return wl, pc, prob, V, J
+
+
+def _fields(prob, x):
+    rhat, _ = sphere_grid(32, 64)
+    far = far_amplitude(prob, x, rhat)
+    g = np.linspace(-0.25, 1.75, 9)
+    X, Y = np.meshgrid(g, g)
+    pts = np.stack([X.ravel(), Y.ravel(), np.full(X.size, 0.4)], -1)   # plane z = 0.4 above C1
+    near = near_field(prob, x, pts)
+    return far, near
+
+
+@pytest.mark.parametrize("prec,rtol", [(mlfma.C128, 1e-6), (mlfma.C64, 1e-4)])
+def test_c1_gmres_vs_dense_solve(c1_solution, prec, rtol):
+    wl, pc, prob, V, J = c1_solution
+    note(f"c1 gmres precision={prec} rtol={rtol}")
+    ctx = make_ctx(wl, pc.M, prec)
+    inc = wl.incidences[0]
+    b = ctx.plane_wave_rhs(inc.khat[None], inc.pol[None])
+    x, stats, rc = ctx.gmres_solve(b, rtol=rtol, max_iter=200, restart=50)
+    note(f"  {stats[0]}")
+    assert rc == mlfma.OK and stats[0]["converged"]
+    assert stats[0]["true_rel_res"] <= rtol
+    xs = x.cpu().numpy()[0]
+    # true residual with the oracle's dense operator
+    Z = prob.dense()
+    r_or = np.linalg.norm(Z @ xs.reshape(-1) - V.reshape(-1)) / np.linalg.norm(V)
+    note(f"  oracle residual {r_or:.3e}, unknowns err {rel_err(xs, J):.3e}")
+    assert r_or < 10 * rtol
+    far_g, near_g = _fields(prob, xs)
+    far_o, near_o = _fields(prob, J)
+    ef, en = rel_err(far_g, far_o), rel_err(near_g, near_o)
+    note(f"  far-field err {ef:.3e} near-field err {en:.3e}")
+    assert ef < 1e-2 and en < 1e-2
+    cs_g, cs_o = scattering_cross_section(prob, xs), scattering_cross_section(prob, J)
+    assert abs(cs_g / cs_o - 1) < 1e-2
+
+
+def test_gmres_initial_guess_and_zero_rhs(c1_solution):
+    wl, pc, prob, V, J = c1_solution
+    ctx = make_ctx(wl, pc.M, mlfma.C128)
+    inc = wl.incidences[0]
+    b = ctx.plane_wave_rhs(inc.khat[None], inc.pol[None])
+    # exact initial guess: converges with no iterations
+    x0 = to_dev(J[None], ctx)
+    x, stats, rc = ctx.gmres_solve(b, x=x0.clone(), rtol=1e-6, max_iter=50, restart=20, use_x0=True)
+    assert rc == mlfma.OK and stats[0]["iterations"] == 0
+    # a guess worse than zero falls back to the zero start
+    bad = to_dev(1e3 * w.random_complex(J[None].shape, 4), ctx)
+    x, stats, rc = ctx.gmres_solve(b, x=bad, rtol=1e-6, max_iter=200, restart=50, use_x0=True)
+    assert rc == mlfma.OK and stats[0]["true_rel_res"] <= 1e-6
+    # zero right-hand side -> zero solution
+    z = torch.zeros_like(b)
+    x, stats, rc = ctx.gmres_solve(z, rtol=1e-6, max_iter=10, restart=5)
+    assert rc == mlfma.OK and float(x.abs().max()) == 0.0
+    # not converged within max_iter -> warning status, best iterate returned
+    x, stats, rc = ctx.gmres_solve(b, rtol=1e-14, max_iter=3, restart=3)
+    assert rc == mlfma.NOT_CONVERGED and not stats[0]["converged"]
+    assert stats[0]["true_rel_res"] < 1.0

@@ -1,0 +1,180 @@
+"""GPU parity of the MLFMA matrix-vector product against the dense FP64
+oracle (rel. 2-norm tolerance 1e-3 for the product), called through the
+C ABI (ctypes binding)."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_helpers import make_ctx, note, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle.pmchwt import DenseProblem, ParticleClass  # noqa: E402
+from paper_2407_21724_amd import mlfma  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-3  # matvec parity bound
+
+
+@pytest.fixture(scope="module")
+def c1():
+    wl = w.workload("c1")
+    v, t, e = wl.meshes[0]
+    pc = ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r)
+    prob = DenseProblem([pc], wl.centers, wl.class_id)
+    P = wl.n_particles
+    prob.prefetch([(a, b) for a in range(P) for b in range(P)])
+    Z = prob.dense()
+    x = w.random_complex((1, P, pc.n), 1)
+    y = (Z @ x[0].reshape(-1)).reshape(P, pc.n)
+    near = np.zeros_like(y)
+    for a in range(P):
+        for b in range(P):
+            if np.max(np.abs(wl.centers[a] - wl.centers[b])) < 0.75:
+                near[a] += prob.block(a, b) @ x[0, b]
+    return dict(wl=wl, pc=pc, prob=prob, Z=Z, x=x, y=y, near=near)
+
+
+@pytest.mark.parametrize("prec", [mlfma.C128, mlfma.C64])
+def test_c1_matvec_vs_dense_oracle(c1, prec):
+    note(f"c1 matvec precision={prec}")
+    ctx = make_ctx(c1["wl"], c1["pc"].M, prec)
+    y = ctx.matvec(to_dev(c1["x"], ctx)).cpu().numpy()[0]
+    err = rel_err(y, c1["y"])
+    note(f"  rel err {err:.3e}")
+    assert err < TOL
+    if prec == mlfma.C128:
+        assert err < 1e-7     # one translation level of small spheres: far error ~1e-9
+
+
+def test_c1_near_and_far_parts(c1):
+    ctx = make_ctx(c1["wl"], c1["pc"].M, mlfma.C128)
+    xd = to_dev(c1["x"], ctx)
+    yn = ctx.matvec_parts(xd, mlfma.PART_NEAR).cpu().numpy()[0]
+    yf = ctx.matvec_parts(xd, mlfma.PART_FAR).cpu().numpy()[0]
+    assert rel_err(yn, c1["near"]) < 1e-12          # same quadrature, FP64 both sides
+    assert rel_err(yf, c1["y"] - c1["near"]) < 1e-6  # far expansion vs direct far blocks
+
+
+def test_c1_deterministic_and_batched(c1):
+    ctx = make_ctx(c1["wl"], c1["pc"].M, mlfma.C64)
+    x3 = np.concatenate([c1["x"], w.random_complex((2,) + c1["x"].shape[1:], 7)])
+    xd = to_dev(x3, ctx)
+    y3 = ctx.matvec(xd).cpu().numpy()
+    y3b = ctx.matvec(xd).cpu().numpy()
+    assert np.array_equal(y3, y3b)                   # no atomics: bitwise repeatable
+    for r in range(3):
+        yr = ctx.matvec(to_dev(x3[r:r + 1], ctx)).cpu().numpy()
+        assert np.array_equal(yr[0], y3[r])          # each RHS independent of the batch
+
+
+def test_c1_rhs_and_preconditioner(c1):
+    ctx = make_ctx(c1["wl"], c1["pc"].M, mlfma.C128)
+    khat = np.array([[0.0, 0.0, 1.0], [np.sin(0.3), 0.0, np.cos(0.3)]])
+    pol = np.array([[1, 0, 0], [np.cos(0.3), 0.0, -np.sin(0.3)]], complex)
+    b = ctx.plane_wave_rhs(khat, pol).cpu().numpy()
+    for r in range(2):
+        assert rel_err(b[r], c1["prob"].rhs(khat[r], pol[r])) < 1e-12
+    Zs = c1["prob"].block(0, 0)
+    z = ctx.precondition(to_dev(c1["x"], ctx)).cpu().numpy()[0]
+    ref = np.linalg.solve(Zs, c1["x"][0].T).T
+    assert rel_err(z, ref) < 1e-10
+
+
+def test_single_particle_is_self_block(c1):
+    wl = c1["wl"]
+    one = w.Workload("one", np.zeros((1, 3)), np.zeros(1, np.int32), wl.meshes, wl.eps_r, wl.n_perp, wl.n_par)
+    ctx = make_ctx(one, c1["pc"].M, mlfma.C128)
+    assert ctx.info()["n_levels"] == 0
+    x = c1["x"][:, :1]
+    y = ctx.matvec(to_dev(x, ctx)).cpu().numpy()[0, 0]
+    assert rel_err(y, c1["prob"].block(0, 0) @ x[0, 0]) < 1e-13
+
+
+def test_far_pair_block_error(c1):
+    """Two spheres two sites apart (the middle site empty): the product is
+    the self blocks plus one far block through one translation level; its
+    block error (the paper's eq. error_TK metric) is small."""
+    wl = c1["wl"]
+    cen = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    two = w.Workload("two", cen, np.zeros(2, np.int32), wl.meshes, wl.eps_r, wl.n_perp, wl.n_par)
+    ctx = make_ctx(two, c1["pc"].M, mlfma.C128)
+    assert ctx.info()["n_levels"] == 1
+    n = c1["pc"].n
+    # unit vectors on particle 1 -> the column block Z^{0,1} appears in y_0
+    X = np.zeros((n, 2, n), complex)
+    X[np.arange(n), 1, np.arange(n)] = 1.0
+    Y = ctx.matvec_parts(to_dev(X, ctx), mlfma.PART_FAR).cpu().numpy()
+    A = Y[:, 0, :].T                                  # computed block Z^{01}
+    prob = DenseProblem([c1["pc"]], cen, [0, 0])
+    Abar = prob.block(0, 1)
+    err = np.linalg.norm(A - Abar, 2) / np.linalg.norm(Abar, 2)
+    note(f"  far block error {err:.3e}")
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("name", ["c2_6x6", "c2_12x12"])
+@pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C128])
+def test_c2_subarrays_vs_golden(name, prec):
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path)
+    nx = int(g["nx"])
+    wl = w.workload("c2", nx, nx)
+    note(f"{name} precision={prec}")
+    ctx = make_ctx(wl, g["M"], prec)
+    x = w.random_complex((1, wl.n_particles, 2 * (wl.n_perp + wl.n_par)), int(g["seed"]))
+    y = ctx.matvec(to_dev(x, ctx)).cpu().numpy()[0]
+    err = rel_err(y[g["rows"]], g["y"])
+    yn = ctx.matvec_parts(to_dev(x, ctx), mlfma.PART_NEAR).cpu().numpy()[0]
+    err_near = rel_err(yn[g["rows"]], g["ynear"])
+    far_err = rel_err(y[g["rows"]] - yn[g["rows"]], g["y"] - g["ynear"])
+    note(f"  rel err {err:.3e} near {err_near:.3e} far-part {far_err:.3e}")
+    assert err < TOL
+    assert err_near < (1e-5 if prec == mlfma.C64 else 1e-12)
+
+
+def test_c2_full_size_sampled_rows():
+    """The bench workload (40 x 40 cylinders, FP32, one RHS, default
+    parameters): rows of 4 interior particles against the oracle."""
+    path = os.path.join(GOLDEN, "c2_40x40_rows.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path)
+    wl = w.workload("c2")
+    note("c2 40x40 FP32 sampled rows")
+    ctx = make_ctx(wl, g["M"], mlfma.C64)
+    x = w.random_complex((1, wl.n_particles, 60), int(g["seed"]))
+    y = ctx.matvec(to_dev(x, ctx)).cpu().numpy()[0]
+    err = rel_err(y[g["rows"]], g["y"])
+    note(f"  rel err {err:.3e} levels {ctx.info()['L']}")
+    assert err < TOL
+
+
+def test_ragged_grid_with_holes():
+    """Odd grid sizes and empty lattice sites (C1 spheres on a 5 x 3 grid with
+    two sites removed) against the dense oracle."""
+    wl0 = w.workload("c1")
+    cen = w.lattice(5, 3, 0.5)
+    keep = np.ones(len(cen), bool)
+    keep[[3, 7]] = False
+    cen = cen[keep]
+    wl = w.Workload("holes", cen, np.zeros(len(cen), np.int32), wl0.meshes, wl0.eps_r, 10, 10)
+    v, t, e = wl.meshes[0]
+    pc = ParticleClass(v, t, e, 10, 10, wl.eps_r)
+    prob = DenseProblem([pc], cen, wl.class_id)
+    P = len(cen)
+    prob.prefetch([(a, b) for a in range(P) for b in range(P)])
+    x = w.random_complex((1, P, pc.n), 3)
+    yref = (prob.dense() @ x[0].reshape(-1)).reshape(P, pc.n)
+    for prec in (mlfma.C64, mlfma.C128):
+        ctx = make_ctx(wl, pc.M, prec)
+        y = ctx.matvec(to_dev(x, ctx)).cpu().numpy()[0]
+        assert rel_err(y, yref) < TOL

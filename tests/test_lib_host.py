@@ -1,0 +1,182 @@
+"""CPU tests of the C-ABI library's host logic: exported symbols, argument
+validation, and the FP64 setup tables checked against the oracle and against
+closed forms (no device calls)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2407_21724_amd", "lib", "libmlfma.so")
+
+if not os.path.exists(LIB):
+    pytest.skip("libmlfma.so not built", allow_module_level=True)
+
+from paper_2407_21724_amd import mlfma  # noqa: E402
+
+
+def test_exports_every_declared_symbol():
+    import ctypes
+    hdr = open(os.path.join(ROOT, "include", "mlfma.h")).read()
+    declared = set(re.findall(r"\b(mlfma_[a-z_]+)\s*\(", hdr))
+    assert len(declared) >= 18
+    lib = ctypes.CDLL(LIB)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared <= set(mlfma.EXPORTS)
+
+
+def _problem(centers, cls, ncls=1, **kw):
+    c = np.ascontiguousarray(centers, np.float64)
+    k = np.ascontiguousarray(cls, np.int32)
+    return c, k, ncls, mlfma.default_params(**kw)
+
+
+@pytest.mark.parametrize("case", ["off_lattice", "duplicate", "non_planar", "bad_class", "nan", "bad_order",
+                                  "bad_precision"])
+def test_build_tree_rejects(case):
+    cen = w.lattice(3, 3, 0.5)
+    cls = np.zeros(9, np.int32)
+    kw = {}
+    if case == "off_lattice":
+        cen[4, 0] += 0.1
+    elif case == "duplicate":
+        cen[4] = cen[3]
+    elif case == "non_planar":
+        cen[4, 2] = 0.3
+    elif case == "bad_class":
+        cls[2] = 1
+    elif case == "nan":
+        cen[1, 1] = np.nan
+    elif case == "bad_order":
+        kw["interp_order"] = 5
+    elif case == "bad_precision":
+        kw["precision"] = 7
+    with pytest.raises(mlfma.MlfmaError):
+        mlfma.Context(cen, cls, 1, mlfma.default_params(**kw))
+
+
+def test_tree_levels_and_truncation():
+    ctx = mlfma.Context(w.lattice(40, 40, 0.5), np.zeros(1600, np.int32), 1)
+    inf = ctx.info()
+    # leaf 0.5: 40, 20, 10, 5, 3 boxes; L from the excess-bandwidth rule
+    assert inf["nx"] == [40, 20, 10, 5, 3]
+    assert inf["L"][0] == 10
+    for lev in range(1, 5):
+        a = 0.5 * 2 ** lev
+        kd = 2 * math.pi * math.sqrt(2) * a
+        assert inf["L"][lev] == math.ceil(kd + 1.8 * 3 ** (2 / 3) * kd ** (1 / 3))
+    assert inf["K"] == [2 * L * L for L in inf["L"]]
+    # a 2 x 2 array has no far interactions
+    assert mlfma.Context(w.lattice(2, 2, 0.5), np.zeros(4, np.int32), 1).info()["n_levels"] == 0
+
+
+@pytest.fixture(scope="module")
+def sphere_setup():
+    from oracle.basis import MeshBasis
+    from oracle.static_modes import static_modes
+    wl = w.workload("c1")
+    v, t, e = wl.meshes[0]
+    Mo, gp, gs = static_modes(MeshBasis(v, t, e), 20, 20)
+    return wl, Mo, np.r_[gp, gs]
+
+
+def test_static_modes_match_oracle_eigenvalues(sphere_setup):
+    wl, Mo, go = sphere_setup
+    v, t, e = wl.meshes[0]
+    Ml, gl = mlfma.static_modes(v, t, e, 20, 20)
+    assert np.abs(gl - go).max() < 1e-11 * np.abs(go).max()
+    # bases may differ inside degenerate multiplets; the spans agree
+    from oracle.basis import MeshBasis
+    from oracle.operators import SelfSingular, static_rwg_operators
+    mb = MeshBasis(v, t, e)
+    Gram, _, _ = static_rwg_operators(mb, SelfSingular(mb))
+    for sl in (slice(0, 20), slice(20, 40)):
+        A, B = Ml[sl], Mo[sl]
+        Q = A @ Gram @ B.T                     # orthogonal iff spans agree
+        assert np.abs(Q @ Q.T - np.eye(20)).max() < 1e-8
+
+
+def test_cylinder_static_modes_equal_oracle():
+    from oracle.basis import MeshBasis
+    from oracle.static_modes import static_modes
+    v, t = w.cylinder(0.3, 0.6)
+    e = w.edge_table(t)
+    Ml, gl = mlfma.static_modes(v, t, e, 15, 15)
+    Mo, gp, gs = static_modes(MeshBasis(v, t, e), 15, 15)
+    assert np.abs(gl - np.r_[gp, gs]).max() < 1e-11 * np.abs(gl).max()
+    assert np.abs(Ml - Mo).max() < 1e-8      # non-degenerate spectrum: same vectors, same sign rule
+
+
+def test_near_blocks_match_oracle(sphere_setup):
+    from oracle.pmchwt import ParticleClass, pair_block, self_block
+    wl, Mo, _ = sphere_setup
+    v, t, e = wl.meshes[0]
+    ctx = mlfma.Context(wl.centers, wl.class_id, 1)
+    ctx.set_static_modes(0, v, t, e, 20, 20, Mo, wl.eps_r)
+    pc = ParticleClass(v, t, e, 20, 20, wl.eps_r, M=Mo)
+    Zs = self_block(pc)
+    assert np.abs(ctx.debug_near_block(0, 0, 0, 0) - Zs).max() < 1e-12 * np.abs(Zs).max()
+    for d in [(1, 0), (1, 1), (0, -1), (-1, 0)]:
+        Zo = pair_block(pc, pc, [0.5 * d[0], 0.5 * d[1], 0.0])
+        Zl = ctx.debug_near_block(0, 0, *d)
+        assert np.abs(Zl - Zo).max() < 1e-12 * np.abs(Zo).max(), d
+    # leaf receiving pattern against the oracle's quadrature of eq. kspace_Rap
+    kh, wts = ctx.debug_level_grid(0)
+    assert abs(wts.sum() - 4 * np.pi) < 1e-12
+    pat = ctx.debug_leaf_pattern(0)                      # [K][2][N]
+    X, W = pc.bs.X, pc.bs.W
+    ph = np.exp(-1j * 2 * np.pi * (kh @ X.T)) * W[None, :]
+    cart = np.stack([ph @ pc.bs.Psi[c].T for c in range(3)], -1)  # [K][N][3]
+    th = np.arccos(np.clip(kh[:, 2], -1, 1))
+    phi = np.arctan2(kh[:, 1], kh[:, 0])
+    th_hat = np.stack([np.cos(th) * np.cos(phi), np.cos(th) * np.sin(phi), -np.sin(th)], -1)
+    assert np.abs(np.einsum("knc,kc->kn", cart, th_hat) - pat[:, 0]).max() < 1e-12 * np.abs(pat).max()
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_translation_tables_reproduce_greens_function(level):
+    """Addition theorem (eq. addition_th with eq. translation_fun): the
+    library's T_L tables and sphere quadrature reproduce g(r - r') for points
+    in two boxes two box-widths apart, to the accuracy the truncation rule
+    targets."""
+    ctx = mlfma.Context(w.lattice(12, 12, 0.5), np.zeros(144, np.int32), 1)
+    a = 0.5 * 2 ** level
+    kh, wts = ctx.debug_level_grid(level)
+    T = ctx.debug_translation(level, 2, 1)             # source box at (+2, +1) boxes
+    k = 2 * np.pi
+    rng = np.random.default_rng(11)
+    errs = []
+    for _ in range(20):
+        d_obs = rng.uniform(-0.5, 0.5, 3) * np.array([a, a, 0.6])   # inside the boxes (z: particle height)
+        d_src = rng.uniform(-0.5, 0.5, 3) * np.array([a, a, 0.6])
+        r = d_obs
+        rp = np.array([2 * a, a, 0.0]) + d_src
+        R = np.linalg.norm(r - rp)
+        g = np.exp(-1j * k * R) / (4 * np.pi * R)
+        approx = np.sum(wts * np.exp(-1j * k * (kh @ d_obs)) * T * np.exp(1j * k * (kh @ d_src)))
+        errs.append(abs(approx - g) / abs(g))
+    assert max(errs) < (2e-2 if level == 0 else 5e-3)
+    assert np.median(errs) < 2e-3
+
+
+def test_set_static_modes_rejects_bad_input(sphere_setup):
+    wl, Mo, _ = sphere_setup
+    v, t, e = wl.meshes[0]
+    ctx = mlfma.Context(wl.centers, wl.class_id, 1)
+    with pytest.raises(mlfma.MlfmaError):
+        ctx.set_static_modes(1, v, t, e, 20, 20, Mo, wl.eps_r)          # class out of range
+    bad = Mo.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(mlfma.MlfmaError):
+        ctx.set_static_modes(0, v, t, e, 20, 20, bad, wl.eps_r)
+    e2 = e.copy()
+    e2[0, [2, 3]] = e2[0, [3, 2]]                                       # orientation broken
+    with pytest.raises(mlfma.MlfmaError):
+        ctx.set_static_modes(0, v, t, e2, 20, 20, Mo, wl.eps_r)
+    with pytest.raises(mlfma.MlfmaError):
+        ctx.debug_near_block(0, 0, 1, 0)                                # not set yet
