@@ -77,13 +77,15 @@ typedef struct {
  * level, K = 2 L^2 directions, 4 x 4 Lagrange interpolation). */
 typedef struct {
   double leaf_size;      /* finest box edge = lattice pitch (0.5)           */
-  int32_t L_leaf;        /* truncation at the finest level (10)             */
+  int32_t L_leaf;        /* truncation at the finest level (default 11, the
+                            excess-bandwidth rule at a 0.5 leaf; the paper
+                            uses 10)                                        */
   int32_t L_rule;        /* coarser levels: 0 = excess-bandwidth rule
                             L = kd + 1.8 d0^(2/3) (kd)^(1/3), d = sqrt2 a;
                             1 = doubling per level                          */
   double digits;         /* d0 of the excess-bandwidth rule (3)             */
   int32_t interp_order;  /* points per direction of the Lagrange stencil
-                            (4 = the paper's 4 x 4; 6 allowed)              */
+                            (default 6; 4 = the paper's 4 x 4)              */
   int32_t precision;     /* MLFMA_C64 or MLFMA_C128                         */
   int32_t outer_levels;  /* subdivision levels of the outer triangle in the
                             singular (touching-pair) quadrature (2)         */
@@ -106,7 +108,8 @@ typedef struct {
   int32_t converged;     /* 1 if true_rel_res <= rtol                      */
 } mlfma_solve_stats;
 
-/* Fill *tp with the defaults above. */
+/* Fill *tp with the defaults: leaf 0.5, L_leaf 11, rule 0, digits 3,
+ * interp_order 6, MLFMA_C64, outer_levels 2. */
 void mlfma_default_params(mlfma_tree_params* tp);
 
 /* Build the quadtree, interaction lists and sphere grids for a particle

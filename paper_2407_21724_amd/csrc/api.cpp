@@ -253,10 +253,10 @@ extern "C" {
 void mlfma_default_params(mlfma_tree_params* tp) {
   if (!tp) return;
   tp->leaf_size = 0.5;
-  tp->L_leaf = 10;
+  tp->L_leaf = 11;
   tp->L_rule = 0;
   tp->digits = 3.0;
-  tp->interp_order = 4;
+  tp->interp_order = 6;
   tp->precision = MLFMA_C64;
   tp->outer_levels = 2;
 }

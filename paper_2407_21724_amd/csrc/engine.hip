@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -51,6 +52,7 @@ __device__ __forceinline__ C2<T> cmul_conj_a(C2<T> a, C2<T> b) {
 
 constexpr int kBlock = 256;
 
+
 #define HIP_TRY(expr)                                                     \
   do {                                                                    \
     hipError_t e_ = (expr);                                               \
@@ -61,36 +63,76 @@ constexpr int kBlock = 256;
   } while (0)
 
 // ------------------------------------------------------------ near field --
-// y[r][p] = sum over the 9 neighbour slots of M_slot x[r][nbr].  One wave
-// per particle, lane = output row (rows lane and lane + 64).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_near(int n, int P, const C2<T>* __restrict__ x, C2<T>* __restrict__ y,
-                                                  const C2<T>* __restrict__ mats, const int* __restrict__ nbr,
-                                                  const int* __restrict__ slot, int nslot_per_p, int accumulate) {
+// y[r][p] = sum over the neighbour slots o of M_{slot(p,o)} x[r][nbr(p,o)].
+// A block handles TPN consecutive particles (4 waves x PW particles; lane =
+// output row, rows lane and lane + 64).  For each slot o the x vectors of
+// the tile's o-neighbours are staged in LDS; when every particle of the tile
+// that has an o-neighbour uses the same matrix (tile_slot >= 0) the matrix
+// is staged once (STAGE_M) and shared, otherwise (tile_slot == -2) each
+// particle reads its own matrix.  tile_slot == -1: no o-neighbour at all.
+template <typename T, int TPN, bool STAGE_M>
+__global__ __launch_bounds__(kBlock) void k_near(int n, int P, int nsp, const C2<T>* __restrict__ x,
+                                                  C2<T>* __restrict__ y, const C2<T>* __restrict__ mats,
+                                                  const int* __restrict__ nbr, const int* __restrict__ slot,
+                                                  const int* __restrict__ tile_slot) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* xs = reinterpret_cast<C2<T>*>(smem_raw);  // [TPN][n]
+  C2<T>* ms = xs + TPN * n;                         // [n][n]
+  constexpr int PW = TPN / (kBlock / 64);
+  const int tile = blockIdx.x, r = blockIdx.y;
+  const int p0 = tile * TPN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int p = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + wave);
-  const int r = blockIdx.y;
-  if (p >= P) return;
-  C2<T> a0{0, 0}, a1{0, 0};
   const int j0 = lane, j1 = lane + 64;
-  for (int o = 0; o < nslot_per_p; ++o) {
-    const int q = nbr[p * nslot_per_p + o];
-    if (q < 0) continue;
-    const C2<T>* __restrict__ M = mats + (size_t)slot[p * nslot_per_p + o] * n * n;
-    const C2<T>* __restrict__ xq = x + ((size_t)r * P + q) * n;
-    for (int k = 0; k < n; ++k) {
-      const C2<T> xv = xq[k];
-      if (j0 < n) cfma(a0, M[(size_t)k * n + j0], xv);
-      if (j1 < n) cfma(a1, M[(size_t)k * n + j1], xv);
+  C2<T> a0[PW], a1[PW];
+#pragma unroll
+  for (int u = 0; u < PW; ++u) a0[u] = a1[u] = {0, 0};
+  for (int o = 0; o < nsp; ++o) {
+    const int ts = tile_slot[tile * nsp + o];
+    if (ts == -1) continue;
+    __syncthreads();
+    for (int i = threadIdx.x; i < TPN * n; i += kBlock) {
+      const int t = i / n, k = i - t * n;
+      const int p = p0 + t;
+      const int q = p < P ? nbr[p * nsp + o] : -1;
+      xs[i] = q >= 0 ? x[((size_t)r * P + q) * n + k] : C2<T>{0, 0};
+    }
+    if (STAGE_M && ts >= 0)
+      for (int i = threadIdx.x; i < n * n; i += kBlock) ms[i] = mats[(size_t)ts * n * n + i];
+    __syncthreads();
+    if (ts >= 0) {
+      const C2<T>* __restrict__ M = STAGE_M ? ms : mats + (size_t)ts * n * n;
+#pragma unroll 4
+      for (int k = 0; k < n; ++k) {
+        const C2<T> m0 = j0 < n ? M[k * n + j0] : C2<T>{0, 0};
+        const C2<T> m1 = j1 < n ? M[k * n + j1] : C2<T>{0, 0};
+#pragma unroll
+        for (int u = 0; u < PW; ++u) {
+          const C2<T> xv = xs[(wave * PW + u) * n + k];
+          cfma(a0[u], m0, xv);
+          cfma(a1[u], m1, xv);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < PW; ++u) {
+        const int p = p0 + wave * PW + u;
+        if (p >= P || nbr[p * nsp + o] < 0) continue;
+        const C2<T>* __restrict__ M = mats + (size_t)slot[p * nsp + o] * n * n;
+        for (int k = 0; k < n; ++k) {
+          const C2<T> xv = xs[(wave * PW + u) * n + k];
+          if (j0 < n) cfma(a0[u], M[k * n + j0], xv);
+          if (j1 < n) cfma(a1[u], M[k * n + j1], xv);
+        }
+      }
     }
   }
-  C2<T>* yp = y + ((size_t)r * P + p) * n;
-  if (accumulate) {
-    if (j0 < n) { C2<T> v = yp[j0]; yp[j0] = {v.x + a0.x, v.y + a0.y}; }
-    if (j1 < n) { C2<T> v = yp[j1]; yp[j1] = {v.x + a1.x, v.y + a1.y}; }
-  } else {
-    if (j0 < n) yp[j0] = a0;
-    if (j1 < n) yp[j1] = a1;
+#pragma unroll
+  for (int u = 0; u < PW; ++u) {
+    const int p = p0 + wave * PW + u;
+    if (p >= P) continue;
+    C2<T>* yp = y + ((size_t)r * P + p) * n;
+    if (j0 < n) yp[j0] = a0[u];
+    if (j1 < n) yp[j1] = a1[u];
   }
 }
 
@@ -103,27 +145,33 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(C2<T>* __restrict__ y, siz
 
 // ------------------------------------------------------- leaf projection --
 // U[r][box(p)][m] = sum_j Rm[class][j][m] x[r][p][j] for a tile of up to TP
-// particles of one class; m over the 2 K0 pattern samples.
+// particles of one class; one thread per pattern sample m (blocks of 128
+// samples along grid y).
+constexpr int kProjBlock = 128;
 template <typename T, int TP>
-__global__ __launch_bounds__(kBlock) void k_project(int n, int P, int M2, int nbox, const C2<T>* __restrict__ x,
-                                                     C2<T>* __restrict__ U, const C2<T>* __restrict__ Rm_all,
-                                                     const int* __restrict__ rm_off, const int* __restrict__ order,
-                                                     const int* __restrict__ tile_start, const int* __restrict__ tile_count,
-                                                     const int* __restrict__ tile_class, const int* __restrict__ box_of) {
+__global__ __launch_bounds__(kProjBlock) void k_project(int n, int P, int M2, int nbox, const C2<T>* __restrict__ x,
+                                                         C2<T>* __restrict__ U, const C2<T>* __restrict__ Rm_all,
+                                                         const int* __restrict__ rm_off, const int* __restrict__ order,
+                                                         const int* __restrict__ tile_start,
+                                                         const int* __restrict__ tile_count,
+                                                         const int* __restrict__ tile_class,
+                                                         const int* __restrict__ box_of) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* xs = reinterpret_cast<C2<T>*>(smem_raw);  // [TP][n]
-  const int tile = blockIdx.x, r = blockIdx.y;
+  const int tile = blockIdx.x, r = blockIdx.z;
   const int cnt = tile_count[tile], st = tile_start[tile];
   const C2<T>* __restrict__ Rm = Rm_all + rm_off[tile_class[tile]];
-  for (int i = threadIdx.x; i < TP * n; i += kBlock) {
+  for (int i = threadIdx.x; i < TP * n; i += kProjBlock) {
     const int t = i / n, j = i - t * n;
     xs[i] = t < cnt ? x[((size_t)r * P + order[st + t]) * n + j] : C2<T>{0, 0};
   }
   __syncthreads();
-  for (int m = threadIdx.x; m < M2; m += kBlock) {
+  const int m = blockIdx.y * kProjBlock + threadIdx.x;
+  if (m < M2) {
     C2<T> acc[TP];
 #pragma unroll
     for (int t = 0; t < TP; ++t) acc[t] = {0, 0};
+#pragma unroll 4
     for (int j = 0; j < n; ++j) {
       const C2<T> z = Rm[(size_t)j * M2 + m];
 #pragma unroll
@@ -156,6 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_receive(int n, int P, int M2, int nb
 #pragma unroll
   for (int u = 0; u < PW; ++u) a0[u] = a1[u] = {0, 0};
   const int j0 = lane, j1 = lane + 64;
+  const bool two = n > 64;
   for (int m0 = 0; m0 < M2; m0 += MC) {
     const int mc = min(MC, M2 - m0);
     __syncthreads();
@@ -164,14 +213,23 @@ __global__ __launch_bounds__(kBlock) void k_receive(int n, int P, int M2, int nb
       gs[i] = (t < cnt && m < mc) ? G[((size_t)r * nbox + box_of[order[st + t]]) * M2 + m0 + m] : C2<T>{0, 0};
     }
     __syncthreads();
-    for (int m = 0; m < mc; ++m) {
-      const C2<T> q0 = j0 < n ? Qm[(size_t)(m0 + m) * n + j0] : C2<T>{0, 0};
-      const C2<T> q1 = j1 < n ? Qm[(size_t)(m0 + m) * n + j1] : C2<T>{0, 0};
+    if (two) {
+      for (int m = 0; m < mc; ++m) {
+        const C2<T> q0 = j0 < n ? Qm[(size_t)(m0 + m) * n + j0] : C2<T>{0, 0};
+        const C2<T> q1 = j1 < n ? Qm[(size_t)(m0 + m) * n + j1] : C2<T>{0, 0};
 #pragma unroll
-      for (int u = 0; u < PW; ++u) {
-        const C2<T> g = gs[(wave + u * (kBlock / 64)) * MC + m];
-        cfma(a0[u], q0, g);
-        cfma(a1[u], q1, g);
+        for (int u = 0; u < PW; ++u) {
+          const C2<T> g = gs[(wave + u * (kBlock / 64)) * MC + m];
+          cfma(a0[u], q0, g);
+          cfma(a1[u], q1, g);
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int m = 0; m < mc; ++m) {
+        const C2<T> q0 = j0 < n ? Qm[(size_t)(m0 + m) * n + j0] : C2<T>{0, 0};
+#pragma unroll
+        for (int u = 0; u < PW; ++u) cfma(a0[u], q0, gs[(wave + u * (kBlock / 64)) * MC + m]);
       }
     }
   }
@@ -186,9 +244,12 @@ __global__ __launch_bounds__(kBlock) void k_receive(int n, int P, int M2, int nb
 }
 
 // -------------------------------------------------------------- aggregate --
-// S_p[r][P][c][s] = sum over children q: phase_q(s) * (Phi Theta S_child)(s)
-// Parent rows [r0, r0 + ts) per block.  tmp: theta-interpolated child rows
-// [ts][np_c]; acc: parent strip [ts][np_p].
+// S_p[r][P][c][s] = sum over children q: phase_q(s) * (Phi Theta S_child)(s).
+// Block = (parent box, component) x strip of ts parent rows x RHS; each
+// thread owns up to VPT outputs of the strip (ts * np_p <= 256 * VPT) and
+// accumulates the four children in registers.  tmp: theta-interpolated
+// child rows [ts][np_c] in LDS.
+constexpr int kAggVPT = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_aggregate(
     int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts,
@@ -197,88 +258,66 @@ __global__ __launch_bounds__(kBlock) void k_aggregate(
     const T* __restrict__ ph_w, const C2<T>* __restrict__ phase) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* tmp = reinterpret_cast<C2<T>*>(smem_raw);
-  C2<T>* acc = tmp + (size_t)ts * npc;
-  const int pb = blockIdx.x, r = blockIdx.y;
-  const int r0 = blockIdx.z * ts;
+  const int pb = blockIdx.x >> 1, comp = blockIdx.x & 1;
+  const int r0 = blockIdx.y * ts, r = blockIdx.z;
   const int nrow = min(ts, ntp - r0);
   const int PI = pb % nxp, PJ = pb / nxp;
   const int Kc = ntc * npc, Kp = ntp * npp;
   const int nbc = nxc * nyc, nbp = nxp * nyp;
   const int half = npc / 2;
-  for (int comp = 0; comp < 2; ++comp) {
-    for (int i = threadIdx.x; i < nrow * npp; i += kBlock) acc[i] = {0, 0};
-    for (int q = 0; q < 4; ++q) {
-      const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
-      if (ci >= nxc || cj >= nyc) continue;
-      const C2<T>* __restrict__ src = Sc + (((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc;
-      __syncthreads();
-      for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
-        const int row = i / npc, col = i - row * npc;
-        const int it = r0 + row;
-        C2<T> v{0, 0};
-        for (int a = 0; a < order; ++a) {
-          const int e = it * order + a;
-          const int cc = th_flip[e] ? (col + half) % npc : col;
-          const C2<T> s = src[th_row[e] * npc + cc];
-          const T w = th_w[e];
-          v.x += w * s.x;
-          v.y += w * s.y;
-        }
-        tmp[i] = v;
+  const int nout = nrow * npp;
+  C2<T> acc[kAggVPT];
+#pragma unroll
+  for (int v = 0; v < kAggVPT; ++v) acc[v] = {0, 0};
+  for (int q = 0; q < 4; ++q) {
+    const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
+    if (ci >= nxc || cj >= nyc) continue;
+    const C2<T>* __restrict__ src = Sc + (((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
+      const int row = i / npc, col = i - row * npc;
+      const int it = r0 + row;
+      C2<T> v{0, 0};
+      for (int a = 0; a < order; ++a) {
+        const int e = it * order + a;
+        const int cc = th_flip[e] ? (col + half) % npc : col;
+        const C2<T> s = src[th_row[e] * npc + cc];
+        const T w = th_w[e];
+        v.x += w * s.x;
+        v.y += w * s.y;
       }
-      __syncthreads();
-      const C2<T>* __restrict__ ph = phase + (size_t)q * Kp;
-      for (int i = threadIdx.x; i < nrow * npp; i += kBlock) {
-        const int row = i / npp, ip = i - row * npp;
-        C2<T> v{0, 0};
-        for (int b = 0; b < order; ++b) {
-          const T w = ph_w[ip * order + b];
-          const C2<T> s = tmp[row * npc + ph_col[ip * order + b]];
-          v.x += w * s.x;
-          v.y += w * s.y;
-        }
-        cfma(acc[i], ph[(r0 + row) * npp + ip], v);
-      }
+      tmp[i] = v;
     }
     __syncthreads();
-    C2<T>* __restrict__ dst = Sp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)r0 * npp;
-    for (int i = threadIdx.x; i < nrow * npp; i += kBlock) dst[i] = acc[i];
-    __syncthreads();
-  }
-}
-
-// -------------------------------------------------------------- translate --
-// G[r][p][c][s] = sum over the interaction list of TL[offset][s] S[r][q][c][s]
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_translate(int nx, int ny, int K, const C2<T>* __restrict__ S,
-                                                       C2<T>* __restrict__ G, const C2<T>* __restrict__ TL) {
-  const int p = blockIdx.x, r = blockIdx.y;
-  const int s = blockIdx.z * kBlock + threadIdx.x;
-  if (s >= K) return;
-  const int I = p % nx, J = p / nx;
-  const int nb = nx * ny;
-  C2<T> g0{0, 0}, g1{0, 0};
-  for (int dy = -3; dy <= 3; ++dy) {
-    const int J2 = J + dy;
-    if (J2 < 0 || J2 >= ny || abs((J2 >> 1) - (J >> 1)) > 1) continue;
-    for (int dx = -3; dx <= 3; ++dx) {
-      if (abs(dx) <= 1 && abs(dy) <= 1) continue;
-      const int I2 = I + dx;
-      if (I2 < 0 || I2 >= nx || abs((I2 >> 1) - (I >> 1)) > 1) continue;
-      const C2<T> t = TL[(size_t)((dy + 3) * 7 + dx + 3) * K + s];
-      const C2<T>* src = S + ((size_t)r * nb + J2 * nx + I2) * 2 * K;
-      cfma(g0, t, src[s]);
-      cfma(g1, t, src[K + s]);
+    const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)r0 * npp;
+#pragma unroll
+    for (int vv = 0; vv < kAggVPT; ++vv) {
+      const int i = threadIdx.x + vv * kBlock;
+      if (i >= nout) continue;
+      const int row = i / npp, ip = i - row * npp;
+      C2<T> s{0, 0};
+      for (int b = 0; b < order; ++b) {
+        const T w = ph_w[ip * order + b];
+        const C2<T> t = tmp[row * npc + ph_col[ip * order + b]];
+        s.x += w * t.x;
+        s.y += w * t.y;
+      }
+      cfma(acc[vv], ph[i], s);
     }
   }
-  C2<T>* dst = G + ((size_t)r * nb + p) * 2 * K;
-  dst[s] = g0;
-  dst[K + s] = g1;
+  C2<T>* __restrict__ dst = Sp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)r0 * npp;
+#pragma unroll
+  for (int vv = 0; vv < kAggVPT; ++vv) {
+    const int i = threadIdx.x + vv * kBlock;
+    if (i < nout) dst[i] = acc[vv];
+  }
 }
 
 // ----------------------------------------------------------- disaggregate --
-// G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), anterpolation as gathers
-// over the transposed stencils.  Child rows [c0, c0 + ts) per block.
+// G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), as gathers over the
+// transposed stencils.  Block = (child box, component) x strip of ts child
+// rows x RHS.  LDS: the phase-weighted parent rows [plo, phi] ([rows][np_p])
+// and their phi-transposed interpolation ([rows][np_c]).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_disaggregate(
     int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int tmax, int pmax,
@@ -287,9 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
     const int* __restrict__ tth_hi, const int* __restrict__ tph_col, const T* __restrict__ tph_w,
     const C2<T>* __restrict__ phase) {
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* tmp = reinterpret_cast<C2<T>*>(smem_raw);
-  const int cb = blockIdx.x, r = blockIdx.y;
-  const int c0 = blockIdx.z * ts;
+  const int cb = blockIdx.x >> 1, comp = blockIdx.x & 1;
+  const int c0 = blockIdx.y * ts, r = blockIdx.z;
   const int nrow = min(ts, ntc - c0);
   const int ci = cb % nxc, cj = cb / nxc;
   const int pb = (cj >> 1) * nxp + (ci >> 1);
@@ -303,41 +341,69 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
     phi = max(phi, tth_hi[rr]);
   }
   const int np_rows = phi - plo + 1;
-  const C2<T>* __restrict__ ph = phase + (size_t)q * Kp;
-  for (int comp = 0; comp < 2; ++comp) {
-    const C2<T>* __restrict__ src = Gp + (((size_t)r * nbp + pb) * 2 + comp) * Kp;
-    __syncthreads();
-    for (int i = threadIdx.x; i < np_rows * npc; i += kBlock) {
-      const int row = i / npc, col = i - row * npc;
-      const int prow = plo + row;
-      C2<T> v{0, 0};
-      for (int e = 0; e < pmax; ++e) {
-        const T w = tph_w[col * pmax + e];
-        const int pc = tph_col[col * pmax + e];
-        const int sidx = prow * npp + pc;
-        const C2<T> t = cmul_conj_a(ph[sidx], src[sidx]);
-        v.x += w * t.x;
-        v.y += w * t.y;
-      }
-      tmp[i] = v;
+  C2<T>* par = reinterpret_cast<C2<T>*>(smem_raw);  // [np_rows][npp]
+  C2<T>* tmp = par + (size_t)np_rows * npp;          // [np_rows][npc]
+  const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)plo * npp;
+  const C2<T>* __restrict__ src = Gp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)plo * npp;
+  for (int i = threadIdx.x; i < np_rows * npp; i += kBlock) par[i] = cmul_conj_a(ph[i], src[i]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < np_rows * npc; i += kBlock) {
+    const int row = i / npc, col = i - row * npc;
+    C2<T> v{0, 0};
+    for (int e = 0; e < pmax; ++e) {
+      const T w = tph_w[col * pmax + e];
+      const C2<T> t = par[row * npp + tph_col[col * pmax + e]];
+      v.x += w * t.x;
+      v.y += w * t.y;
     }
-    __syncthreads();
-    C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc;
-    for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
-      const int row = i / npc, col = i - row * npc;
-      const int it = c0 + row;
-      C2<T> v{0, 0};
-      for (int e = 0; e < tmax; ++e) {
-        const int idx = it * tmax + e;
-        const int cc = tth_flip[idx] ? (col + half) % npc : col;
-        const C2<T> s = tmp[(tth_row[idx] - plo) * npc + cc];
-        const T w = tth_w[idx];
-        v.x += w * s.x;
-        v.y += w * s.y;
-      }
-      C2<T> o = dst[it * npc + col];
-      dst[it * npc + col] = {o.x + v.x, o.y + v.y};
+    tmp[i] = v;
+  }
+  __syncthreads();
+  C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc;
+  for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
+    const int row = i / npc, col = i - row * npc;
+    const int it = c0 + row;
+    C2<T> v{0, 0};
+    for (int e = 0; e < tmax; ++e) {
+      const int idx = it * tmax + e;
+      const int cc = tth_flip[idx] ? (col + half) % npc : col;
+      const C2<T> s = tmp[(tth_row[idx] - plo) * npc + cc];
+      const T w = tth_w[idx];
+      v.x += w * s.x;
+      v.y += w * s.y;
     }
+    C2<T> o = dst[it * npc + col];
+    dst[it * npc + col] = {o.x + v.x, o.y + v.y};
+  }
+}
+
+// -------------------------------------------------------------- translate --
+// G[r][p][c][s] = sum over the interaction list of TL[offset][s] S[r][q][c][s]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_translate(int nx, int ny, int K, const C2<T>* __restrict__ S,
+                                                       C2<T>* __restrict__ G, const C2<T>* __restrict__ TL) {
+  const int p = blockIdx.x, r = blockIdx.y;
+  const int s = blockIdx.z * kBlock + threadIdx.x;
+  if (s < K) {
+    const int I = p % nx, J = p / nx;
+    const int nb = nx * ny;
+    C2<T> g0{0, 0}, g1{0, 0};
+    for (int dy = -3; dy <= 3; ++dy) {
+      const int J2 = J + dy;
+      if (J2 < 0 || J2 >= ny || abs((J2 >> 1) - (J >> 1)) > 1) continue;
+      for (int dx = -3; dx <= 3; ++dx) {
+        if (abs(dx) <= 1 && abs(dy) <= 1) continue;
+        const int I2 = I + dx;
+        if (I2 < 0 || I2 >= nx || abs((I2 >> 1) - (I >> 1)) > 1) continue;
+        const C2<T> t = TL[(size_t)((dy + 3) * 7 + dx + 3) * K + s];
+        const C2<T>* src = S + ((size_t)r * nb + J2 * nx + I2) * 2 * K;
+        cfma(g0, t, src[s]);
+        cfma(g1, t, src[K + s]);
+      }
+    }
+    C2<T>* dst = G + ((size_t)r * nb + p) * 2 * K;
+    dst[s] = g0;
+    dst[K + s] = g1;
   }
 }
 
@@ -516,6 +582,7 @@ class EngineT final : public Engine {
   };
   struct Itp {
     int order, tmax, pmax, ts_agg, ts_dis;
+    size_t lds_dis;
     DevMem th_row, th_w, th_flip, ph_col, ph_w, tth_row, tth_w, tth_flip, tth_lo, tth_hi, tph_col, tph_w, phase;
   };
 
@@ -560,41 +627,38 @@ class EngineT final : public Engine {
       if (int rc = put_i(I.tph_col, T0.tph_col, err)) return rc;
       if (int rc = put_r(I.tph_w, T0.tph_w, err)) return rc;
       if (int rc = put_c(I.phase, T0.phase, err)) return rc;
-      // strip heights so that the LDS tiles stay within the budget
+      // aggregation strips: each thread owns at most kAggVPT outputs
       const Lvl &C = lv_[l - 1], &Pp = lv_[l];
-      const size_t row_agg = (size_t)(C.np + Pp.np) * sizeof(CT);
-      I.ts_agg = (int)std::max<size_t>(1, std::min<size_t>(Pp.nt, kLdsBudget / row_agg));
-      // disaggregation: largest child strip whose parent-row range fits
-      int ts = C.nt;
-      while (ts > 1) {
-        size_t worst = 0;
-        for (int c0 = 0; c0 < C.nt; c0 += ts) {
-          int lo = Pp.nt, hi = -1;
-          for (int rr = c0; rr < std::min(C.nt, c0 + ts); ++rr) {
-            lo = std::min(lo, T0.tth_lo[rr]);
-            hi = std::max(hi, T0.tth_hi[rr]);
-          }
-          worst = std::max<size_t>(worst, (size_t)(hi - lo + 1));
-        }
-        if (worst * C.np * sizeof(CT) <= kLdsBudget) break;
-        ts = (ts + 1) / 2;
+      if (Pp.np > kBlock * kAggVPT) {
+        err = "aggregation: more than " + std::to_string(kBlock * kAggVPT) + " phi samples per row at level " +
+              std::to_string(l);
+        return -1;
       }
-      {
-        size_t worst = 0;
+      I.ts_agg = std::max(1, std::min(Pp.nt, (kBlock * kAggVPT) / Pp.np));
+      if ((size_t)I.ts_agg * C.np * sizeof(CT) > kLdsBudget) I.ts_agg = std::max<int>(1, kLdsBudget / (C.np * sizeof(CT)));
+      // disaggregation strips: at most kDisRows child rows, and the staged
+      // parent rows ([rows][np_p + np_c]) within the LDS budget
+      auto worst_rows = [&](int ts) {
+        int worst = 0;
         for (int c0 = 0; c0 < C.nt; c0 += ts) {
           int lo = Pp.nt, hi = -1;
           for (int rr = c0; rr < std::min(C.nt, c0 + ts); ++rr) {
             lo = std::min(lo, T0.tth_lo[rr]);
             hi = std::max(hi, T0.tth_hi[rr]);
           }
-          worst = std::max<size_t>(worst, (size_t)(hi - lo + 1));
+          worst = std::max(worst, hi - lo + 1);
         }
-        if (worst * C.np * sizeof(CT) > kLdsBudget) {
-          err = "disaggregation tile exceeds the LDS budget at level " + std::to_string(l);
-          return -1;
-        }
+        return worst;
+      };
+      const size_t row_bytes = (size_t)(Pp.np + C.np) * sizeof(CT);
+      int ts = std::min(C.nt, kDisRows);
+      while (ts > 1 && (size_t)worst_rows(ts) * row_bytes > kLdsBudget) --ts;
+      if ((size_t)worst_rows(ts) * row_bytes > kLdsBudget) {
+        err = "disaggregation tile exceeds the LDS budget at level " + std::to_string(l);
+        return -1;
       }
       I.ts_dis = ts;
+      I.lds_dis = (size_t)worst_rows(ts) * row_bytes;
     }
     // leaf data
     nx0_ = u.nx0;
@@ -638,6 +702,24 @@ class EngineT final : public Engine {
       }
       if (int rc = put_i(self_nbr_, self_nbr, err)) return rc;
       if (int rc = put_i(self_slot_, self_slot, err)) return rc;
+      // per particle tile and slot: the shared matrix, -1 (none) or -2 (mixed)
+      auto tile_slots = [&](const std::vector<int>& nbr, const std::vector<int>& slot, int nsp) {
+        const int ntl = (P_ + kTPN - 1) / kTPN;
+        std::vector<int> ts((size_t)ntl * nsp, -1);
+        for (int t = 0; t < ntl; ++t)
+          for (int o = 0; o < nsp; ++o) {
+            int v = -1;
+            for (int p = t * kTPN; p < std::min(P_, (t + 1) * kTPN); ++p) {
+              if (nbr[(size_t)p * nsp + o] < 0) continue;
+              const int sl = slot[(size_t)p * nsp + o];
+              v = (v == -1 || v == sl) ? sl : -2;
+            }
+            ts[(size_t)t * nsp + o] = v;
+          }
+        return ts;
+      };
+      if (int rc = put_i(near_tile_slot_, tile_slots(u.near_nbr, u.near_slot, 9), err)) return rc;
+      if (int rc = put_i(self_tile_slot_, tile_slots(self_nbr, self_slot, 1), err)) return rc;
     }
     centers_ = u.centers;
     nslots_ = (int)u.near_mats.size();
@@ -676,18 +758,62 @@ class EngineT final : public Engine {
     return 0;
   }
 
+  // Graph-cached product: the kernel sequence of one (x, y, R, parts)
+  // combination is captured once on an internal stream and replayed on the
+  // caller's stream.
   int matvec(const void* xv, void* yv, int R, int parts, void* stream, std::string& err) override {
+    const int old_alloc = R_alloc_;
     if (int rc = ensure(R, err)) return rc;
+    if (R_alloc_ != old_alloc) clear_graphs();
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!use_graphs_ || prof_on_) return enqueue(xv, yv, R, parts, st, err);
+    GraphEntry* g = nullptr;
+    for (auto& e : graphs_)
+      if (e.x == xv && e.y == yv && e.R == R && e.parts == parts) g = &e;
+    if (!g) {
+      if (!cap_stream_) HIP_TRY(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+      if (graphs_.size() >= kMaxGraphs) {
+        auto oldest = std::min_element(graphs_.begin(), graphs_.end(),
+                                       [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
+        destroy_entry(*oldest);
+        graphs_.erase(oldest);
+      }
+      GraphEntry e;
+      e.x = xv;
+      e.y = yv;
+      e.R = R;
+      e.parts = parts;
+      HIP_TRY(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+      int rc = enqueue(xv, yv, R, parts, cap_stream_, err);
+      hipGraph_t graph = nullptr;
+      hipError_t ce = hipStreamEndCapture(cap_stream_, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      HIP_TRY(ce);
+      hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIP_TRY(ie);
+      graphs_.push_back(std::move(e));
+      g = &graphs_.back();
+    }
+    g->used = ++use_clock_;
+    HIP_TRY(hipGraphLaunch(g->exec, st));
+    return 0;
+  }
+
+  int enqueue(const void* xv, void* yv, int R, int parts, hipStream_t st, std::string& err) {
+    cur_st_ = st;
     const CT* x = reinterpret_cast<const CT*>(xv);
     CT* y = reinterpret_cast<CT*>(yv);
     const dim3 blk(kBlock);
     const double cb = sizeof(CT);
     if (parts & 1) {
-      dim3 grid((P_ + 3) / 4, R);
-      begin("near", cb * ((double)2 * R * P_ * n_ + (double)nslots_ * n_ * n_), 8.0 * R * nnear_ * (double)n_ * n_, st);
-      hipLaunchKernelGGL(k_near<T>, grid, blk, 0, st, n_, P_, x, y, near_mats_.template as<CT>(),
-                         near_nbr_.template as<int>(), near_slot_.template as<int>(), 9, 0);
+      begin("near", cb * ((double)2 * R * P_ * n_ + (double)nslots_ * n_ * n_),
+                       8.0 * R * nnear_ * (double)n_ * n_);
+      launch_near(x, y, R, near_mats_.template as<CT>(), near_nbr_.template as<int>(), near_slot_.template as<int>(),
+                  near_tile_slot_.template as<int>(), 9, st);
       end(st);
     } else {
       const size_t cnt = (size_t)R * P_ * n_;
@@ -697,11 +823,11 @@ class EngineT final : public Engine {
       const Lvl& L0 = lv_[0];
       const int nb0 = L0.nx * L0.ny;
       {
-        dim3 grid(ntiles_, R);
+        dim3 grid(ntiles_, (M2_ + kProjBlock - 1) / kProjBlock, R);
         size_t sh = (size_t)kTP * n_ * sizeof(CT);
         begin("project", cb * ((double)R * P_ * n_ + (double)R * P_ * M2_ + (double)nc_ * n_ * M2_),
-              8.0 * R * P_ * (double)n_ * M2_, st);
-        hipLaunchKernelGGL((k_project<T, kTP>), grid, blk, sh, st, n_, P_, M2_, nb0, x, L0.S.template as<CT>(),
+                         8.0 * R * P_ * (double)n_ * M2_);
+        hipLaunchKernelGGL((k_project<T, kTP>), grid, dim3(kProjBlock), sh, st, n_, P_, M2_, nb0, x, L0.S.template as<CT>(),
                            Rm_.template as<CT>(), rm_off_.template as<int>(), order_.template as<int>(),
                            tile_start_.template as<int>(), tile_count_.template as<int>(),
                            tile_class_.template as<int>(), box_of_.template as<int>());
@@ -710,10 +836,10 @@ class EngineT final : public Engine {
       for (int l = 1; l < ntl_; ++l) {
         const Lvl &C = lv_[l - 1], &Pp = lv_[l];
         const Itp& I = it_[l];
-        dim3 grid(Pp.nx * Pp.ny, R, (Pp.nt + I.ts_agg - 1) / I.ts_agg);
-        size_t sh = (size_t)I.ts_agg * (C.np + Pp.np) * sizeof(CT);
+        dim3 grid(Pp.nx * Pp.ny * 2, (Pp.nt + I.ts_agg - 1) / I.ts_agg, R);
+        size_t sh = (size_t)I.ts_agg * C.np * sizeof(CT);
         begin("aggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
-              2.0 * R * (double)C.nx * C.ny * 2 * (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K), st);
+              2.0 * R * (double)C.nx * C.ny * 2 * (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K));
         hipLaunchKernelGGL(k_aggregate<T>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
                            Pp.np, I.ts_agg, C.S.template as<CT>(), Pp.S.template as<CT>(), I.th_row.template as<int>(),
                            I.th_w.template as<T>(), I.th_flip.template as<int>(), I.ph_col.template as<int>(),
@@ -724,18 +850,17 @@ class EngineT final : public Engine {
         const Lvl& L = lv_[l];
         dim3 grid(L.nx * L.ny, R, (L.K + kBlock - 1) / kBlock);
         begin("translate_l" + std::to_string(l), cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K),
-              16.0 * R * (double)pairs_[l] * L.K, st);
+                         16.0 * R * (double)pairs_[l] * L.K);
         hipLaunchKernelGGL(k_translate<T>, grid, blk, 0, st, L.nx, L.ny, L.K, L.S.template as<CT>(),
                            L.G.template as<CT>(), L.TL.template as<CT>());
         end(st);
         if (l + 1 < ntl_) {
           const Lvl& Pp = lv_[l + 1];
           const Itp& I = it_[l + 1];
-          dim3 g2(L.nx * L.ny, R, (L.nt + I.ts_dis - 1) / I.ts_dis);
-          // LDS: the largest parent-row range of any strip
-          size_t sh = kLdsBudget;
+          dim3 g2(L.nx * L.ny * 2, (L.nt + I.ts_dis - 1) / I.ts_dis, R);
+          size_t sh = I.lds_dis;
           begin("disaggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
-                2.0 * R * (double)L.nx * L.ny * 2 * (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K), st);
+                2.0 * R * (double)L.nx * L.ny * 2 * (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K));
           hipLaunchKernelGGL(k_disaggregate<T>, g2, blk, sh, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.ny, Pp.nt, Pp.np,
                              I.ts_dis, I.tmax, I.pmax, Pp.G.template as<CT>(), L.G.template as<CT>(),
                              I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
@@ -748,7 +873,7 @@ class EngineT final : public Engine {
         dim3 grid(ntiles_, R);
         size_t sh = 0;
         begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
-              8.0 * R * P_ * (double)n_ * M2_, st);
+                         8.0 * R * P_ * (double)n_ * M2_);
         hipLaunchKernelGGL((k_receive<T, kTP>), grid, blk, sh, st, n_, P_, M2_, nb0, y, L0.G.template as<CT>(),
                            Qm_.template as<CT>(), qm_off_.template as<int>(), order_.template as<int>(),
                            tile_start_.template as<int>(), tile_count_.template as<int>(),
@@ -762,12 +887,23 @@ class EngineT final : public Engine {
 
   int precondition(const void* xv, void* yv, int R, void* stream, std::string& err) override {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    dim3 grid((P_ + 3) / 4, R);
-    hipLaunchKernelGGL(k_near<T>, grid, dim3(kBlock), 0, st, n_, P_, reinterpret_cast<const CT*>(xv),
-                       reinterpret_cast<CT*>(yv), zinv_.template as<CT>(), self_nbr_.template as<int>(),
-                       self_slot_.template as<int>(), 1, 0);
+    launch_near(reinterpret_cast<const CT*>(xv), reinterpret_cast<CT*>(yv), R, zinv_.template as<CT>(),
+                self_nbr_.template as<int>(), self_slot_.template as<int>(), self_tile_slot_.template as<int>(), 1, st);
     HIP_TRY(hipGetLastError());
     return 0;
+  }
+
+  void launch_near(const CT* x, CT* y, int R, const CT* mats, const int* nbr, const int* slot, const int* tile_slot,
+                   int nsp, hipStream_t st) {
+    dim3 grid((P_ + kTPN - 1) / kTPN, R);
+    const size_t xs_bytes = (size_t)kTPN * n_ * sizeof(CT);
+    const size_t m_bytes = (size_t)n_ * n_ * sizeof(CT);
+    if (xs_bytes + m_bytes <= 64 * 1024)
+      hipLaunchKernelGGL((k_near<T, kTPN, true>), grid, dim3(kBlock), xs_bytes + m_bytes, st, n_, P_, nsp, x, y, mats,
+                         nbr, slot, tile_slot);
+    else
+      hipLaunchKernelGGL((k_near<T, kTPN, false>), grid, dim3(kBlock), xs_bytes, st, n_, P_, nsp, x, y, mats, nbr,
+                         slot, tile_slot);
   }
 
   int rhs(const std::vector<cd>& pat, const std::vector<V3>& khat, int R, void* b, void* stream,
@@ -831,7 +967,9 @@ class EngineT final : public Engine {
 
  private:
   static constexpr int kTP = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int kTPN = 16;
   static constexpr size_t kLdsBudget = 48 * 1024;
+  static constexpr int kDisRows = 8;
 
   template <typename U>
   static int put_raw(DevMem& d, const U* h, size_t count, std::string& err) {
@@ -854,30 +992,20 @@ class EngineT final : public Engine {
     return put_raw(d, w.data(), w.size(), err);
   }
 
+  bool prof_on_ = false;
+  std::vector<StageTime> table_;
+  std::map<std::string, int> stage_index_;
+  int cur_stage_ = -1;
   struct Rec {
     int stage;
     hipEvent_t a, b;
   };
-  bool prof_on_ = false;
   std::vector<hipEvent_t> pool_;
   std::vector<Rec> rec_;
-  std::vector<StageTime> table_;
-  std::map<std::string, int> stage_index_;
-  int cur_stage_ = -1;
   hipEvent_t cur_a_{};
+  hipStream_t cur_st_{};
 
-  hipEvent_t take_event() {
-    if (!pool_.empty()) {
-      hipEvent_t e = pool_.back();
-      pool_.pop_back();
-      return e;
-    }
-    hipEvent_t e{};
-    (void)hipEventCreate(&e);
-    return e;
-  }
-  void begin(const std::string& name, double bytes, double flops, hipStream_t st) {
-    if (!prof_on_) return;
+  void register_stage(const std::string& name, double bytes, double flops) {
     auto it = stage_index_.find(name);
     if (it == stage_index_.end()) {
       StageTime t;
@@ -888,8 +1016,51 @@ class EngineT final : public Engine {
       it = stage_index_.emplace(name, (int)table_.size() - 1).first;
     }
     cur_stage_ = it->second;
+  }
+
+  struct GraphEntry {
+    const void* x = nullptr;
+    void* y = nullptr;
+    int R = 0, parts = 0;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long used = 0;
+  };
+  static constexpr size_t kMaxGraphs = 32;
+  std::vector<GraphEntry> graphs_;
+  hipStream_t cap_stream_ = nullptr;
+  unsigned long long use_clock_ = 0;
+  bool use_graphs_ = std::getenv("MLFMA_NO_GRAPH") == nullptr;
+
+  static void destroy_entry(GraphEntry& e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    e.exec = nullptr;
+  }
+  void clear_graphs() {
+    for (auto& e : graphs_) destroy_entry(e);
+    graphs_.clear();
+  }
+
+ public:
+  ~EngineT() override {
+    (void)hipDeviceSynchronize();
+    clear_graphs();
+    for (auto e : pool_) (void)hipEventDestroy(e);
+    for (auto& r : rec_) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+  }
+
+ private:
+  // Profiling: launches are bracketed by HIP events on the launch stream
+  // (direct launches only; the product is not graph-captured while
+  // profiling).
+  void begin(const std::string& name, double bytes, double flops) {
+    if (!prof_on_) return;
+    register_stage(name, bytes, flops);
     cur_a_ = take_event();
-    (void)hipEventRecord(cur_a_, st);
+    (void)hipEventRecord(cur_a_, cur_st_);
   }
   void end(hipStream_t st) {
     if (!prof_on_) return;
@@ -897,13 +1068,23 @@ class EngineT final : public Engine {
     (void)hipEventRecord(b, st);
     rec_.push_back({cur_stage_, cur_a_, b});
   }
+  hipEvent_t take_event() {
+    if (!pool_.empty()) {
+      hipEvent_t e = pool_.back();
+      pool_.pop_back();
+      return e;
+    }
+    hipEvent_t e{};
+    (void)hipEventCreate(&e);
+    return e;
+  }
 
   int N_ = 0, n_ = 0, P_ = 0, nc_ = 0, ntl_ = 0, nx0_ = 0, ny0_ = 0, ntiles_ = 0, tp_ = 0, M2_ = 0, R_alloc_ = 0;
   std::vector<Lvl> lv_;
   std::vector<Itp> it_;
   DevMem box_of_, class_of_, order_, tile_start_, tile_count_, tile_class_;
   DevMem Rm_, Qm_, rm_off_, qm_off_;
-  DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_;
+  DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;
   std::vector<V3> centers_;
   int nslots_ = 0;
   long long nnear_ = 0;
