@@ -164,8 +164,8 @@ int mlfma_plane_wave_rhs(mlfma_ctx* ctx, int32_t R, const double* khat, const do
                          void* stream);
 
 /* y = Z x for R right-hand sides (the hot path, Sec. IV).  x_dev, y_dev:
- * caller-owned device buffers [R][P][2][N] in the context precision; they
- * must not overlap (EINVAL).  Asynchronous on `stream`; no host
+ * caller-owned device buffers [R][P][2][N] in the context precision,
+ * 16-byte aligned; they must not overlap (EINVAL otherwise).  Asynchronous on `stream`; no host
  * synchronisation.  Scratch pattern buffers are held by the context and
  * grow to the largest R seen. */
 int mlfma_matvec(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream);

@@ -466,6 +466,7 @@ int mlfma_matvec_parts(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R
   return guarded(ctx, [&]() -> int {
     if (!x_dev || !y_dev || R < 1 || parts < 1 || parts > 3) return fail(ctx, MLFMA_EINVAL, "matvec arguments");
     if (x_dev == y_dev) return fail(ctx, MLFMA_EINVAL, "x and y must not alias");
+    if (((uintptr_t)x_dev | (uintptr_t)y_dev) & 15) return fail(ctx, MLFMA_EINVAL, "x and y must be 16-byte aligned");
     if (int rc = do_prepare(ctx)) return rc;
     const size_t bytes = (size_t)R * ctx->P * 2 * ctx->N * (ctx->tp.precision == MLFMA_C128 ? 16 : 8);
     const char *xa = (const char*)x_dev, *ya = (const char*)y_dev;

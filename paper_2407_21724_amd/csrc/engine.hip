@@ -18,6 +18,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "engine.hpp"
@@ -141,6 +142,170 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(C2<T>* __restrict__ y, siz
   size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * kBlock;
   for (; i < count; i += stride) y[i] = {0, 0};
+}
+
+// ------------------------------------------------------------ MFMA GEMM --
+// Real FP32 GEMM on the matrix cores, C[m][n] (+)= sum_k A[m][k] B[k][n],
+// used for the dense contractions of the product (near blocks, leaf
+// radiation, receive).  Complex matrices enter in real 2x2-block form: for
+// a complex matrix Z the real matrix has Z_r, -Z_i in row 2i and Z_i, Z_r in
+// row 2i+1, so that interleaved (re, im) vectors are its real operands.
+//   A: row-major [M][lda].
+//   B column n, segment s (K = nseg * kseg): floats Bsrc[bcol[n*nseg+s] *
+//     ldb + k'] with k = s*kseg + k'; bcol < 0 gives a zero column.
+//   C column n: floats Cdst[ccol[n] * ldc + m].
+//   blockIdx.z = right-hand side r: B and C advance by strideB, strideC.
+// Block = 4 waves, tile 64 x 64, K staged in chunks of 16 through LDS;
+// wave w owns rows [16w, 16w+16) as four 16 x 16 MFMA tiles.  Lane layout
+// of v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16k, B[k][j] from lane
+// j + 16k, result row 4*(lane/16) + v, column lane % 16 in register v.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kGM = 64;
+template <int NT, int KC>
+__global__ __launch_bounds__(kBlock) void k_gemm_f32(int M, int ncols, int nseg, int kseg, const float* __restrict__ A,
+                                                      int lda, const float* __restrict__ Bsrc, int ldb,
+                                                      const int* __restrict__ bcol, float* __restrict__ Cdst, int ldc,
+                                                      const int* __restrict__ ccol, int accumulate, size_t strideB,
+                                                      size_t strideC) {
+  constexpr int BN = 16 * NT;
+  __shared__ float As[kGM][KC + 1];
+  __shared__ float Bs[KC][BN + 4];
+  const int m0 = blockIdx.x * kGM, n0 = blockIdx.y * BN, r = blockIdx.z;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const float* __restrict__ Bb = Bsrc + (size_t)r * strideB;
+  const int K = nseg * kseg;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < (kGM * KC) / kBlock; ++i) {
+      const int idx = t + i * kBlock;
+      const int row = idx / KC, kk = idx % KC;
+      const int m = m0 + row, k = k0 + kk;
+      As[row][kk] = (m < M && k < K) ? A[(size_t)m * lda + k] : 0.f;
+    }
+    for (int idx = t; idx < BN * KC; idx += kBlock) {
+      const int col = idx / KC, kk = idx % KC;
+      const int n = n0 + col, k = k0 + kk;
+      float v = 0.f;
+      if (n < ncols && k < K) {
+        const int sgm = k / kseg;
+        const int src = bcol[(size_t)n * nseg + sgm];
+        if (src >= 0) v = Bb[(size_t)src * ldb + (k - sgm * kseg)];
+      }
+      Bs[kk][col] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC / 4; ++k4) {
+      const float a = As[16 * wave + (lane & 15)][4 * k4 + (lane >> 4)];
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        const float b = Bs[4 * k4 + (lane >> 4)][16 * c + (lane & 15)];
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+      }
+    }
+  }
+  float* __restrict__ Cb = Cdst + (size_t)r * strideC;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    const int n = n0 + 16 * c + (lane & 15);
+    if (n >= ncols) continue;
+    float* __restrict__ col = Cb + (size_t)ccol[n] * ldc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + 16 * wave + 4 * (lane >> 4) + v;
+      if (m < M) col[m] = accumulate ? col[m] + acc[c][v] : acc[c][v];
+    }
+  }
+}
+
+// Streaming variant: no LDS staging of the operands.  Block = 4 waves that
+// share one output tile of RT x CT 16 x 16 MFMA tiles and split the K range
+// four ways; partial sums are reduced through LDS in a fixed order.  K is
+// walked in steps of 16 with a k-permutation inside each step: lane (i, kq)
+// loads the 4 consecutive values k = 16 s + 4 kq + q (one 16-byte load) of
+// its A row and B column, and MFMA q contracts over kq.  A and B use the same
+// permutation, so the sum covers every k once.  Requires lda, ldb, kseg and
+// the segment length multiples of 4 floats and 16-byte aligned bases.
+template <int RT, int CT>
+__global__ __launch_bounds__(kBlock) void k_gemm_stream(int M, int ncols, int nseg, int kseg,
+                                                         const float* __restrict__ A, int lda,
+                                                         const float* __restrict__ Bsrc, int ldb,
+                                                         const int* __restrict__ bcol, float* __restrict__ Cdst,
+                                                         int ldc, const int* __restrict__ ccol, int accumulate,
+                                                         size_t strideB, size_t strideC) {
+  __shared__ f32x4 red[3][RT * CT][64];
+  const int m0 = blockIdx.x * 16 * RT, n0 = blockIdx.y * 16 * CT, r = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  const float* __restrict__ Bb = Bsrc + (size_t)r * strideB;
+  const int K = nseg * kseg;
+  const int nsup = (K + 15) / 16;
+  const int s0 = (wave * nsup) / 4, s1 = ((wave + 1) * nsup) / 4;
+  // per column tile: this lane's column and its source rows per segment
+  int ncol[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) ncol[ct] = n0 + 16 * ct + i;
+  f32x4 acc[RT][CT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int sup = s0; sup < s1; ++sup) {
+    const int k = 16 * sup + 4 * kq;
+    f32x4 a[RT], b[CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int m = m0 + 16 * rt + i;
+      a[rt] = (m < M && k < K) ? *reinterpret_cast<const f32x4*>(A + (size_t)m * lda + k) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      b[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int n = ncol[ct];
+      if (n < ncols && k < K) {
+        const int sg = nseg == 1 ? 0 : k / kseg;
+        const int src = bcol[(size_t)n * nseg + sg];
+        if (src >= 0) b[ct] = *reinterpret_cast<const f32x4*>(Bb + (size_t)src * ldb + (k - sg * kseg));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][q], b[ct][q], acc[rt][ct], 0, 0, 0);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) red[wave - 1][rt * CT + ct][lane] = acc[rt][ct];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  float* __restrict__ Cb = Cdst + (size_t)r * strideC;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      f32x4 v = acc[rt][ct];
+#pragma unroll
+      for (int w = 0; w < 3; ++w) v += red[w][rt * CT + ct][lane];
+      const int n = ncol[ct];
+      if (n >= ncols) continue;
+      float* __restrict__ col = Cb + (size_t)ccol[n] * ldc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + 16 * rt + 4 * kq + e;
+        if (m < M) col[m] = accumulate ? col[m] + v[e] : v[e];
+      }
+    }
 }
 
 // ------------------------------------------------------- leaf projection --
@@ -739,8 +904,91 @@ class EngineT final : public Engine {
               pairs_[l]++;
             }
     }
+    if (int rc = upload_mfma(u, err)) return rc;
     R_alloc_ = 0;
     return 0;
+  }
+
+  // Real 2x2-block forms of the dense contractions for the matrix cores
+  // (FP32 contexts only): radiation and receiving matrices per class, and
+  // the nine near blocks side by side when every particle uses the same
+  // block for a given neighbour offset.
+  int upload_mfma(const Upload& u, std::string& err) {
+    mfma_ = std::is_same<T, float>::value && std::getenv("MLFMA_NO_MFMA") == nullptr;
+    near_uniform_ = false;
+    if (!mfma_) return 0;
+    const int n = n_, nf = 2 * n_;
+    auto put_f = [&](DevMem& d, const std::vector<float>& v) { return put_raw(d, v.data(), v.size(), err); };
+    auto block2 = [](std::vector<float>& A, size_t lda, size_t row, size_t col, cd z) {
+      A[row * lda + col] = (float)z.real();
+      A[row * lda + col + 1] = (float)-z.imag();
+      A[(row + 1) * lda + col] = (float)z.imag();
+      A[(row + 1) * lda + col + 1] = (float)z.real();
+    };
+    // class ranges of the class-sorted particle order
+    cls_start_.assign(nc_, 0);
+    cls_count_.assign(nc_, 0);
+    for (size_t i = 0; i < u.order.size(); ++i) {
+      const int c = u.class_of[u.order[i]];
+      if (cls_count_[c] == 0) cls_start_[c] = (int)i;
+      cls_count_[c]++;
+    }
+    std::vector<int> pb(u.order), pc(u.order.size());
+    for (size_t i = 0; i < u.order.size(); ++i) pc[i] = u.box_of[u.order[i]];
+    if (int rc = put_i(proj_part_, pb, err)) return rc;
+    if (int rc = put_i(proj_box_, pc, err)) return rc;
+    if (ntl_ > 0) {
+      const int M2 = M2_;
+      std::vector<float> Ap((size_t)nc_ * 2 * M2 * nf, 0.f), Ar((size_t)nc_ * nf * 2 * M2, 0.f);
+      for (int c = 0; c < nc_; ++c) {
+        const cd* R = u.Rm[c].data();  // [j][mc]
+        const cd* Q = u.Qm[c].data();  // [mc][j]
+        std::vector<float> a((size_t)2 * M2 * nf, 0.f), b((size_t)nf * 2 * M2, 0.f);
+        for (int mc = 0; mc < M2; ++mc)
+          for (int j = 0; j < n; ++j) {
+            block2(a, nf, 2 * mc, 2 * j, R[(size_t)j * M2 + mc]);
+            block2(b, 2 * M2, 2 * j, 2 * mc, Q[(size_t)mc * n + j]);
+          }
+        std::copy(a.begin(), a.end(), Ap.begin() + (size_t)c * a.size());
+        std::copy(b.begin(), b.end(), Ar.begin() + (size_t)c * b.size());
+      }
+      if (int rc = put_f(A_proj_, Ap)) return rc;
+      if (int rc = put_f(A_recv_, Ar)) return rc;
+    }
+    // near blocks: one matrix per offset shared by all particles?
+    std::vector<int> sl(9, -1);
+    bool uniform = true;
+    for (int p = 0; p < P_ && uniform; ++p)
+      for (int o = 0; o < 9; ++o) {
+        if (u.near_nbr[(size_t)p * 9 + o] < 0) continue;
+        const int sv = u.near_slot[(size_t)p * 9 + o];
+        if (sl[o] == -1) sl[o] = sv;
+        else if (sl[o] != sv) uniform = false;
+      }
+    near_uniform_ = uniform;
+    if (uniform) {
+      const size_t lda = (size_t)9 * nf;
+      std::vector<float> An((size_t)nf * lda, 0.f);
+      for (int o = 0; o < 9; ++o) {
+        if (sl[o] < 0) continue;
+        const cd* Zt = u.near_mats[sl[o]].data();  // transposed: [k][j] = Z[j][k]
+        for (int j = 0; j < n; ++j)
+          for (int k = 0; k < n; ++k) block2(An, lda, 2 * j, (size_t)o * nf + 2 * k, Zt[(size_t)k * n + j]);
+      }
+      if (int rc = put_f(A_near_, An)) return rc;
+      std::vector<int> iota(P_);
+      for (int p = 0; p < P_; ++p) iota[p] = p;
+      if (int rc = put_i(iota_, iota, err)) return rc;
+    }
+    return 0;
+  }
+
+  template <int RT, int CT>
+  void gemm(int M, int ncols, int nseg, int kseg, const float* A, int lda, const float* B, int ldb, const int* bcol,
+            float* C, int ldc, const int* ccol, int acc, size_t sB, size_t sC, int R, hipStream_t st) {
+    dim3 grid((M + 16 * RT - 1) / (16 * RT), (ncols + 16 * CT - 1) / (16 * CT), R);
+    hipLaunchKernelGGL((k_gemm_stream<RT, CT>), grid, dim3(kBlock), 0, st, M, ncols, nseg, kseg, A, lda, B, ldb,
+                       bcol, C, ldc, ccol, acc, sB, sC);
   }
 
   int ensure(int R, std::string& err) {
@@ -812,8 +1060,15 @@ class EngineT final : public Engine {
     if (parts & 1) {
       begin("near", cb * ((double)2 * R * P_ * n_ + (double)nslots_ * n_ * n_),
                        8.0 * R * nnear_ * (double)n_ * n_);
-      launch_near(x, y, R, near_mats_.template as<CT>(), near_nbr_.template as<int>(), near_slot_.template as<int>(),
-                  near_tile_slot_.template as<int>(), 9, st);
+      if (mfma_ && near_uniform_) {
+        const int nf = 2 * n_;
+        gemm<4, 1>(nf, P_, 9, nf, A_near_.template as<float>(), 9 * nf, reinterpret_cast<const float*>(x), nf,
+                    near_nbr_.template as<int>(), reinterpret_cast<float*>(y), nf, iota_.template as<int>(), 0,
+                    (size_t)P_ * nf, (size_t)P_ * nf, R, st);
+      } else {
+        launch_near(x, y, R, near_mats_.template as<CT>(), near_nbr_.template as<int>(),
+                    near_slot_.template as<int>(), near_tile_slot_.template as<int>(), 9, st);
+      }
       end(st);
     } else {
       const size_t cnt = (size_t)R * P_ * n_;
@@ -827,10 +1082,21 @@ class EngineT final : public Engine {
         size_t sh = (size_t)kTP * n_ * sizeof(CT);
         begin("project", cb * ((double)R * P_ * n_ + (double)R * P_ * M2_ + (double)nc_ * n_ * M2_),
                          8.0 * R * P_ * (double)n_ * M2_);
-        hipLaunchKernelGGL((k_project<T, kTP>), grid, dim3(kProjBlock), sh, st, n_, P_, M2_, nb0, x, L0.S.template as<CT>(),
+        if (mfma_) {
+          const int nf = 2 * n_;
+          for (int c = 0; c < nc_; ++c)
+            if (cls_count_[c] > 0)
+              gemm<4, 2>(2 * M2_, cls_count_[c], 1, nf, A_proj_.template as<float>() + (size_t)c * 2 * M2_ * nf, nf,
+                          reinterpret_cast<const float*>(x), nf, proj_part_.template as<int>() + cls_start_[c],
+                          reinterpret_cast<float*>(L0.S.template as<CT>()), 2 * M2_,
+                          proj_box_.template as<int>() + cls_start_[c], 0, (size_t)P_ * nf, (size_t)nb0 * 2 * M2_, R,
+                          st);
+        } else {
+          hipLaunchKernelGGL((k_project<T, kTP>), grid, dim3(kProjBlock), sh, st, n_, P_, M2_, nb0, x, L0.S.template as<CT>(),
                            Rm_.template as<CT>(), rm_off_.template as<int>(), order_.template as<int>(),
                            tile_start_.template as<int>(), tile_count_.template as<int>(),
                            tile_class_.template as<int>(), box_of_.template as<int>());
+              }
         end(st);
       }
       for (int l = 1; l < ntl_; ++l) {
@@ -874,10 +1140,21 @@ class EngineT final : public Engine {
         size_t sh = 0;
         begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
                          8.0 * R * P_ * (double)n_ * M2_);
-        hipLaunchKernelGGL((k_receive<T, kTP>), grid, blk, sh, st, n_, P_, M2_, nb0, y, L0.G.template as<CT>(),
+        if (mfma_) {
+          const int nf = 2 * n_;
+          for (int c = 0; c < nc_; ++c)
+            if (cls_count_[c] > 0)
+              gemm<4, 1>(nf, cls_count_[c], 1, 2 * M2_, A_recv_.template as<float>() + (size_t)c * nf * 2 * M2_,
+                          2 * M2_, reinterpret_cast<const float*>(L0.G.template as<CT>()), 2 * M2_,
+                          proj_box_.template as<int>() + cls_start_[c], reinterpret_cast<float*>(y), nf,
+                          proj_part_.template as<int>() + cls_start_[c], 1, (size_t)nb0 * 2 * M2_, (size_t)P_ * nf,
+                          R, st);
+        } else {
+          hipLaunchKernelGGL((k_receive<T, kTP>), grid, blk, sh, st, n_, P_, M2_, nb0, y, L0.G.template as<CT>(),
                            Qm_.template as<CT>(), qm_off_.template as<int>(), order_.template as<int>(),
                            tile_start_.template as<int>(), tile_count_.template as<int>(),
                            tile_class_.template as<int>(), box_of_.template as<int>());
+              }
         end(st);
       }
     }
@@ -1085,6 +1362,9 @@ class EngineT final : public Engine {
   DevMem box_of_, class_of_, order_, tile_start_, tile_count_, tile_class_;
   DevMem Rm_, Qm_, rm_off_, qm_off_;
   DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;
+  bool mfma_ = false, near_uniform_ = false;
+  DevMem A_proj_, A_recv_, A_near_, proj_part_, proj_box_, iota_;
+  std::vector<int> cls_start_, cls_count_;
   std::vector<V3> centers_;
   int nslots_ = 0;
   long long nnear_ = 0;
