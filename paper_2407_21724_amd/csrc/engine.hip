@@ -409,90 +409,122 @@ __global__ __launch_bounds__(kBlock) void k_receive(int n, int P, int M2, int nb
 }
 
 // -------------------------------------------------------------- aggregate --
+// i / d for 0 <= i < 2^20 by a float reciprocal: (i + 0.5) / d is at least
+// 0.5/d away from an integer and the rounding error stays below that.
+__device__ __forceinline__ int fdiv(int i, float inv_d) { return (int)(((float)i + 0.5f) * inv_d); }
+
 // S_p[r][P][c][s] = sum over children q: phase_q(s) * (Phi Theta S_child)(s).
-// Block = (parent box, component) x strip of ts parent rows x RHS; each
-// thread owns up to VPT outputs of the strip (ts * np_p <= 256 * VPT) and
-// accumulates the four children in registers.  tmp: theta-interpolated
-// child rows [ts][np_c] in LDS.
+// Block = (parent box, component) x strip of ts parent rows x RHS.  The
+// strip's stencil tables and the needed rows [crow_lo, crow_hi] of all four
+// children (contiguous in each child pattern) are staged in LDS at once;
+// the theta pass writes tmp [4][ts][np_c]; each thread owns up to kAggVPT
+// outputs of the strip and sums the four children in registers.
 constexpr int kAggVPT = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_aggregate(
-    int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts,
+    int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int crows_max,
     const C2<T>* __restrict__ Sc, C2<T>* __restrict__ Sp, const int* __restrict__ th_row,
     const T* __restrict__ th_w, const int* __restrict__ th_flip, const int* __restrict__ ph_col,
-    const T* __restrict__ ph_w, const C2<T>* __restrict__ phase) {
+    const T* __restrict__ ph_w, const C2<T>* __restrict__ phase, const int* __restrict__ strip_crow) {
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* tmp = reinterpret_cast<C2<T>*>(smem_raw);
+  C2<T>* cbuf = reinterpret_cast<C2<T>*>(smem_raw);  // [4][crows_max][npc]
+  C2<T>* tmp = cbuf + (size_t)4 * crows_max * npc;    // [4][ts][npc]
+  T* thw = reinterpret_cast<T*>(tmp + (size_t)4 * ts * npc);
+  T* phw = thw + ts * order;
+  int* thr = reinterpret_cast<int*>(phw + npp * order);  // child row relative to crow_lo; -1-row if flipped
+  int* phc = thr + ts * order;
   const int pb = blockIdx.x >> 1, comp = blockIdx.x & 1;
-  const int r0 = blockIdx.y * ts, r = blockIdx.z;
+  const int strip = blockIdx.y, r = blockIdx.z;
+  const int r0 = strip * ts;
   const int nrow = min(ts, ntp - r0);
+  const int clo = strip_crow[2 * strip], crows = strip_crow[2 * strip + 1] - clo + 1;
   const int PI = pb % nxp, PJ = pb / nxp;
   const int Kc = ntc * npc, Kp = ntp * npp;
   const int nbc = nxc * nyc, nbp = nxp * nyp;
   const int half = npc / 2;
-  const int nout = nrow * npp;
-  C2<T> acc[kAggVPT];
-#pragma unroll
-  for (int v = 0; v < kAggVPT; ++v) acc[v] = {0, 0};
-  for (int q = 0; q < 4; ++q) {
-    const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
-    if (ci >= nxc || cj >= nyc) continue;
-    const C2<T>* __restrict__ src = Sc + (((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc;
-    __syncthreads();
-    for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
-      const int row = i / npc, col = i - row * npc;
-      const int it = r0 + row;
-      C2<T> v{0, 0};
-      for (int a = 0; a < order; ++a) {
-        const int e = it * order + a;
-        const int cc = th_flip[e] ? (col + half) % npc : col;
-        const C2<T> s = src[th_row[e] * npc + cc];
-        const T w = th_w[e];
-        v.x += w * s.x;
-        v.y += w * s.y;
-      }
-      tmp[i] = v;
-    }
-    __syncthreads();
-    const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)r0 * npp;
-#pragma unroll
-    for (int vv = 0; vv < kAggVPT; ++vv) {
-      const int i = threadIdx.x + vv * kBlock;
-      if (i >= nout) continue;
-      const int row = i / npp, ip = i - row * npp;
-      C2<T> s{0, 0};
-      for (int b = 0; b < order; ++b) {
-        const T w = ph_w[ip * order + b];
-        const C2<T> t = tmp[row * npc + ph_col[ip * order + b]];
-        s.x += w * t.x;
-        s.y += w * t.y;
-      }
-      cfma(acc[vv], ph[i], s);
-    }
+  const float inv_npc = 1.0f / npc, inv_npp = 1.0f / npp, inv_cs = 1.0f / (crows * npc),
+              inv_ts = 1.0f / (nrow * npc);
+  for (int i = threadIdx.x; i < nrow * order; i += kBlock) {
+    const int e = r0 * order + i;
+    thw[i] = th_w[e];
+    thr[i] = th_flip[e] ? -1 - (th_row[e] - clo) : th_row[e] - clo;
   }
+  for (int i = threadIdx.x; i < npp * order; i += kBlock) {
+    phw[i] = ph_w[i];
+    phc[i] = ph_col[i];
+  }
+  const int cs = crows * npc;
+  for (int i = threadIdx.x; i < 4 * cs; i += kBlock) {
+    const int q = fdiv(i, inv_cs), j = i - q * cs;
+    const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
+    cbuf[q * crows_max * npc + j] =
+        (ci < nxc && cj < nyc) ? Sc[(((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc + (size_t)clo * npc + j]
+                               : C2<T>{0, 0};
+  }
+  __syncthreads();
+  const int tsz = nrow * npc;
+  for (int i = threadIdx.x; i < 4 * tsz; i += kBlock) {
+    const int q = fdiv(i, inv_ts), j = i - q * tsz;
+    const int row = fdiv(j, inv_npc), col = j - row * npc;
+    const int colf = col + half < npc ? col + half : col + half - npc;
+    const C2<T>* cq = cbuf + q * crows_max * npc;
+    C2<T> v{0, 0};
+    for (int a = 0; a < order; ++a) {
+      const int rr = thr[row * order + a];
+      const T w = thw[row * order + a];
+      const C2<T> sv = rr >= 0 ? cq[rr * npc + col] : cq[(-1 - rr) * npc + colf];
+      v.x += w * sv.x;
+      v.y += w * sv.y;
+    }
+    tmp[q * ts * npc + j] = v;
+  }
+  __syncthreads();
+  const int nout = nrow * npp;
   C2<T>* __restrict__ dst = Sp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)r0 * npp;
 #pragma unroll
   for (int vv = 0; vv < kAggVPT; ++vv) {
     const int i = threadIdx.x + vv * kBlock;
-    if (i < nout) dst[i] = acc[vv];
+    if (i >= nout) continue;
+    const int row = fdiv(i, inv_npp), ip = i - row * npp;
+    C2<T> acc{0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      C2<T> sv{0, 0};
+      const C2<T>* tq = tmp + q * ts * npc + row * npc;
+      for (int b = 0; b < order; ++b) {
+        const T w = phw[ip * order + b];
+        const C2<T> t = tq[phc[ip * order + b]];
+        sv.x += w * t.x;
+        sv.y += w * t.y;
+      }
+      cfma(acc, phase[(size_t)q * Kp + (size_t)(r0 + row) * npp + ip], sv);
+    }
+    dst[i] = acc;
   }
 }
 
 // ----------------------------------------------------------- disaggregate --
 // G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), as gathers over the
 // transposed stencils.  Block = (child box, component) x strip of ts child
-// rows x RHS.  LDS: the phase-weighted parent rows [plo, phi] ([rows][np_p])
-// and their phi-transposed interpolation ([rows][np_c]).
+// rows x RHS.  LDS: the strip's transposed theta tables, the transposed phi
+// tables, the phase-weighted parent rows [plo, phi] ([rows][np_p]) and their
+// phi-transposed interpolation ([rows][np_c]).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_disaggregate(
     int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int tmax, int pmax,
-    const C2<T>* __restrict__ Gp, C2<T>* __restrict__ Gc, const int* __restrict__ tth_row,
-    const T* __restrict__ tth_w, const int* __restrict__ tth_flip, const int* __restrict__ tth_lo,
-    const int* __restrict__ tth_hi, const int* __restrict__ tph_col, const T* __restrict__ tph_w,
-    const C2<T>* __restrict__ phase) {
+    int prows_max, const C2<T>* __restrict__ Gp, C2<T>* __restrict__ Gc, const int* __restrict__ tth_row,
+    const T* __restrict__ tth_w, const int* __restrict__ tth_flip, const int* __restrict__ strip_prow,
+    const int* __restrict__ tph_col, const T* __restrict__ tph_w, const C2<T>* __restrict__ phase) {
   extern __shared__ unsigned char smem_raw[];
+  C2<T>* par = reinterpret_cast<C2<T>*>(smem_raw);    // [prows_max][npp]
+  C2<T>* tmp = par + (size_t)prows_max * npp;           // [prows_max][npc]
+  T* ttw = reinterpret_cast<T*>(tmp + (size_t)prows_max * npc);
+  T* tpw = ttw + ts * tmax;
+  int* ttr = reinterpret_cast<int*>(tpw + npc * pmax);  // parent row relative to plo; -1-row if flipped
+  int* tpc = ttr + ts * tmax;
   const int cb = blockIdx.x >> 1, comp = blockIdx.x & 1;
-  const int c0 = blockIdx.y * ts, r = blockIdx.z;
+  const int strip = blockIdx.y, r = blockIdx.z;
+  const int c0 = strip * ts;
   const int nrow = min(ts, ntc - c0);
   const int ci = cb % nxc, cj = cb / nxc;
   const int pb = (cj >> 1) * nxp + (ci >> 1);
@@ -500,76 +532,77 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
   const int Kc = ntc * npc, Kp = ntp * npp;
   const int nbc = nxc * nyc, nbp = nxp * nyp;
   const int half = npc / 2;
-  int plo = ntp, phi = -1;
-  for (int rr = c0; rr < c0 + nrow; ++rr) {
-    plo = min(plo, tth_lo[rr]);
-    phi = max(phi, tth_hi[rr]);
+  const int plo = strip_prow[2 * strip], prows = strip_prow[2 * strip + 1] - plo + 1;
+  const float inv_npc = 1.0f / npc;
+  for (int i = threadIdx.x; i < nrow * tmax; i += kBlock) {
+    const int e = c0 * tmax + i;
+    ttw[i] = tth_w[e];
+    ttr[i] = tth_flip[e] ? -1 - (tth_row[e] - plo) : tth_row[e] - plo;
   }
-  const int np_rows = phi - plo + 1;
-  C2<T>* par = reinterpret_cast<C2<T>*>(smem_raw);  // [np_rows][npp]
-  C2<T>* tmp = par + (size_t)np_rows * npp;          // [np_rows][npc]
+  for (int i = threadIdx.x; i < npc * pmax; i += kBlock) {
+    tpw[i] = tph_w[i];
+    tpc[i] = tph_col[i];
+  }
   const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)plo * npp;
   const C2<T>* __restrict__ src = Gp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)plo * npp;
-  for (int i = threadIdx.x; i < np_rows * npp; i += kBlock) par[i] = cmul_conj_a(ph[i], src[i]);
+  for (int i = threadIdx.x; i < prows * npp; i += kBlock) par[i] = cmul_conj_a(ph[i], src[i]);
   __syncthreads();
-  for (int i = threadIdx.x; i < np_rows * npc; i += kBlock) {
-    const int row = i / npc, col = i - row * npc;
+  for (int i = threadIdx.x; i < prows * npc; i += kBlock) {
+    const int row = fdiv(i, inv_npc), col = i - row * npc;
     C2<T> v{0, 0};
     for (int e = 0; e < pmax; ++e) {
-      const T w = tph_w[col * pmax + e];
-      const C2<T> t = par[row * npp + tph_col[col * pmax + e]];
+      const T w = tpw[col * pmax + e];
+      const C2<T> t = par[row * npp + tpc[col * pmax + e]];
       v.x += w * t.x;
       v.y += w * t.y;
     }
     tmp[i] = v;
   }
   __syncthreads();
-  C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc;
+  C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc + (size_t)c0 * npc;
   for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
-    const int row = i / npc, col = i - row * npc;
-    const int it = c0 + row;
+    const int row = fdiv(i, inv_npc), col = i - row * npc;
+    const int colf = col + half < npc ? col + half : col + half - npc;
     C2<T> v{0, 0};
     for (int e = 0; e < tmax; ++e) {
-      const int idx = it * tmax + e;
-      const int cc = tth_flip[idx] ? (col + half) % npc : col;
-      const C2<T> s = tmp[(tth_row[idx] - plo) * npc + cc];
-      const T w = tth_w[idx];
-      v.x += w * s.x;
-      v.y += w * s.y;
+      const int rr = ttr[row * tmax + e];
+      const T w = ttw[row * tmax + e];
+      const C2<T> sv = rr >= 0 ? tmp[rr * npc + col] : tmp[(-1 - rr) * npc + colf];
+      v.x += w * sv.x;
+      v.y += w * sv.y;
     }
-    C2<T> o = dst[it * npc + col];
-    dst[it * npc + col] = {o.x + v.x, o.y + v.y};
+    C2<T> o = dst[i];
+    dst[i] = {o.x + v.x, o.y + v.y};
   }
 }
 
 // -------------------------------------------------------------- translate --
-// G[r][p][c][s] = sum over the interaction list of TL[offset][s] S[r][q][c][s]
+// G[r][p][c][s] = sum over the interaction list of TL[offset][s] S[r][q][c][s].
+// The list of box p (at most 27 (source box, offset) pairs, built on the
+// host) is uniform over the block, so all partner loads are independent.
+constexpr int kMaxIL = 27;
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_translate(int nx, int ny, int K, const C2<T>* __restrict__ S,
-                                                       C2<T>* __restrict__ G, const C2<T>* __restrict__ TL) {
+__global__ __launch_bounds__(kBlock) void k_translate(int nb, int K, const C2<T>* __restrict__ S,
+                                                       C2<T>* __restrict__ G, const C2<T>* __restrict__ TL,
+                                                       const int* __restrict__ il_cnt, const int* __restrict__ il_src,
+                                                       const int* __restrict__ il_off) {
   const int p = blockIdx.x, r = blockIdx.y;
   const int s = blockIdx.z * kBlock + threadIdx.x;
-  if (s < K) {
-    const int I = p % nx, J = p / nx;
-    const int nb = nx * ny;
-    C2<T> g0{0, 0}, g1{0, 0};
-    for (int dy = -3; dy <= 3; ++dy) {
-      const int J2 = J + dy;
-      if (J2 < 0 || J2 >= ny || abs((J2 >> 1) - (J >> 1)) > 1) continue;
-      for (int dx = -3; dx <= 3; ++dx) {
-        if (abs(dx) <= 1 && abs(dy) <= 1) continue;
-        const int I2 = I + dx;
-        if (I2 < 0 || I2 >= nx || abs((I2 >> 1) - (I >> 1)) > 1) continue;
-        const C2<T> t = TL[(size_t)((dy + 3) * 7 + dx + 3) * K + s];
-        const C2<T>* src = S + ((size_t)r * nb + J2 * nx + I2) * 2 * K;
-        cfma(g0, t, src[s]);
-        cfma(g1, t, src[K + s]);
-      }
-    }
-    C2<T>* dst = G + ((size_t)r * nb + p) * 2 * K;
-    dst[s] = g0;
-    dst[K + s] = g1;
+  if (s >= K) return;
+  const int cnt = il_cnt[p];
+  const C2<T>* __restrict__ Sr = S + (size_t)r * nb * 2 * K;
+  C2<T> g0{0, 0}, g1{0, 0};
+#pragma unroll 4
+  for (int e = 0; e < cnt; ++e) {
+    const int q = il_src[p * kMaxIL + e], o = il_off[p * kMaxIL + e];
+    const C2<T> t = TL[(size_t)o * K + s];
+    const C2<T>* src = Sr + (size_t)q * 2 * K;
+    cfma(g0, t, src[s]);
+    cfma(g1, t, src[K + s]);
   }
+  C2<T>* dst = G + ((size_t)r * nb + p) * 2 * K;
+  dst[s] = g0;
+  dst[K + s] = g1;
 }
 
 // -------------------------------------------------------------------- rhs --
@@ -743,11 +776,13 @@ class EngineT final : public Engine {
   struct Lvl {
     int nx, ny, nt, np, K;
     DevMem TL;
+    DevMem il_cnt, il_src, il_off;  // interaction lists
     DevMem S, G;  // pattern buffers, sized for R_alloc
   };
   struct Itp {
-    int order, tmax, pmax, ts_agg, ts_dis;
-    size_t lds_dis;
+    int order, tmax, pmax, ts_agg, ts_dis, crows_max, prows_max;
+    size_t lds_dis, lds_agg;
+    DevMem strip_crow, strip_prow;
     DevMem th_row, th_w, th_flip, ph_col, ph_w, tth_row, tth_w, tth_flip, tth_lo, tth_hi, tph_col, tph_w, phase;
   };
 
@@ -772,6 +807,26 @@ class EngineT final : public Engine {
       L.np = g.np;
       L.K = g.K;
       if (int rc = put_c(L.TL, tr.TL[l], err)) return rc;
+      // interaction lists: children of the parent's neighbours that are not
+      // neighbours themselves
+      std::vector<int> cnt(L.nx * L.ny, 0), src((size_t)L.nx * L.ny * kMaxIL, 0), off((size_t)L.nx * L.ny * kMaxIL, 0);
+      for (int J = 0; J < L.ny; ++J)
+        for (int I = 0; I < L.nx; ++I) {
+          const int p = J * L.nx + I;
+          for (int dy = -3; dy <= 3; ++dy)
+            for (int dx = -3; dx <= 3; ++dx) {
+              if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+              const int I2 = I + dx, J2 = J + dy;
+              if (I2 < 0 || J2 < 0 || I2 >= L.nx || J2 >= L.ny) continue;
+              if (std::abs((I2 >> 1) - (I >> 1)) > 1 || std::abs((J2 >> 1) - (J >> 1)) > 1) continue;
+              src[(size_t)p * kMaxIL + cnt[p]] = J2 * L.nx + I2;
+              off[(size_t)p * kMaxIL + cnt[p]] = (dy + 3) * 7 + (dx + 3);
+              cnt[p]++;
+            }
+        }
+      if (int rc = put_i(L.il_cnt, cnt, err)) return rc;
+      if (int rc = put_i(L.il_src, src, err)) return rc;
+      if (int rc = put_i(L.il_off, off, err)) return rc;
     }
     for (int l = 1; l < ntl_; ++l) {
       const InterpTables& T0 = tr.it[l];
@@ -792,38 +847,80 @@ class EngineT final : public Engine {
       if (int rc = put_i(I.tph_col, T0.tph_col, err)) return rc;
       if (int rc = put_r(I.tph_w, T0.tph_w, err)) return rc;
       if (int rc = put_c(I.phase, T0.phase, err)) return rc;
-      // aggregation strips: each thread owns at most kAggVPT outputs
+      // aggregation strips: each thread owns at most kAggVPT outputs; the
+      // strip's child rows and stencil tables are staged in LDS
       const Lvl &C = lv_[l - 1], &Pp = lv_[l];
       if (Pp.np > kBlock * kAggVPT) {
         err = "aggregation: more than " + std::to_string(kBlock * kAggVPT) + " phi samples per row at level " +
               std::to_string(l);
         return -1;
       }
-      I.ts_agg = std::max(1, std::min(Pp.nt, (kBlock * kAggVPT) / Pp.np));
-      if ((size_t)I.ts_agg * C.np * sizeof(CT) > kLdsBudget) I.ts_agg = std::max<int>(1, kLdsBudget / (C.np * sizeof(CT)));
-      // disaggregation strips: at most kDisRows child rows, and the staged
-      // parent rows ([rows][np_p + np_c]) within the LDS budget
-      auto worst_rows = [&](int ts) {
-        int worst = 0;
-        for (int c0 = 0; c0 < C.nt; c0 += ts) {
+      const int order = T0.order;
+      auto agg_plan = [&](int ts, std::vector<int>& rng, int& cmax) {
+        rng.clear();
+        cmax = 0;
+        for (int r0 = 0; r0 < Pp.nt; r0 += ts) {
+          int lo = C.nt, hi = -1;
+          for (int it = r0; it < std::min(Pp.nt, r0 + ts); ++it)
+            for (int a2 = 0; a2 < order; ++a2) {
+              lo = std::min(lo, T0.th_row[(size_t)it * order + a2]);
+              hi = std::max(hi, T0.th_row[(size_t)it * order + a2]);
+            }
+          rng.push_back(lo);
+          rng.push_back(hi);
+          cmax = std::max(cmax, hi - lo + 1);
+        }
+        return (size_t)4 * (cmax + ts) * C.np * sizeof(CT) + (size_t)ts * order * (sizeof(T) + 4) +
+               (size_t)Pp.np * order * (sizeof(T) + 4);
+      };
+      // strip height: bounded by the per-thread outputs; split further only
+      // while the grid has fewer than kMinBlocks blocks
+      int ts = std::max(1, std::min(Pp.nt, (kBlock * kAggVPT) / Pp.np));
+      while (ts > 1 && (size_t)Pp.nx * Pp.ny * 2 * ((Pp.nt + ts - 1) / ts) < kMinBlocks) ts = (ts + 1) / 2;
+      std::vector<int> rng;
+      int cmax = 0;
+      size_t lds = agg_plan(ts, rng, cmax);
+      while (ts > 1 && lds > kLdsBudget) lds = agg_plan(--ts, rng, cmax);
+      if (lds > kLdsBudget) {
+        err = "aggregation tile exceeds the LDS budget at level " + std::to_string(l);
+        return -1;
+      }
+      I.ts_agg = ts;
+      I.crows_max = cmax;
+      I.lds_agg = lds;
+      if (int rc = put_i(I.strip_crow, rng, err)) return rc;
+      // disaggregation strips: at most kDisRows child rows; the staged parent
+      // rows ([rows][np_p + np_c]) and tables within the LDS budget
+      auto dis_plan = [&](int tsd, std::vector<int>& prng, int& pmax_rows) {
+        prng.clear();
+        pmax_rows = 0;
+        for (int c0 = 0; c0 < C.nt; c0 += tsd) {
           int lo = Pp.nt, hi = -1;
-          for (int rr = c0; rr < std::min(C.nt, c0 + ts); ++rr) {
+          for (int rr = c0; rr < std::min(C.nt, c0 + tsd); ++rr) {
             lo = std::min(lo, T0.tth_lo[rr]);
             hi = std::max(hi, T0.tth_hi[rr]);
           }
-          worst = std::max(worst, hi - lo + 1);
+          prng.push_back(lo);
+          prng.push_back(hi);
+          pmax_rows = std::max(pmax_rows, hi - lo + 1);
         }
-        return worst;
+        return (size_t)pmax_rows * (Pp.np + C.np) * sizeof(CT) + (size_t)tsd * T0.tmax * (sizeof(T) + 4) +
+               (size_t)C.np * T0.pmax * (sizeof(T) + 4);
       };
-      const size_t row_bytes = (size_t)(Pp.np + C.np) * sizeof(CT);
-      int ts = std::min(C.nt, kDisRows);
-      while (ts > 1 && (size_t)worst_rows(ts) * row_bytes > kLdsBudget) --ts;
-      if ((size_t)worst_rows(ts) * row_bytes > kLdsBudget) {
+      int tsd = C.nt;
+      while (tsd > 1 && (size_t)C.nx * C.ny * 2 * ((C.nt + tsd - 1) / tsd) < kMinBlocks) tsd = (tsd + 1) / 2;
+      std::vector<int> prng;
+      int pmr = 0;
+      size_t ldsd = dis_plan(tsd, prng, pmr);
+      while (tsd > 1 && ldsd > kLdsBudget) ldsd = dis_plan(--tsd, prng, pmr);
+      if (ldsd > kLdsBudget) {
         err = "disaggregation tile exceeds the LDS budget at level " + std::to_string(l);
         return -1;
       }
-      I.ts_dis = ts;
-      I.lds_dis = (size_t)worst_rows(ts) * row_bytes;
+      I.ts_dis = tsd;
+      I.prows_max = pmr;
+      I.lds_dis = ldsd;
+      if (int rc = put_i(I.strip_prow, prng, err)) return rc;
     }
     // leaf data
     nx0_ = u.nx0;
@@ -1103,13 +1200,14 @@ class EngineT final : public Engine {
         const Lvl &C = lv_[l - 1], &Pp = lv_[l];
         const Itp& I = it_[l];
         dim3 grid(Pp.nx * Pp.ny * 2, (Pp.nt + I.ts_agg - 1) / I.ts_agg, R);
-        size_t sh = (size_t)I.ts_agg * C.np * sizeof(CT);
+        size_t sh = I.lds_agg;
         begin("aggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
               2.0 * R * (double)C.nx * C.ny * 2 * (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K));
         hipLaunchKernelGGL(k_aggregate<T>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
-                           Pp.np, I.ts_agg, C.S.template as<CT>(), Pp.S.template as<CT>(), I.th_row.template as<int>(),
-                           I.th_w.template as<T>(), I.th_flip.template as<int>(), I.ph_col.template as<int>(),
-                           I.ph_w.template as<T>(), I.phase.template as<CT>());
+                           Pp.np, I.ts_agg, I.crows_max, C.S.template as<CT>(), Pp.S.template as<CT>(),
+                           I.th_row.template as<int>(), I.th_w.template as<T>(), I.th_flip.template as<int>(),
+                           I.ph_col.template as<int>(), I.ph_w.template as<T>(), I.phase.template as<CT>(),
+                           I.strip_crow.template as<int>());
         end(st);
       }
       for (int l = ntl_ - 1; l >= 0; --l) {
@@ -1117,8 +1215,9 @@ class EngineT final : public Engine {
         dim3 grid(L.nx * L.ny, R, (L.K + kBlock - 1) / kBlock);
         begin("translate_l" + std::to_string(l), cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K),
                          16.0 * R * (double)pairs_[l] * L.K);
-        hipLaunchKernelGGL(k_translate<T>, grid, blk, 0, st, L.nx, L.ny, L.K, L.S.template as<CT>(),
-                           L.G.template as<CT>(), L.TL.template as<CT>());
+        hipLaunchKernelGGL(k_translate<T>, grid, blk, 0, st, L.nx * L.ny, L.K, L.S.template as<CT>(),
+                           L.G.template as<CT>(), L.TL.template as<CT>(), L.il_cnt.template as<int>(),
+                           L.il_src.template as<int>(), L.il_off.template as<int>());
         end(st);
         if (l + 1 < ntl_) {
           const Lvl& Pp = lv_[l + 1];
@@ -1128,10 +1227,10 @@ class EngineT final : public Engine {
           begin("disaggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
                 2.0 * R * (double)L.nx * L.ny * 2 * (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K));
           hipLaunchKernelGGL(k_disaggregate<T>, g2, blk, sh, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.ny, Pp.nt, Pp.np,
-                             I.ts_dis, I.tmax, I.pmax, Pp.G.template as<CT>(), L.G.template as<CT>(),
+                             I.ts_dis, I.tmax, I.pmax, I.prows_max, Pp.G.template as<CT>(), L.G.template as<CT>(),
                              I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
-                             I.tth_lo.template as<int>(), I.tth_hi.template as<int>(), I.tph_col.template as<int>(),
-                             I.tph_w.template as<T>(), I.phase.template as<CT>());
+                             I.strip_prow.template as<int>(), I.tph_col.template as<int>(), I.tph_w.template as<T>(),
+                             I.phase.template as<CT>());
           end(st);
         }
       }
@@ -1246,7 +1345,7 @@ class EngineT final : public Engine {
   static constexpr int kTP = sizeof(T) == 4 ? 16 : 8;
   static constexpr int kTPN = 16;
   static constexpr size_t kLdsBudget = 48 * 1024;
-  static constexpr int kDisRows = 8;
+  static constexpr size_t kMinBlocks = 1024;
 
   template <typename U>
   static int put_raw(DevMem& d, const U* h, size_t count, std::string& err) {
