@@ -106,6 +106,8 @@ typedef struct {
   double true_rel_res;   /* ||V - Z x|| / ||V|| recomputed at exit         */
   double time_s;         /* wall time of the solve                         */
   int32_t converged;     /* 1 if true_rel_res <= rtol                      */
+  int32_t reorth;        /* iterations that took a second Gram-Schmidt pass */
+  int32_t cycles;        /* restart cycles                                  */
 } mlfma_solve_stats;
 
 /* Fill *tp with the defaults: leaf 0.5, L_leaf 11, rule 0, digits 3,
@@ -180,11 +182,15 @@ int mlfma_matvec_parts(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R
 int mlfma_precondition(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream);
 
 #define MLFMA_SOLVE_USE_X0 1
+#define MLFMA_SOLVE_ALWAYS_REORTH 2
 
 /* Right-preconditioned restarted GMRES (Sec. V stage v; preconditioner
- * blockdiag(Z_s)) for R right-hand sides solved in lock-step.  Arnoldi
- * (classical Gram-Schmidt, applied twice), Givens rotations and the Krylov
- * basis are FP64; the matrix-vector products run in the context precision.
+ * blockdiag(Z_s)) for R right-hand sides solved in lock-step.  Arnoldi is
+ * classical Gram-Schmidt with a second pass where the first removed more
+ * than half of |w|^2 (Daniel-Gragg-Kaufman-Stewart test), or always with
+ * flags & MLFMA_SOLVE_ALWAYS_REORTH.  Arnoldi, Givens rotations and the
+ * Krylov basis are FP64; the matrix-vector products run in the context
+ * precision.
  *  b_dev, x_dev: device [R][P][2][N] in the context precision.  x_dev holds
  *  the initial guess if flags & MLFMA_SOLVE_USE_X0 (else zero is used) and
  *  the best iterate on return.  rtol: relative tolerance on the true

@@ -501,7 +501,8 @@ int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R,
     if (int rc = do_prepare(ctx)) return rc;
     std::vector<GmresResult> res;
     std::string err;
-    int rc = ctx->eng->gmres(b_dev, x_dev, R, rtol, max_iter, restart, (flags & MLFMA_SOLVE_USE_X0) != 0, res, stream, err);
+    int rc = ctx->eng->gmres(b_dev, x_dev, R, rtol, max_iter, restart, (flags & MLFMA_SOLVE_USE_X0) != 0,
+                              (flags & MLFMA_SOLVE_ALWAYS_REORTH) != 0, res, stream, err);
     if (rc) return fail(ctx, rc, err);
     bool all = true;
     for (int r = 0; r < R; ++r) {
@@ -512,6 +513,8 @@ int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R,
         stats[r].true_rel_res = res[r].true_rel_res;
         stats[r].time_s = res[r].time_s;
         stats[r].converged = res[r].converged;
+        stats[r].reorth = res[r].reorth;
+        stats[r].cycles = res[r].cycles;
       }
     }
     if (!all) {

@@ -634,78 +634,169 @@ __global__ __launch_bounds__(kBlock) void k_from_z(const Z* __restrict__ a, C2<T
     b[i] = {(T)a[i].x, (T)a[i].y};
 }
 
-// partial[r][blk][i] = sum over this block's chunk of conj(V[i][r][k]) w[r][k]
-// for i < nv; also (i = nv) the squared norm of w when want_norm.
-__global__ __launch_bounds__(kBlock) void k_multidot(int nv, int ld_r, size_t Nt, size_t vstride, const Z* __restrict__ V,
-                                                      const Z* __restrict__ w, Z* __restrict__ partial, int nblk) {
-  __shared__ Z red[kBlock];
-  const int r = blockIdx.y, blk = blockIdx.x;
-  const size_t chunk = (Nt + nblk - 1) / nblk;
-  const size_t k0 = blk * chunk, k1 = min(Nt, k0 + chunk);
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+constexpr int kDotChunk = 512;      // vector elements per block and sweep (8 per lane)
+constexpr int kDotMaxBlocks = 512;
+
+// Block partial sums of the inner products conj(V_i) . w (slots i < nv) and,
+// when want_norm, of |w|^2 (slot nv), in one sweep over the basis.  The four
+// waves of a block share one stretch of w and take the slots round-robin;
+// partial[((r * ldp) + slot) * gridDim.x + blockIdx.x].  RHS r is skipped
+// where gate[r] == 0.
+__global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t Nt, size_t vstride,
+                                                  const Z* __restrict__ V, const Z* __restrict__ w,
+                                                  Z* __restrict__ partial, int ldp, const int* __restrict__ gate) {
+  const int r = blockIdx.y;
+  if (gate && !gate[r]) return;
+  const int nblk = gridDim.x, blk = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Z* wr = w + (size_t)r * Nt;
-  for (int i = 0; i < nv; ++i) {
-    const Z* vi = V + i * vstride + (size_t)r * Nt;
-    Z acc{0, 0};
-    for (size_t k = k0 + threadIdx.x; k < k1; k += kBlock) cfma_conj_a(acc, vi[k], wr[k]);
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) {
-        red[threadIdx.x].x += red[threadIdx.x + s].x;
-        red[threadIdx.x].y += red[threadIdx.x + s].y;
+  for (int s = wave; s < nv + want_norm; s += kBlock / 64) {
+    const Z* vr = s == nv ? wr : V + (size_t)s * vstride + (size_t)r * Nt;
+    double ax = 0, ay = 0;
+    for (size_t c0 = (size_t)blk * kDotChunk; c0 < Nt; c0 += (size_t)nblk * kDotChunk) {
+#pragma unroll
+      for (int e = 0; e < kDotChunk / 64; ++e) {
+        const size_t k = c0 + (size_t)e * 64 + lane;
+        if (k < Nt) {
+          const Z a = vr[k], b = wr[k];
+          ax += a.x * b.x + a.y * b.y;
+          ay += a.x * b.y - a.y * b.x;
+        }
       }
-      __syncthreads();
     }
-    if (threadIdx.x == 0) partial[((size_t)r * nblk + blk) * ld_r + i] = red[0];
-    __syncthreads();
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (lane == 0) partial[((size_t)r * ldp + s) * nblk + blk] = Z{ax, ay};
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_partials(int nv, int ld_r, int nblk, const Z* __restrict__ partial,
-                                                             Z* __restrict__ out) {
-  const int r = blockIdx.x;
-  for (int i = threadIdx.x; i < nv; i += kBlock) {
-    Z acc{0, 0};
-    for (int b = 0; b < nblk; ++b) {
-      const Z v = partial[((size_t)r * nblk + b) * ld_r + i];
-      acc.x += v.x;
-      acc.y += v.y;
+// out[r * ldo + s] = sum over b < nblk of partial[((r * ldp) + s) * nblk + b]
+// (grid: slots x R), in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_reduce(int nblk, const Z* __restrict__ partial, int ldp,
+                                                    Z* __restrict__ out, int ldo, const int* __restrict__ gate) {
+  const int s = blockIdx.x, r = blockIdx.y;
+  if (gate && !gate[r]) return;
+  __shared__ double red[2][kBlock / 64];
+  const Z* p = partial + ((size_t)r * ldp + s) * nblk;
+  double ax = 0, ay = 0;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    ax += p[b].x;
+    ay += p[b].y;
+  }
+  ax = wave_sum(ax);
+  ay = wave_sum(ay);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    red[0][wave] = ax;
+    red[1][wave] = ay;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Z o{0, 0};
+    for (int q = 0; q < kBlock / 64; ++q) {
+      o.x += red[0][q];
+      o.y += red[1][q];
     }
-    out[(size_t)r * ld_r + i] = acc;
+    out[(size_t)r * ldo + s] = o;
   }
 }
 
-// w[r] -= sum_{i<nv} V[i][r] h[r][i]
-__global__ __launch_bounds__(kBlock) void k_subtract_proj(int nv, int ld_r, size_t Nt, size_t vstride, const Z* __restrict__ V,
-                                                           const Z* __restrict__ h, Z* __restrict__ w) {
+// w[r] -= sum_{i<nv} V_i[r] c[r][i]; block partial sums of |w[r]|^2 after the
+// update go to partial[r * gridDim.x + blockIdx.x] (imaginary part 0).
+__global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, size_t vstride, const Z* __restrict__ V,
+                                                           const Z* __restrict__ c, int ldc, Z* __restrict__ w,
+                                                           Z* __restrict__ partial, const int* __restrict__ gate) {
   const int r = blockIdx.y;
+  if (gate && !gate[r]) return;
+  __shared__ double red[kBlock / 64];
+  const Z* cr = c + (size_t)r * ldc;
+  Z* wr = w + (size_t)r * Nt;
+  const Z* Vr = V + (size_t)r * Nt;
+  double s2 = 0;
   for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
-    Z acc = w[(size_t)r * Nt + k];
-    for (int i = 0; i < nv; ++i) {
-      const Z v = V[i * vstride + (size_t)r * Nt + k];
-      const Z c = h[(size_t)r * ld_r + i];
-      acc.x -= v.x * c.x - v.y * c.y;
-      acc.y -= v.x * c.y + v.y * c.x;
+    Z acc = wr[k];
+    int i = 0;
+    for (; i + 4 <= nv; i += 4) {
+      Z v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = Vr[(size_t)(i + u) * vstride + k];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const Z q = cr[i + u];
+        acc.x -= v[u].x * q.x - v[u].y * q.y;
+        acc.y -= v[u].x * q.y + v[u].y * q.x;
+      }
     }
-    w[(size_t)r * Nt + k] = acc;
+    for (; i < nv; ++i) {
+      const Z v = Vr[(size_t)i * vstride + k], q = cr[i];
+      acc.x -= v.x * q.x - v.y * q.y;
+      acc.y -= v.x * q.y + v.y * q.x;
+    }
+    wr[k] = acc;
+    s2 += acc.x * acc.x + acc.y * acc.y;
+  }
+  s2 = wave_sum(s2);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o = 0;
+    for (int q = 0; q < kBlock / 64; ++q) o += red[q];
+    partial[(size_t)r * gridDim.x + blockIdx.x] = Z{o, 0};
   }
 }
 
-// out[r] = a[r] * s[r] (+ out[r] if accumulate); s is a per-RHS complex scalar
-__global__ __launch_bounds__(kBlock) void k_scale(size_t Nt, const Z* __restrict__ a, const Z* __restrict__ s,
-                                                   int ld_s, Z* __restrict__ out, int accumulate) {
+// Selective reorthogonalisation (Daniel-Gragg-Kaufman-Stewart): a second
+// Gram-Schmidt pass is taken where the first removed more than half of
+// |w|^2, i.e. |w'| < |w| / sqrt(2); always when `always`.
+__global__ void k_dgks_gate(int R, const Z* __restrict__ h1, int ld, int nv, const Z* __restrict__ n1,
+                            int* __restrict__ gate, int always) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  gate[r] = (always || n1[r].x < 0.5 * h1[(size_t)r * ld + nv].x) ? 1 : 0;
+}
+
+// Hessenberg column: col[r][i] = h1 + h2 (i < nv), col[r][nv] = |w| after the
+// last pass, col[r][nv+1] = gate; scale[r] = 1 / |w| (0 for a zero vector).
+__global__ __launch_bounds__(kBlock) void k_arnoldi_col(int nv, int ld, const Z* __restrict__ h1,
+                                                         const Z* __restrict__ n1, const Z* __restrict__ h2,
+                                                         const Z* __restrict__ n2, const int* __restrict__ gate,
+                                                         Z* __restrict__ col, double* __restrict__ scale) {
+  const int r = blockIdx.x;
+  const int g = gate[r];
+  for (int i = threadIdx.x; i < nv; i += kBlock) {
+    const Z a = h1[(size_t)r * ld + i];
+    const Z b = g ? h2[(size_t)r * ld + i] : Z{0, 0};
+    col[(size_t)r * ld + i] = Z{a.x + b.x, a.y + b.y};
+  }
+  if (threadIdx.x == 0) {
+    const double nn = sqrt(fmax(0.0, g ? n2[r].x : n1[r].x));
+    col[(size_t)r * ld + nv] = Z{nn, 0};
+    col[(size_t)r * ld + nv + 1] = Z{(double)g, 0};
+    scale[r] = nn > 0 ? 1.0 / nn : 0.0;
+  }
+}
+
+// out[r] = a[r] * s[r] with a real per-RHS factor
+__global__ __launch_bounds__(kBlock) void k_scale_real(size_t Nt, const Z* __restrict__ a,
+                                                        const double* __restrict__ s, Z* __restrict__ out) {
   const int r = blockIdx.y;
-  const Z c = s[(size_t)r * ld_s];
+  const double c = s[r];
   for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
     const Z v = a[(size_t)r * Nt + k];
-    Z o = {v.x * c.x - v.y * c.y, v.x * c.y + v.y * c.x};
-    if (accumulate) {
-      const Z prev = out[(size_t)r * Nt + k];
-      o.x += prev.x;
-      o.y += prev.y;
-    }
-    out[(size_t)r * Nt + k] = o;
+    out[(size_t)r * Nt + k] = Z{v.x * c, v.y * c};
   }
+}
+
+// out += a
+__global__ __launch_bounds__(kBlock) void k_add(size_t cnt, const Z* __restrict__ a, Z* __restrict__ out) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
+    out[i] = {out[i].x + a[i].x, out[i].y + a[i].y};
 }
 
 // out = a - b
@@ -758,6 +849,30 @@ struct DevMem {
     release();
     if (b == 0) return hipSuccess;
     hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  template <typename U>
+  U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+// Pinned host staging for the small per-iteration GMRES transfers.
+struct HostMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  HostMem() = default;
+  HostMem(const HostMem&) = delete;
+  HostMem& operator=(const HostMem&) = delete;
+  ~HostMem() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    release();
+    hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
     if (e == hipSuccess) bytes = b;
     return e;
   }
@@ -1303,7 +1418,7 @@ class EngineT final : public Engine {
     return 0;
   }
 
-  int gmres(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0,
+  int gmres(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0, bool always_reorth,
             std::vector<GmresResult>& res, void* stream, std::string& err) override;
 
   void profile(bool enable) override {
@@ -1426,6 +1541,7 @@ class EngineT final : public Engine {
       (void)hipEventDestroy(r.b);
     }
     if (cap_stream_) (void)hipStreamDestroy(cap_stream_);
+    if (col_ev_) (void)hipEventDestroy(col_ev_);
   }
 
  private:
@@ -1469,22 +1585,28 @@ class EngineT final : public Engine {
   long long nnear_ = 0;
   std::vector<long long> pairs_;
   // GMRES workspace
-  DevMem gV_, gw_, gx_, gb_, gtmp_, gtmpT_, gtmpT2_, gpart_, gh_, gh2_;
+  DevMem gV_, gw_, gx_, gb_, gtmp_, gtmpT_, gtmpT2_, gpart_, gh_, gh2_, gcol_, gn_, ggate_, gscale_;
+  HostMem hcol_, hy_;
+  hipEvent_t col_ev_ = nullptr;
 };
 
-// Right-preconditioned restarted GMRES with CGS2 Arnoldi in FP64.  Each RHS
-// has its own Krylov space; all RHS advance in lock-step and converged ones
-// are frozen (their columns are no longer updated).
+// Right-preconditioned restarted GMRES, Arnoldi in FP64 by classical
+// Gram-Schmidt with selective (DGKS) or unconditional reorthogonalisation.
+// Each RHS has its own Krylov space; all RHS advance in lock-step and
+// converged ones are frozen (their Hessenberg columns are no longer updated,
+// so their correction coefficients are zero).  Per iteration the host waits
+// once, for the Hessenberg column; the next product is already queued.
 template <typename T>
 int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0,
-                      std::vector<GmresResult>& res, void* stream, std::string& err) {
+                      bool always_reorth, std::vector<GmresResult>& res, void* stream, std::string& err) {
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t Nt = (size_t)P_ * n_;
   const size_t tot = (size_t)R * Nt;
   const size_t vstride = tot;  // V[i] is [R][Nt]
-  const int ld = m + 2;        // leading dimension for per-RHS coefficient arrays
-  const int nblk = (int)std::min<size_t>(256, (Nt + kBlock - 1) / kBlock);
+  const int ld = m + 2;        // per-RHS coefficient slots: m + 1 dots/norm + gate
+  const int nblk_d = (int)std::min<size_t>(kDotMaxBlocks, (Nt + kDotChunk - 1) / kDotChunk);
+  const int nblk_s = (int)std::min<size_t>(1024, (Nt + kBlock - 1) / kBlock);
   HIP_TRY(gV_.alloc((size_t)(m + 1) * tot * sizeof(Z)));
   HIP_TRY(gw_.alloc(tot * sizeof(Z)));
   HIP_TRY(gx_.alloc(tot * sizeof(Z)));
@@ -1492,9 +1614,16 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
   HIP_TRY(gtmp_.alloc(tot * sizeof(Z)));
   HIP_TRY(gtmpT_.alloc(tot * sizeof(CT)));
   HIP_TRY(gtmpT2_.alloc(tot * sizeof(CT)));
-  HIP_TRY(gpart_.alloc((size_t)R * nblk * ld * sizeof(Z)));
+  HIP_TRY(gpart_.alloc((size_t)R * ld * std::max(nblk_d, nblk_s) * sizeof(Z)));
   HIP_TRY(gh_.alloc((size_t)R * ld * sizeof(Z)));
   HIP_TRY(gh2_.alloc((size_t)R * ld * sizeof(Z)));
+  HIP_TRY(gcol_.alloc((size_t)R * ld * sizeof(Z)));
+  HIP_TRY(gn_.alloc((size_t)2 * R * sizeof(Z)));
+  HIP_TRY(ggate_.alloc((size_t)R * sizeof(int)));
+  HIP_TRY(gscale_.alloc((size_t)R * sizeof(double)));
+  HIP_TRY(hcol_.alloc((size_t)R * ld * sizeof(Z)));
+  HIP_TRY(hy_.alloc((size_t)R * ld * sizeof(Z)));
+  if (!col_ev_) HIP_TRY(hipEventCreateWithFlags(&col_ev_, hipEventDisableTiming));
   Z* V = gV_.as<Z>();
   Z* w = gw_.as<Z>();
   Z* x = gx_.as<Z>();
@@ -1503,13 +1632,26 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
   CT* tT = gtmpT_.as<CT>();
   CT* tT2 = gtmpT2_.as<CT>();
   Z* part = gpart_.as<Z>();
-  Z* h = gh_.as<Z>();
+  Z* h1 = gh_.as<Z>();
   Z* h2 = gh2_.as<Z>();
+  Z* col = gcol_.as<Z>();
+  Z* n1 = gn_.as<Z>();
+  Z* n2 = n1 + R;
+  int* gate = ggate_.as<int>();
+  double* scale = gscale_.as<double>();
+  Z* hcol = hcol_.as<Z>();
+  Z* hy = hy_.as<Z>();
   const dim3 blk(kBlock);
   const dim3 gv(grid1d(Nt) > 1024 ? 1024 : grid1d(Nt), R);
-  auto launch_multidot = [&](int nv, const Z* vecs, const Z* ww, Z* out) {
-    hipLaunchKernelGGL(k_multidot, dim3(nblk, R), blk, 0, st, nv, ld, Nt, vstride, vecs, ww, part, nblk);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(R), blk, 0, st, nv, ld, nblk, part, out);
+  // h[r][0..nv) = V_i^H w_r, and h[r][nv] = |w_r|^2 when want_norm
+  auto dots = [&](int nv, int want_norm, const Z* ww, Z* out, int ldo, const int* g) {
+    hipLaunchKernelGGL(k_dots, dim3(nblk_d, R), blk, 0, st, nv, want_norm, Nt, vstride, V, ww, part, ld, g);
+    hipLaunchKernelGGL(k_reduce, dim3(nv + want_norm, R), blk, 0, st, nblk_d, part, ld, out, ldo, g);
+  };
+  // ww -= sum_i V_i c_i; nout[r] = |ww_r|^2
+  auto subtract = [&](int nv, const Z* c, Z* ww, Z* nout, const int* g) {
+    hipLaunchKernelGGL(k_subtract_norm, dim3(nblk_s, R), blk, 0, st, nv, Nt, vstride, V, c, ld, ww, part, g);
+    hipLaunchKernelGGL(k_reduce, dim3(1, R), blk, 0, st, nblk_s, part, 1, nout, 1, g);
   };
   // operator A z = Z (P^-1 z), z FP64 -> result FP64 in `out`
   auto apply_A = [&](const Z* z, Z* out, bool precond) -> int {
@@ -1524,13 +1666,12 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
     hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, dst, out, tot);
     return 0;
   };
-  std::vector<Z> hh((size_t)R * ld), hnorm((size_t)R * ld);
   auto norms = [&](const Z* vec, std::vector<double>& out) -> int {
-    launch_multidot(1, vec, vec, h2);
-    HIP_TRY(hipMemcpyAsync(hnorm.data(), h2, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
+    dots(0, 1, vec, n1, 1, nullptr);
+    HIP_TRY(hipMemcpyAsync(hcol, n1, (size_t)R * sizeof(Z), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     out.resize(R);
-    for (int r = 0; r < R; ++r) out[r] = std::sqrt(std::max(0.0, hnorm[(size_t)r * ld].x));
+    for (int r = 0; r < R; ++r) out[r] = std::sqrt(std::max(0.0, hcol[r].x));
     return 0;
   };
   hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, reinterpret_cast<const CT*>(bv), b, tot);
@@ -1560,56 +1701,62 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
     }
   }
   std::vector<char> done(R, 0);
-  std::vector<int> iters(R, 0);
+  std::vector<int> iters(R, 0), reorth(R, 0), cycles(R, 0);
   for (int r = 0; r < R; ++r) {
     if (bnorm[r] == 0.0 || rnorm[r] <= rtol * bnorm[r]) done[r] = 1;
   }
   int total_it = 0;
   std::vector<std::vector<cd>> H(R), cs(R), sn(R), g(R);
+  std::vector<double> s0(R);
   while (true) {
     bool all_done = true;
     for (int r = 0; r < R; ++r) all_done &= (bool)done[r];
     if (all_done || total_it >= max_iter) break;
     // V0 = r / |r| (zero for finished RHS so they stay frozen)
     for (int r = 0; r < R; ++r) {
-      hh[(size_t)r * ld] = done[r] || rnorm[r] == 0.0 ? Z{0, 0} : Z{1.0 / rnorm[r], 0};
+      s0[r] = done[r] || rnorm[r] == 0.0 ? 0.0 : 1.0 / rnorm[r];
       H[r].assign((size_t)(m + 1) * m, 0.0);
       cs[r].assign(m, 0.0);
       sn[r].assign(m, 0.0);
       g[r].assign(m + 1, 0.0);
       g[r][0] = rnorm[r];
+      if (!done[r]) cycles[r]++;
     }
-    HIP_TRY(hipMemcpyAsync(h, hh.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_scale, gv, blk, 0, st, Nt, w, h, ld, V, 0);
+    HIP_TRY(hipMemcpyAsync(scale, s0.data(), (size_t)R * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_scale_real, gv, blk, 0, st, Nt, w, scale, V);
     int j = 0;
     std::vector<char> active(R);
     for (int r = 0; r < R; ++r) active[r] = !done[r];
+    if (int rc = apply_A(V, w, true)) return rc;
     for (; j < m && total_it < max_iter; ++j) {
-      Z* vj1 = V + (size_t)(j + 1) * vstride;
-      if (int rc = apply_A(V + (size_t)j * vstride, w, true)) return rc;
       ++total_it;
-      // CGS2
-      launch_multidot(j + 1, V, w, h);
-      hipLaunchKernelGGL(k_subtract_proj, gv, blk, 0, st, j + 1, ld, Nt, vstride, V, h, w);
-      launch_multidot(j + 1, V, w, h2);
-      hipLaunchKernelGGL(k_subtract_proj, gv, blk, 0, st, j + 1, ld, Nt, vstride, V, h2, w);
-      HIP_TRY(hipMemcpyAsync(hh.data(), h, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
-      std::vector<Z> hh2((size_t)R * ld);
-      HIP_TRY(hipMemcpyAsync(hh2.data(), h2, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
-      std::vector<double> wn;
-      if (int rc = norms(w, wn)) return rc;
+      const int nv = j + 1;
+      // w = A v_j: two Gram-Schmidt passes, the second where DGKS asks for it
+      dots(nv, 1, w, h1, ld, nullptr);
+      subtract(nv, h1, w, n1, nullptr);
+      hipLaunchKernelGGL(k_dgks_gate, dim3((R + 63) / 64), dim3(64), 0, st, R, h1, ld, nv, n1, gate,
+                         always_reorth ? 1 : 0);
+      dots(nv, 0, w, h2, ld, gate);
+      subtract(nv, h2, w, n2, gate);
+      hipLaunchKernelGGL(k_arnoldi_col, dim3(R), blk, 0, st, nv, ld, h1, n1, h2, n2, gate, col, scale);
+      hipLaunchKernelGGL(k_scale_real, gv, blk, 0, st, Nt, w, scale, V + (size_t)(j + 1) * vstride);
+      HIP_TRY(hipMemcpyAsync(hcol, col, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipEventRecord(col_ev_, st));
+      // queue the next product before the host looks at the column
+      if (j + 1 < m && total_it < max_iter)
+        if (int rc = apply_A(V + (size_t)(j + 1) * vstride, w, true)) return rc;
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipEventSynchronize(col_ev_));
       bool any_active = false;
       for (int r = 0; r < R; ++r) {
-        if (!active[r]) {
-          hh[(size_t)r * ld] = Z{0, 0};
-          continue;
-        }
+        if (!active[r]) continue;
         iters[r]++;
+        const Z* cr = hcol + (size_t)r * ld;
+        reorth[r] += cr[nv + 1].x != 0.0;
         std::vector<cd>& Hr = H[r];
-        for (int i = 0; i <= j; ++i)
-          Hr[(size_t)i * m + j] = cd(hh[(size_t)r * ld + i].x + hh2[(size_t)r * ld + i].x,
-                                     hh[(size_t)r * ld + i].y + hh2[(size_t)r * ld + i].y);
-        Hr[(size_t)(j + 1) * m + j] = wn[r];
+        for (int i = 0; i <= j; ++i) Hr[(size_t)i * m + j] = cd(cr[i].x, cr[i].y);
+        const double wn = cr[nv].x;
+        Hr[(size_t)(j + 1) * m + j] = wn;
         for (int i = 0; i < j; ++i) {  // previous rotations
           cd a = Hr[(size_t)i * m + j], bb = Hr[(size_t)(i + 1) * m + j];
           Hr[(size_t)i * m + j] = std::conj(cs[r][i]) * a + std::conj(sn[r][i]) * bb;
@@ -1629,22 +1776,22 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
         g[r][j + 1] = -sn[r][j] * g[r][j];
         g[r][j] = std::conj(cs[r][j]) * g[r][j];
         const double est = std::abs(g[r][j + 1]);
-        if (est <= rtol * bnorm[r] || wn[r] == 0.0) active[r] = 0;
+        if (!std::isfinite(est)) {
+          err = "non-finite Arnoldi coefficient";
+          return -5;  // non-finite
+        }
+        if (est <= rtol * bnorm[r] || wn == 0.0) active[r] = 0;
         any_active |= (bool)active[r];
-        hh[(size_t)r * ld] = wn[r] > 0 ? Z{1.0 / wn[r], 0} : Z{0, 0};
       }
-      HIP_TRY(hipMemcpyAsync(h, hh.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_scale, gv, blk, 0, st, Nt, w, h, ld, vj1, 0);
       if (!any_active) {
         ++j;
         break;
       }
     }
     // x += P^-1 V y with H y = g (upper triangular, per RHS, size j)
-    std::vector<Z> yv((size_t)R * ld, Z{0, 0});
+    for (size_t i = 0; i < (size_t)R * ld; ++i) hy[i] = Z{0, 0};
     for (int r = 0; r < R; ++r) {
       if (done[r]) continue;
-      const int jr = std::min(j, iters[r] - (total_it - j > 0 ? 0 : 0));
       std::vector<cd> yy(j, 0.0);
       for (int i = j - 1; i >= 0; --i) {
         cd s = g[r][i];
@@ -1652,21 +1799,15 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
         cd d = H[r][(size_t)i * m + i];
         yy[i] = d == 0.0 ? 0.0 : s / d;
       }
-      (void)jr;
-      for (int i = 0; i < j; ++i) yv[(size_t)r * ld + i] = Z{yy[i].real(), yy[i].imag()};
+      for (int i = 0; i < j; ++i) hy[(size_t)r * ld + i] = Z{yy[i].real(), yy[i].imag()};
     }
-    HIP_TRY(hipMemcpyAsync(h, yv.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_combine, gv, blk, 0, st, j, ld, Nt, vstride, V, h, tmp, 0);
-    // x += P^-1 tmp (in FP64 through the context precision)
+    HIP_TRY(hipMemcpyAsync(h1, hy, (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_combine, gv, blk, 0, st, j, ld, Nt, vstride, V, h1, tmp, 0);
+    // x += P^-1 tmp (through the context precision)
     hipLaunchKernelGGL(k_from_z<T>, dim3(grid1d(tot)), blk, 0, st, tmp, tT, tot);
     if (int rc = precondition(tT, tT2, R, stream, err)) return rc;
     hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, tT2, tmp, tot);
-    {
-      std::vector<Z> one((size_t)R * ld, Z{0, 0});
-      for (int r = 0; r < R; ++r) one[(size_t)r * ld] = done[r] ? Z{0, 0} : Z{1, 0};
-      HIP_TRY(hipMemcpyAsync(h2, one.data(), (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_scale, gv, blk, 0, st, Nt, tmp, h2, ld, x, 1);
-    }
+    hipLaunchKernelGGL(k_add, dim3(grid1d(tot)), blk, 0, st, tot, tmp, x);
     // true residual
     if (int rc = residual(w)) return rc;
     if (int rc = norms(w, rnorm)) return rc;
@@ -1682,6 +1823,8 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
     res[r].true_rel_res = bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0;
     res[r].converged = res[r].true_rel_res <= rtol;
     res[r].time_s = secs;
+    res[r].reorth = reorth[r];
+    res[r].cycles = cycles[r];
   }
   return 0;
 }

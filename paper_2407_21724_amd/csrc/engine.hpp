@@ -41,6 +41,8 @@ struct GmresResult {
   double true_rel_res = 0;
   double time_s = 0;
   int converged = 0;
+  int reorth = 0;   // iterations that took the second Gram-Schmidt pass
+  int cycles = 0;   // restart cycles
 };
 
 struct StageTime {
@@ -62,7 +64,7 @@ class Engine {
   virtual int rhs(const std::vector<cd>& pat, const std::vector<V3>& khat, int R, void* b, void* stream,
                   std::string& err) = 0;
   virtual int gmres(const void* b, void* x, int R, double rtol, int max_iter, int restart, bool use_x0,
-                    std::vector<GmresResult>& res, void* stream, std::string& err) = 0;
+                    bool always_reorth, std::vector<GmresResult>& res, void* stream, std::string& err) = 0;
   virtual long long device_bytes() const = 0;
 };
 

@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENONFINITE, NOT_CONVERGED = 0, -1, -2, -3, 
 C64, C128 = 0, 1
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 SOLVE_USE_X0 = 1
+SOLVE_ALWAYS_REORTH = 2
 
 
 class MlfmaError(RuntimeError):
@@ -52,7 +53,7 @@ class StageTime(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("true_rel_res", C.c_double), ("time_s", C.c_double),
-                ("converged", C.c_int32)]
+                ("converged", C.c_int32), ("reorth", C.c_int32), ("cycles", C.c_int32)]
 
 
 EXPORTS = [
@@ -248,17 +249,19 @@ class Context:
                     "precondition")
         return out
 
-    def gmres_solve(self, b, x=None, rtol=1e-4, max_iter=1000, restart=100, use_x0=False, stream=None):
+    def gmres_solve(self, b, x=None, rtol=1e-4, max_iter=1000, restart=100, use_x0=False, always_reorth=False,
+                    stream=None):
         import torch
         R = b.shape[0]
         if x is None:
             x = torch.zeros_like(b)
         stats = (SolveStats * R)()
         rc = self._check(lib().mlfma_gmres_solve(self._h, self._dev(b, R), self._dev(x, R), R, rtol, max_iter,
-                                                 restart, SOLVE_USE_X0 if use_x0 else 0, stats,
+                                                 restart, (SOLVE_USE_X0 if use_x0 else 0)
+                                                 | (SOLVE_ALWAYS_REORTH if always_reorth else 0), stats,
                                                  _stream_ptr(stream)), "gmres_solve")
         out = [dict(iterations=s.iterations, true_rel_res=s.true_rel_res, time_s=s.time_s,
-                    converged=bool(s.converged)) for s in stats]
+                    converged=bool(s.converged), reorth=s.reorth, cycles=s.cycles) for s in stats]
         return x, out, rc
 
     def profile(self, enable: bool):

@@ -65,7 +65,9 @@ def test_tree_levels_and_truncation():
     inf = ctx.info()
     # leaf 0.5: 40, 20, 10, 5, 3 boxes; L from the excess-bandwidth rule
     assert inf["nx"] == [40, 20, 10, 5, 3]
-    assert inf["L"][0] == 10
+    assert inf["L"][0] == 11                       # library default finest truncation
+    assert mlfma.Context(w.lattice(40, 40, 0.5), np.zeros(1600, np.int32), 1,
+                         mlfma.default_params(L_leaf=10)).info()["L"][0] == 10
     for lev in range(1, 5):
         a = 0.5 * 2 ** lev
         kd = 2 * math.pi * math.sqrt(2) * a
