@@ -24,19 +24,119 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-FP32_VALU_PEAK = 157.3e12  # MI355X FP32 vector
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP32_MFMA_PEAK = 157.3e12   # MI355X dense FP32 matrix-core peak
+FP32_VALU_PEAK = 157.3e12   # MI355X FP32 vector peak
+ENGINE_SRC = os.path.join(ROOT, "paper_2407_21724_amd", "csrc", "engine.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_c2_40x40.json")
+
+# product stages (as named by mlfma_profile_read) -> kernel symbol prefix and
+# the roofline that bounds it
+KERNELS = [
+    ("near+project", "k_gemm_stream<4, 1, 0>", "mfma"),
+    ("near", "k_gemm_stream<4, 1, 1>", "mfma"),
+    ("project", "k_gemm_stream<4, 1, 2>", "mfma"),
+    ("receive", "k_gemm_stream<4, 1, 3>", "mfma"),
+    ("aggregate_l", "k_aggregate", "hbm"),
+    ("translate_l", "k_translate", "hbm"),
+    ("disaggregate_l", "k_disaggregate", "hbm"),
+]
+
+
+def kernel_of(stage):
+    for prefix, sym, bound in KERNELS:
+        if stage == prefix or (prefix.endswith("_l") and stage.startswith(prefix)):
+            return sym, bound
+    return stage, "hbm"
+
+
+def source_digest():
+    import hashlib
+    with open(ENGINE_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def kernel_table(stages):
+    """Group per-stage event timings by kernel symbol (the unit rocprofv3
+    reports): total time, launches, algorithmic bytes and flops per launch."""
+    groups = {}
+    for s in stages:
+        sym, bound = kernel_of(s["name"])
+        g = groups.setdefault(sym, {"kernel": sym, "bound": bound, "total_ms": 0.0, "launches": 0,
+                                    "bytes": 0.0, "flops": 0.0, "stages": []})
+        g["total_ms"] += s["total_ms"]
+        g["launches"] += s["launches"]
+        g["bytes"] += s["bytes_per_launch"] * s["launches"]
+        g["flops"] += s["flops_per_launch"] * s["launches"]
+        g["stages"].append(s["name"])
+    return groups
+
+
+def measured_traffic(sym):
+    """HBM bytes per launch of kernel `sym` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, or None when they are missing or were taken
+    on another version of the kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(sym)
+    return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def pmc_digest(fetch_csv, write_csv, copy_mib, out_path):
+    """Turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) into HBM bytes per launch per kernel symbol.  Each counter is
+    scaled by the ratio of known bytes to its reading on the plain copy
+    kernel of the calibration (the largest dispatch of the run)."""
+    import csv
+    from collections import defaultdict
+
+    def read(path, counter):
+        per = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                per[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return per
+
+    fetch, write = read(fetch_csv, "FETCH_SIZE"), read(write_csv, "WRITE_SIZE")
+    copy_bytes = copy_mib * 2 ** 20
+    cal_f = max(max(v) for v in fetch.values()) * 1024.0
+    cal_w = max(max(v) for v in write.values()) * 1024.0
+    sf, sw = copy_bytes / cal_f, copy_bytes / cal_w
+    kernels = {}
+    for name in fetch:
+        sym = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("mlfma::", "")
+        if not sym.startswith("k_"):
+            continue
+        fb = sum(fetch[name]) / len(fetch[name]) * 1024.0 * sf
+        wb = sum(write.get(name, [0.0])) / max(1, len(write.get(name, []))) * 1024.0 * sw
+        kernels[sym] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                        "traffic_bytes_per_launch": fb + wb, "dispatches": len(fetch[name])}
+    rec = {"workload": "40x40 cylinders, FP32 product, R = 1", "source_sha256": source_digest(),
+           "calibration": {"copy_bytes": copy_bytes, "fetch_KiB": cal_f / 1024, "write_KiB": cal_w / 1024,
+                           "fetch_scale": sf, "write_scale": sw},
+           "kernels": kernels}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(wl, M):
     """Oracle cost of one full dense product of this workload, from a bounded
-    sample: S distinct pair blocks computed by the oracle on all host cores,
-    plus block products timed on one core; extrapolated to the 6,241
-    distinct offset blocks and 1,600^2 block products of one product."""
+    sample: S distinct pair blocks computed by the oracle on the host cores
+    (at most 16 worker processes, forked before the GPU is initialised), plus
+    block products timed on one core; extrapolated to the 6,241 distinct
+    offset blocks and 1,600^2 block products of one product."""
     import numpy as np
 
     from oracle.pmchwt import DenseProblem, ParticleClass
-    cores = len(os.sched_getaffinity(0))
+    cores = min(16, len(os.sched_getaffinity(0)))
     v, t, e = wl.meshes[0]
     pc = ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r, M=M)
     prob = DenseProblem([pc], wl.centers, wl.class_id)
@@ -74,7 +174,14 @@ def main():
     ap.add_argument("--rhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--pmc-digest", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="digest two rocprofv3 counter CSVs into the traffic record and exit")
     args = ap.parse_args()
+    if args.pmc_digest:
+        pmc_digest(args.pmc_digest[0], args.pmc_digest[1], args.copy_calibration or 256, TRAFFIC_FILE)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the product is computed on a single MI355X; "
               "multi-GPU sharding is not part of this build", file=sys.stderr)
@@ -86,15 +193,27 @@ def main():
     import workloads as w
     from paper_2407_21724_amd import mlfma
 
-    torch.cuda.set_device(0)
     wl = w.workload("c2")
     v, t, e = wl.meshes[0]
     t0 = time.perf_counter()
-    M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+    M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)     # host-only call
+    modes_s = time.perf_counter() - t0
+    # the oracle leg runs first, before this process touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl, M)
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration * 2 ** 18, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    t0 = time.perf_counter()
     ctx = mlfma.Context(wl.centers, wl.class_id, 1, mlfma.default_params(precision=mlfma.C64))
     ctx.set_static_modes(0, v, t, e, wl.n_perp, wl.n_par, M, wl.eps_r)
     ctx.prepare()
-    setup_s = time.perf_counter() - t0
+    setup_s = time.perf_counter() - t0 + modes_s
     info = ctx.info()
     R = args.rhs
     P, n = wl.n_particles, 2 * (wl.n_perp + wl.n_par)
@@ -113,8 +232,8 @@ def main():
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
-        # second pass over the same steps with per-kernel HIP events recorded
-        # on the launch stream (captured in the replayed graph)
+        # second pass over the same steps, launched directly (not from the
+        # cached graph) with per-kernel HIP events recorded on the stream
         ctx.profile(True)
         for _ in range(args.steps):
             ctx.matvec(x, out=y)
@@ -123,19 +242,24 @@ def main():
         ctx.profile(False)
     value = wl.n_unknowns * R / (ms * 1e-3)
 
-    # roofline of the dominant kernel (largest share of the timed region)
-    dom = max(stages, key=lambda s: s["total_ms"])
-    avg_ms = dom["total_ms"] / dom["launches"]
-    if dom["name"].startswith(("translate", "aggregate", "disaggregate")):
-        achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    # roofline of the dominant kernel (largest share of the product's time)
+    groups = kernel_table(stages)
+    dom = max(groups.values(), key=lambda g: g["total_ms"])
+    avg_s = dom["total_ms"] / dom["launches"] * 1e-3
+    if dom["bound"] == "hbm":
+        achieved = dom["bytes"] / dom["launches"] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                "frac": achieved / HBM_PEAK_GBS}
     else:
-        achieved = dom["flops_per_launch"] / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": achieved * 1e12 / FP32_VALU_PEAK, "traffic": None}
-    roof["kernel"] = dom["name"]
-    roof["avg_launch_us"] = avg_ms * 1e3
+        achieved = dom["flops"] / dom["launches"] / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": achieved * 1e12 / FP32_MFMA_PEAK}
+    roof["traffic"] = measured_traffic(dom["kernel"]) if R == 1 else None
+    roof["kernel"] = dom["kernel"]
+    roof["stages"] = dom["stages"]
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["algorithmic_bytes_per_launch"] = dom["bytes"] / dom["launches"]
+    roof["algorithmic_flops_per_launch"] = dom["flops"] / dom["launches"]
 
     out = {
         "metric": "MLFMA-SMR matvec throughput (unknowns*RHS/s); GMRES time-to-1e-4 reported beside it",
@@ -147,6 +271,7 @@ def main():
                    "rhs": R, "levels": info["n_levels"], "L": info["L"], "K": info["K"]},
         "roofline": roof,
         "stages_us": {s["name"]: round(1e3 * s["total_ms"] / s["launches"], 2) for s in stages},
+        "kernels_us": {g["kernel"]: round(1e3 * g["total_ms"] / g["launches"], 2) for g in groups.values()},
         "setup_s": setup_s,
     }
     if not args.no_gmres:
@@ -158,9 +283,10 @@ def main():
         torch.cuda.synchronize()
         out["gmres"] = {"time_to_1e-4_s": time.perf_counter() - t0, "iterations": st[0]["iterations"],
                         "true_rel_res": st[0]["true_rel_res"], "converged": st[0]["converged"],
-                        "restart": 100, "rhs": 1, "initial_guess": "zero"}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, M)
+                        "restart": 100, "rhs": 1, "initial_guess": "zero", "reorth": st[0]["reorth"],
+                        "cycles": st[0]["cycles"]}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

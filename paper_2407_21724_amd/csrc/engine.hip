@@ -9,6 +9,7 @@
 //   TL_l        [49][K_l]            translation function per box offset
 // Every kernel writes each output element once (no atomics), so repeated
 // products are bitwise reproducible.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -144,6 +145,17 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(C2<T>* __restrict__ y, siz
   for (; i < count; i += stride) y[i] = {0, 0};
 }
 
+// XCD-aware block order.  The dispatcher deals consecutive workgroups of a
+// launch to the 8 XCDs in turn, and each XCD has its own L2.  A launch of
+// 8 * ceil(total / 8) blocks renumbered this way gives XCD x the contiguous
+// logical range [x * per, (x + 1) * per), so neighbouring tiles, which read
+// the same inputs, share one L2.  Logical ids >= total are idle blocks.
+__device__ __forceinline__ int xcd_block(int b, int total) {
+  const int per = (total + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+inline int xcd_grid(int total) { return 8 * ((total + 7) / 8); }
+
 // ------------------------------------------------------------ MFMA GEMM --
 // Real FP32 GEMM on the matrix cores, C[m][n] (+)= sum_k A[m][k] B[k][n],
 // used for the dense contractions of the product (near blocks, leaf
@@ -155,74 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(C2<T>* __restrict__ y, siz
 //     ldb + k'] with k = s*kseg + k'; bcol < 0 gives a zero column.
 //   C column n: floats Cdst[ccol[n] * ldc + m].
 //   blockIdx.z = right-hand side r: B and C advance by strideB, strideC.
-// Block = 4 waves, tile 64 x 64, K staged in chunks of 16 through LDS;
-// wave w owns rows [16w, 16w+16) as four 16 x 16 MFMA tiles.  Lane layout
-// of v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16k, B[k][j] from lane
-// j + 16k, result row 4*(lane/16) + v, column lane % 16 in register v.
+// Lane layout of v_mfma_f32_16x16x4f32: A[i][k] from lane i + 16k, B[k][j]
+// from lane j + 16k, result row 4*(lane/16) + v, column lane % 16 in
+// register v.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kGM = 64;
-template <int NT, int KC>
-__global__ __launch_bounds__(kBlock) void k_gemm_f32(int M, int ncols, int nseg, int kseg, const float* __restrict__ A,
-                                                      int lda, const float* __restrict__ Bsrc, int ldb,
-                                                      const int* __restrict__ bcol, float* __restrict__ Cdst, int ldc,
-                                                      const int* __restrict__ ccol, int accumulate, size_t strideB,
-                                                      size_t strideC) {
-  constexpr int BN = 16 * NT;
-  __shared__ float As[kGM][KC + 1];
-  __shared__ float Bs[KC][BN + 4];
-  const int m0 = blockIdx.x * kGM, n0 = blockIdx.y * BN, r = blockIdx.z;
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const float* __restrict__ Bb = Bsrc + (size_t)r * strideB;
-  const int K = nseg * kseg;
-  f32x4 acc[NT];
-#pragma unroll
-  for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < (kGM * KC) / kBlock; ++i) {
-      const int idx = t + i * kBlock;
-      const int row = idx / KC, kk = idx % KC;
-      const int m = m0 + row, k = k0 + kk;
-      As[row][kk] = (m < M && k < K) ? A[(size_t)m * lda + k] : 0.f;
-    }
-    for (int idx = t; idx < BN * KC; idx += kBlock) {
-      const int col = idx / KC, kk = idx % KC;
-      const int n = n0 + col, k = k0 + kk;
-      float v = 0.f;
-      if (n < ncols && k < K) {
-        const int sgm = k / kseg;
-        const int src = bcol[(size_t)n * nseg + sgm];
-        if (src >= 0) v = Bb[(size_t)src * ldb + (k - sgm * kseg)];
-      }
-      Bs[kk][col] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < KC / 4; ++k4) {
-      const float a = As[16 * wave + (lane & 15)][4 * k4 + (lane >> 4)];
-#pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        const float b = Bs[4 * k4 + (lane >> 4)][16 * c + (lane & 15)];
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
-      }
-    }
-  }
-  float* __restrict__ Cb = Cdst + (size_t)r * strideC;
-#pragma unroll
-  for (int c = 0; c < NT; ++c) {
-    const int n = n0 + 16 * c + (lane & 15);
-    if (n >= ncols) continue;
-    float* __restrict__ col = Cb + (size_t)ccol[n] * ldc;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int m = m0 + 16 * wave + 4 * (lane >> 4) + v;
-      if (m < M) col[m] = accumulate ? col[m] + acc[c][v] : acc[c][v];
-    }
-  }
-}
 
-// Streaming variant: no LDS staging of the operands.  Block = 4 waves that
+// No LDS staging of the operands.  Block = 4 waves that
 // share one output tile of RT x CT 16 x 16 MFMA tiles and split the K range
 // four ways; partial sums are reduced through LDS in a fixed order.  K is
 // walked in steps of 16 with a k-permutation inside each step: lane (i, kq)
@@ -230,18 +180,45 @@ __global__ __launch_bounds__(kBlock) void k_gemm_f32(int M, int ncols, int nseg,
 // its A row and B column, and MFMA q contracts over kq.  A and B use the same
 // permutation, so the sum covers every k once.  Requires lda, ldb, kseg and
 // the segment length multiples of 4 floats and 16-byte aligned bases.
-template <int RT, int CT>
-__global__ __launch_bounds__(kBlock) void k_gemm_stream(int M, int ncols, int nseg, int kseg,
-                                                         const float* __restrict__ A, int lda,
-                                                         const float* __restrict__ Bsrc, int ldb,
-                                                         const int* __restrict__ bcol, float* __restrict__ Cdst,
-                                                         int ldc, const int* __restrict__ ccol, int accumulate,
-                                                         size_t strideB, size_t strideC) {
+//
+// One launch runs up to two independent GEMMs (jobs): blocks [0, j0.tiles)
+// take job 0, the rest job 1.  Within a job, block t computes row tile
+// t % tiles_m of column tile t / tiles_m.  With a_off set, column tile nt
+// multiplies A + a_off[nt] (one matrix per group of columns, e.g. per
+// particle class, each group padded to whole column tiles).  Tag only gives
+// each use its own kernel symbol.
+struct GemmJob {
+  const float* A;
+  const int* a_off;
+  const float* B;
+  const int* bcol;  // B column n, segment s: floats B[bcol[n*nseg+s] * ldb + k'] (< 0: zero column)
+  float* C;
+  const int* ccol;  // C column n: floats C[ccol[n] * ldc + m] (< 0: not written)
+  size_t sB, sC;    // per right-hand side (blockIdx.z) strides of B and C
+  int M, ncols, nseg, kseg, lda, ldb, ldc, acc, tiles_m, tiles;
+  int xcd;          // (job 0 only) blocks in XCD-aware order over a grid of xcd_grid(tiles)
+};
+
+template <int RT, int CT, int Tag>
+__global__ __launch_bounds__(kBlock) void k_gemm_stream(GemmJob j0, GemmJob j1) {
   __shared__ f32x4 red[3][RT * CT][64];
-  const int m0 = blockIdx.x * 16 * RT, n0 = blockIdx.y * 16 * CT, r = blockIdx.z;
+  const int bid = j0.xcd ? xcd_block(blockIdx.x, j0.tiles + j1.tiles) : (int)blockIdx.x;
+  if (bid >= j0.tiles + j1.tiles) return;
+  const bool second = bid >= j0.tiles;
+  const int t = second ? bid - j0.tiles : bid;
+  const int M = second ? j1.M : j0.M, ncols = second ? j1.ncols : j0.ncols;
+  const int nseg = second ? j1.nseg : j0.nseg, kseg = second ? j1.kseg : j0.kseg;
+  const int lda = second ? j1.lda : j0.lda, ldb = second ? j1.ldb : j0.ldb, ldc = second ? j1.ldc : j0.ldc;
+  const int accumulate = second ? j1.acc : j0.acc, tiles_m = second ? j1.tiles_m : j0.tiles_m;
+  const int* __restrict__ bcol = second ? j1.bcol : j0.bcol;
+  const int* __restrict__ ccol = second ? j1.ccol : j0.ccol;
+  const int* __restrict__ a_off = second ? j1.a_off : j0.a_off;
+  const int tm = t % tiles_m, tn = t / tiles_m;
+  const float* __restrict__ A = (second ? j1.A : j0.A) + (a_off ? a_off[tn] : 0);
+  const int m0 = tm * 16 * RT, n0 = tn * 16 * CT, r = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 15, kq = lane >> 4;
-  const float* __restrict__ Bb = Bsrc + (size_t)r * strideB;
+  const float* __restrict__ Bb = (second ? j1.B : j0.B) + (size_t)r * (second ? j1.sB : j0.sB);
   const int K = nseg * kseg;
   const int nsup = (K + 15) / 16;
   const int s0 = (wave * nsup) / 4, s1 = ((wave + 1) * nsup) / 4;
@@ -289,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm_stream(int M, int ncols, int ns
   }
   __syncthreads();
   if (wave != 0) return;
-  float* __restrict__ Cb = Cdst + (size_t)r * strideC;
+  float* __restrict__ Cb = (second ? j1.C : j0.C) + (size_t)r * (second ? j1.sC : j0.sC);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -299,7 +276,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm_stream(int M, int ncols, int ns
       for (int w = 0; w < 3; ++w) v += red[w][rt * CT + ct][lane];
       const int n = ncol[ct];
       if (n >= ncols) continue;
-      float* __restrict__ col = Cb + (size_t)ccol[n] * ldc;
+      const int dcol = ccol[n];
+      if (dcol < 0) continue;
+      float* __restrict__ col = Cb + (size_t)dcol * ldc;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int m = m0 + 16 * rt + 4 * kq + e;
@@ -504,9 +483,10 @@ __global__ __launch_bounds__(kBlock) void k_aggregate(
 }
 
 // ----------------------------------------------------------- disaggregate --
-// G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), as gathers over the
-// transposed stencils.  Block = (child box, component) x strip of ts child
-// rows x RHS.  LDS: the strip's transposed theta tables, the transposed phi
+// G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), the anterpolation written
+// as gathers over the transposed stencils, added to the child's translated
+// pattern.  Block = (child box, component) x strip of ts child rows x RHS,
+// in XCD-aware order over a 1-D grid (child box fastest).  LDS: the strip's transposed theta tables, the transposed phi
 // tables, the phase-weighted parent rows [plo, phi] ([rows][np_p]) and their
 // phi-transposed interpolation ([rows][np_c]).
 template <typename T>
@@ -514,7 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
     int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int tmax, int pmax,
     int prows_max, const C2<T>* __restrict__ Gp, C2<T>* __restrict__ Gc, const int* __restrict__ tth_row,
     const T* __restrict__ tth_w, const int* __restrict__ tth_flip, const int* __restrict__ strip_prow,
-    const int* __restrict__ tph_col, const T* __restrict__ tph_w, const C2<T>* __restrict__ phase) {
+    const int* __restrict__ tph_col, const T* __restrict__ tph_w, const C2<T>* __restrict__ phase, int nstrips,
+    int R) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* par = reinterpret_cast<C2<T>*>(smem_raw);    // [prows_max][npp]
   C2<T>* tmp = par + (size_t)prows_max * npp;           // [prows_max][npc]
@@ -522,8 +503,12 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
   T* tpw = ttw + ts * tmax;
   int* ttr = reinterpret_cast<int*>(tpw + npc * pmax);  // parent row relative to plo; -1-row if flipped
   int* tpc = ttr + ts * tmax;
-  const int cb = blockIdx.x >> 1, comp = blockIdx.x & 1;
-  const int strip = blockIdx.y, r = blockIdx.z;
+  const int total = nxc * nyc * 2 * nstrips * R;
+  const int lb = xcd_block(blockIdx.x, total);
+  if (lb >= total) return;
+  const int bx = lb % (nxc * nyc * 2), rest = lb / (nxc * nyc * 2);
+  const int cb = bx >> 1, comp = bx & 1;
+  const int strip = rest % nstrips, r = rest / nstrips;
   const int c0 = strip * ts;
   const int nrow = min(ts, ntc - c0);
   const int ci = cb % nxc, cj = cb / nxc;
@@ -571,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
       v.x += w * sv.x;
       v.y += w * sv.y;
     }
-    C2<T> o = dst[i];
+    const C2<T> o = dst[i];
     dst[i] = {o.x + v.x, o.y + v.y};
   }
 }
@@ -580,14 +565,20 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
 // G[r][p][c][s] = sum over the interaction list of TL[offset][s] S[r][q][c][s].
 // The list of box p (at most 27 (source box, offset) pairs, built on the
 // host) is uniform over the block, so all partner loads are independent.
+// Blocks (box fastest, then RHS, then 256-sample chunk) in XCD-aware order.
 constexpr int kMaxIL = 27;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_translate(int nb, int K, const C2<T>* __restrict__ S,
                                                        C2<T>* __restrict__ G, const C2<T>* __restrict__ TL,
                                                        const int* __restrict__ il_cnt, const int* __restrict__ il_src,
-                                                       const int* __restrict__ il_off) {
-  const int p = blockIdx.x, r = blockIdx.y;
-  const int s = blockIdx.z * kBlock + threadIdx.x;
+                                                       const int* __restrict__ il_off, int R) {
+  const int nz = (K + kBlock - 1) / kBlock;
+  const int total = nb * R * nz;
+  const int lb = xcd_block(blockIdx.x, total);
+  if (lb >= total) return;
+  const int p = lb % nb, rest = lb / nb;
+  const int r = rest % R;
+  const int s = (rest / R) * kBlock + threadIdx.x;
   if (s >= K) return;
   const int cnt = il_cnt[p];
   const C2<T>* __restrict__ Sr = S + (size_t)r * nb * 2 * K;
@@ -888,6 +879,10 @@ int grid1d(size_t work) {
 template <typename T>
 class EngineT final : public Engine {
   using CT = C2<T>;
+  struct Pending {  // a profiled stage whose launch has not happened yet
+    int stage = -1;
+    hipEvent_t a = nullptr, b = nullptr;
+  };
   struct Lvl {
     int nx, ny, nt, np, K;
     DevMem TL;
@@ -1137,18 +1132,38 @@ class EngineT final : public Engine {
       A[(row + 1) * lda + col] = (float)z.imag();
       A[(row + 1) * lda + col + 1] = (float)z.real();
     };
-    // class ranges of the class-sorted particle order
-    cls_start_.assign(nc_, 0);
-    cls_count_.assign(nc_, 0);
-    for (size_t i = 0; i < u.order.size(); ++i) {
-      const int c = u.class_of[u.order[i]];
-      if (cls_count_[c] == 0) cls_start_[c] = (int)i;
-      cls_count_[c]++;
+    // GEMM columns of the projection and receive: particles grouped by class
+    // (the class-sorted order), each class padded to whole 16-column tiles
+    // (padding columns are -1: zero input, not written); one matrix offset
+    // per column tile.
+    {
+      std::vector<int> part, box, aop, aor;
+      const int nf0 = 2 * n_;
+      size_t i = 0;
+      while (i < u.order.size()) {
+        const int c = u.class_of[u.order[i]];
+        size_t e = i;
+        while (e < u.order.size() && u.class_of[u.order[e]] == c) ++e;
+        for (size_t k = i; k < e; ++k) {
+          part.push_back(u.order[k]);
+          box.push_back(u.box_of[u.order[k]]);
+        }
+        while (part.size() % 16) {
+          part.push_back(-1);
+          box.push_back(-1);
+        }
+        while (aop.size() < part.size() / 16) {
+          aop.push_back(c * 2 * M2_ * nf0);
+          aor.push_back(c * nf0 * 2 * M2_);
+        }
+        i = e;
+      }
+      ncols_pad_ = (int)part.size();
+      if (int rc = put_i(gcol_part_, part, err)) return rc;
+      if (int rc = put_i(gcol_box_, box, err)) return rc;
+      if (int rc = put_i(a_off_proj_, aop, err)) return rc;
+      if (int rc = put_i(a_off_recv_, aor, err)) return rc;
     }
-    std::vector<int> pb(u.order), pc(u.order.size());
-    for (size_t i = 0; i < u.order.size(); ++i) pc[i] = u.box_of[u.order[i]];
-    if (int rc = put_i(proj_part_, pb, err)) return rc;
-    if (int rc = put_i(proj_box_, pc, err)) return rc;
     if (ntl_ > 0) {
       const int M2 = M2_;
       std::vector<float> Ap((size_t)nc_ * 2 * M2 * nf, 0.f), Ar((size_t)nc_ * nf * 2 * M2, 0.f);
@@ -1193,14 +1208,6 @@ class EngineT final : public Engine {
       if (int rc = put_i(iota_, iota, err)) return rc;
     }
     return 0;
-  }
-
-  template <int RT, int CT>
-  void gemm(int M, int ncols, int nseg, int kseg, const float* A, int lda, const float* B, int ldb, const int* bcol,
-            float* C, int ldc, const int* ccol, int acc, size_t sB, size_t sC, int R, hipStream_t st) {
-    dim3 grid((M + 16 * RT - 1) / (16 * RT), (ncols + 16 * CT - 1) / (16 * CT), R);
-    hipLaunchKernelGGL((k_gemm_stream<RT, CT>), grid, dim3(kBlock), 0, st, M, ncols, nseg, kseg, A, lda, B, ldb,
-                       bcol, C, ldc, ccol, acc, sB, sC);
   }
 
   int ensure(int R, std::string& err) {
@@ -1263,113 +1270,186 @@ class EngineT final : public Engine {
     return 0;
   }
 
+  // GEMM job descriptors of the matrix-core stages (see k_gemm_stream).
+  GemmJob near_job(const CT* x, CT* y, int R) const {
+    const int nf = 2 * n_;
+    GemmJob j{};
+    j.A = A_near_.template as<float>();
+    j.B = reinterpret_cast<const float*>(x);
+    j.bcol = near_nbr_.template as<int>();
+    j.C = reinterpret_cast<float*>(y);
+    j.ccol = iota_.template as<int>();
+    j.sB = j.sC = (size_t)P_ * nf;
+    j.M = nf;
+    j.ncols = P_;
+    j.nseg = 9;
+    j.kseg = nf;
+    j.lda = 9 * nf;
+    j.ldb = j.ldc = nf;
+    j.acc = 0;
+    j.tiles_m = (nf + 16 * kRT - 1) / (16 * kRT);
+    j.tiles = j.tiles_m * ((P_ + 15) / 16);
+    (void)R;
+    return j;
+  }
+  // U0 = radiation matrix of each particle's class times x (eq. kspace_Rap)
+  GemmJob project_job(const CT* x) const {
+    const int nf = 2 * n_;
+    GemmJob j{};
+    j.A = A_proj_.template as<float>();
+    j.a_off = a_off_proj_.template as<int>();
+    j.B = reinterpret_cast<const float*>(x);
+    j.bcol = gcol_part_.template as<int>();
+    j.C = reinterpret_cast<float*>(lv_[0].S.template as<CT>());
+    j.ccol = gcol_box_.template as<int>();
+    j.sB = (size_t)P_ * nf;
+    j.sC = (size_t)lv_[0].nx * lv_[0].ny * 2 * M2_;
+    j.M = 2 * M2_;
+    j.ncols = ncols_pad_;
+    j.nseg = 1;
+    j.kseg = nf;
+    j.lda = nf;
+    j.ldb = nf;
+    j.ldc = 2 * M2_;
+    j.acc = 0;
+    j.tiles_m = (j.M + 16 * kRT - 1) / (16 * kRT);
+    j.tiles = j.tiles_m * (ncols_pad_ / 16);
+    return j;
+  }
+  // y += receiving matrix of each particle's class times G0 (eqs. Tmn_fmm, Kmn_fmm)
+  GemmJob receive_job(CT* y) const {
+    const int nf = 2 * n_;
+    GemmJob j{};
+    j.A = A_recv_.template as<float>();
+    j.a_off = a_off_recv_.template as<int>();
+    j.B = reinterpret_cast<const float*>(lv_[0].G.template as<CT>());
+    j.bcol = gcol_box_.template as<int>();
+    j.C = reinterpret_cast<float*>(y);
+    j.ccol = gcol_part_.template as<int>();
+    j.sB = (size_t)lv_[0].nx * lv_[0].ny * 2 * M2_;
+    j.sC = (size_t)P_ * nf;
+    j.M = nf;
+    j.ncols = ncols_pad_;
+    j.nseg = 1;
+    j.kseg = 2 * M2_;
+    j.lda = 2 * M2_;
+    j.ldb = 2 * M2_;
+    j.ldc = nf;
+    j.acc = 1;
+    j.tiles_m = (j.M + 16 * kRT - 1) / (16 * kRT);
+    j.tiles = j.tiles_m * (ncols_pad_ / 16);
+    j.xcd = 1;  // the row tiles of one column tile read the same G0 columns
+    return j;
+  }
+  template <int Tag>
+  void launch_gemm(Pending& pr, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
+    const int nt = j0.tiles + j1.tiles;
+    launch(pr, k_gemm_stream<kRT, 1, Tag>, dim3(j0.xcd ? xcd_grid(nt) : nt, 1, R), dim3(kBlock), 0, st, j0, j1);
+  }
+
+  // One product y = Z x: near-field apply and leaf projection (one launch on
+  // the matrix cores), aggregation up the tree, then from the top level down
+  // translation and disaggregation, and receive.
   int enqueue(const void* xv, void* yv, int R, int parts, hipStream_t st, std::string& err) {
-    cur_st_ = st;
     const CT* x = reinterpret_cast<const CT*>(xv);
     CT* y = reinterpret_cast<CT*>(yv);
     const dim3 blk(kBlock);
     const double cb = sizeof(CT);
-    if (parts & 1) {
-      begin("near", cb * ((double)2 * R * P_ * n_ + (double)nslots_ * n_ * n_),
-                       8.0 * R * nnear_ * (double)n_ * n_);
-      if (mfma_ && near_uniform_) {
-        const int nf = 2 * n_;
-        gemm<4, 1>(nf, P_, 9, nf, A_near_.template as<float>(), 9 * nf, reinterpret_cast<const float*>(x), nf,
-                    near_nbr_.template as<int>(), reinterpret_cast<float*>(y), nf, iota_.template as<int>(), 0,
-                    (size_t)P_ * nf, (size_t)P_ * nf, R, st);
-      } else {
-        launch_near(x, y, R, near_mats_.template as<CT>(), near_nbr_.template as<int>(),
-                    near_slot_.template as<int>(), near_tile_slot_.template as<int>(), 9, st);
-      }
-      end(st);
+    const bool near = parts & 1, far = (parts & 2) && ntl_ > 0;
+    const double near_bytes = cb * ((double)2 * R * P_ * n_ + (double)nslots_ * n_ * n_);
+    const double near_flops = 8.0 * R * nnear_ * (double)n_ * n_;
+    const double proj_bytes = cb * ((double)R * P_ * n_ + (double)R * P_ * M2_ + (double)nc_ * n_ * M2_);
+    const double proj_flops = 8.0 * R * P_ * (double)n_ * M2_;
+    // leaf-level pattern buffers (only when there is a far part)
+    const Lvl* L0 = far ? &lv_[0] : nullptr;
+    const int nb0 = far ? L0->nx * L0->ny : 0;
+    const GemmJob none{};
+    const bool near_mfma = mfma_ && near_uniform_;
+    if (near && far && near_mfma) {
+      auto pr = begin("near+project", near_bytes + proj_bytes, near_flops + proj_flops);
+      launch_gemm<0>(pr, near_job(x, y, R), project_job(x), R, st);
     } else {
-      const size_t cnt = (size_t)R * P_ * n_;
-      hipLaunchKernelGGL(k_fill_zero<T>, dim3(grid1d(cnt)), blk, 0, st, y, cnt);
-    }
-    if ((parts & 2) && ntl_ > 0) {
-      const Lvl& L0 = lv_[0];
-      const int nb0 = L0.nx * L0.ny;
-      {
-        dim3 grid(ntiles_, (M2_ + kProjBlock - 1) / kProjBlock, R);
-        size_t sh = (size_t)kTP * n_ * sizeof(CT);
-        begin("project", cb * ((double)R * P_ * n_ + (double)R * P_ * M2_ + (double)nc_ * n_ * M2_),
-                         8.0 * R * P_ * (double)n_ * M2_);
-        if (mfma_) {
-          const int nf = 2 * n_;
-          for (int c = 0; c < nc_; ++c)
-            if (cls_count_[c] > 0)
-              gemm<4, 2>(2 * M2_, cls_count_[c], 1, nf, A_proj_.template as<float>() + (size_t)c * 2 * M2_ * nf, nf,
-                          reinterpret_cast<const float*>(x), nf, proj_part_.template as<int>() + cls_start_[c],
-                          reinterpret_cast<float*>(L0.S.template as<CT>()), 2 * M2_,
-                          proj_box_.template as<int>() + cls_start_[c], 0, (size_t)P_ * nf, (size_t)nb0 * 2 * M2_, R,
-                          st);
-        } else {
-          hipLaunchKernelGGL((k_project<T, kTP>), grid, dim3(kProjBlock), sh, st, n_, P_, M2_, nb0, x, L0.S.template as<CT>(),
-                           Rm_.template as<CT>(), rm_off_.template as<int>(), order_.template as<int>(),
-                           tile_start_.template as<int>(), tile_count_.template as<int>(),
-                           tile_class_.template as<int>(), box_of_.template as<int>());
-              }
-        end(st);
+      if (near) {
+        auto pr = begin("near", near_bytes, near_flops);
+        if (near_mfma)
+          launch_gemm<1>(pr, near_job(x, y, R), none, R, st);
+        else
+          launch_near(pr, x, y, R, near_mats_.template as<CT>(), near_nbr_.template as<int>(),
+                      near_slot_.template as<int>(), near_tile_slot_.template as<int>(), 9, st);
+      } else {
+        const size_t cnt = (size_t)R * P_ * n_;
+        hipLaunchKernelGGL(k_fill_zero<T>, dim3(grid1d(cnt)), blk, 0, st, y, cnt);
       }
+      if (far) {
+        auto pr = begin("project", proj_bytes, proj_flops);
+        if (mfma_) {
+          launch_gemm<2>(pr, project_job(x), none, R, st);
+        } else {
+          dim3 grid(ntiles_, (M2_ + kProjBlock - 1) / kProjBlock, R);
+          size_t sh = (size_t)kTP * n_ * sizeof(CT);
+          launch(pr, k_project<T, kTP>, grid, dim3(kProjBlock), sh, st, n_, P_, M2_, nb0, x,
+                             L0->S.template as<CT>(), Rm_.template as<CT>(), rm_off_.template as<int>(),
+                             order_.template as<int>(), tile_start_.template as<int>(),
+                             tile_count_.template as<int>(), tile_class_.template as<int>(),
+                             box_of_.template as<int>());
+        }
+      }
+    }
+    if (far) {
       for (int l = 1; l < ntl_; ++l) {
         const Lvl &C = lv_[l - 1], &Pp = lv_[l];
         const Itp& I = it_[l];
         dim3 grid(Pp.nx * Pp.ny * 2, (Pp.nt + I.ts_agg - 1) / I.ts_agg, R);
         size_t sh = I.lds_agg;
-        begin("aggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
-              2.0 * R * (double)C.nx * C.ny * 2 * (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K));
-        hipLaunchKernelGGL(k_aggregate<T>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
+        auto pr = begin("aggregate_l" + std::to_string(l),
+                        cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
+                        2.0 * R * (double)C.nx * C.ny * 2 *
+                            (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K));
+        launch(pr, k_aggregate<T>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
                            Pp.np, I.ts_agg, I.crows_max, C.S.template as<CT>(), Pp.S.template as<CT>(),
                            I.th_row.template as<int>(), I.th_w.template as<T>(), I.th_flip.template as<int>(),
                            I.ph_col.template as<int>(), I.ph_w.template as<T>(), I.phase.template as<CT>(),
                            I.strip_crow.template as<int>());
-        end(st);
       }
       for (int l = ntl_ - 1; l >= 0; --l) {
         const Lvl& L = lv_[l];
-        dim3 grid(L.nx * L.ny, R, (L.K + kBlock - 1) / kBlock);
-        begin("translate_l" + std::to_string(l), cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K),
-                         16.0 * R * (double)pairs_[l] * L.K);
-        hipLaunchKernelGGL(k_translate<T>, grid, blk, 0, st, L.nx * L.ny, L.K, L.S.template as<CT>(),
-                           L.G.template as<CT>(), L.TL.template as<CT>(), L.il_cnt.template as<int>(),
-                           L.il_src.template as<int>(), L.il_off.template as<int>());
-        end(st);
+        {
+          dim3 grid(xcd_grid(L.nx * L.ny * R * ((L.K + kBlock - 1) / kBlock)));
+          auto pr = begin("translate_l" + std::to_string(l), cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K),
+                          16.0 * R * (double)pairs_[l] * L.K);
+          launch(pr, k_translate<T>, grid, blk, 0, st, L.nx * L.ny, L.K, L.S.template as<CT>(),
+                 L.G.template as<CT>(), L.TL.template as<CT>(), L.il_cnt.template as<int>(),
+                 L.il_src.template as<int>(), L.il_off.template as<int>(), R);
+        }
         if (l + 1 < ntl_) {
           const Lvl& Pp = lv_[l + 1];
           const Itp& I = it_[l + 1];
-          dim3 g2(L.nx * L.ny * 2, (L.nt + I.ts_dis - 1) / I.ts_dis, R);
+          const int nstrips = (L.nt + I.ts_dis - 1) / I.ts_dis;
+          dim3 g2(xcd_grid(L.nx * L.ny * 2 * nstrips * R));
           size_t sh = I.lds_dis;
-          begin("disaggregate_l" + std::to_string(l), cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
-                2.0 * R * (double)L.nx * L.ny * 2 * (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K));
-          hipLaunchKernelGGL(k_disaggregate<T>, g2, blk, sh, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.ny, Pp.nt, Pp.np,
+          auto pr = begin("disaggregate_l" + std::to_string(l),
+                          cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
+                          2.0 * R * (double)L.nx * L.ny * 2 *
+                              (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K));
+          launch(pr, k_disaggregate<T>, g2, blk, sh, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.ny, Pp.nt, Pp.np,
                              I.ts_dis, I.tmax, I.pmax, I.prows_max, Pp.G.template as<CT>(), L.G.template as<CT>(),
                              I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
-                             I.strip_prow.template as<int>(), I.tph_col.template as<int>(), I.tph_w.template as<T>(),
-                             I.phase.template as<CT>());
-          end(st);
+                             I.strip_prow.template as<int>(), I.tph_col.template as<int>(),
+                             I.tph_w.template as<T>(), I.phase.template as<CT>(), nstrips, R);
         }
       }
       {
-        dim3 grid(ntiles_, R);
-        size_t sh = 0;
-        begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
-                         8.0 * R * P_ * (double)n_ * M2_);
+        auto pr = begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
+                        8.0 * R * P_ * (double)n_ * M2_);
         if (mfma_) {
-          const int nf = 2 * n_;
-          for (int c = 0; c < nc_; ++c)
-            if (cls_count_[c] > 0)
-              gemm<4, 1>(nf, cls_count_[c], 1, 2 * M2_, A_recv_.template as<float>() + (size_t)c * nf * 2 * M2_,
-                          2 * M2_, reinterpret_cast<const float*>(L0.G.template as<CT>()), 2 * M2_,
-                          proj_box_.template as<int>() + cls_start_[c], reinterpret_cast<float*>(y), nf,
-                          proj_part_.template as<int>() + cls_start_[c], 1, (size_t)nb0 * 2 * M2_, (size_t)P_ * nf,
-                          R, st);
+          launch_gemm<3>(pr, receive_job(y), none, R, st);
         } else {
-          hipLaunchKernelGGL((k_receive<T, kTP>), grid, blk, sh, st, n_, P_, M2_, nb0, y, L0.G.template as<CT>(),
-                           Qm_.template as<CT>(), qm_off_.template as<int>(), order_.template as<int>(),
-                           tile_start_.template as<int>(), tile_count_.template as<int>(),
-                           tile_class_.template as<int>(), box_of_.template as<int>());
-              }
-        end(st);
+          dim3 grid(ntiles_, R);
+          launch(pr, k_receive<T, kTP>, grid, blk, 0, st, n_, P_, M2_, nb0, y, L0->G.template as<CT>(),
+                             Qm_.template as<CT>(), qm_off_.template as<int>(), order_.template as<int>(),
+                             tile_start_.template as<int>(), tile_count_.template as<int>(),
+                             tile_class_.template as<int>(), box_of_.template as<int>());
+        }
       }
     }
     HIP_TRY(hipGetLastError());
@@ -1378,23 +1458,24 @@ class EngineT final : public Engine {
 
   int precondition(const void* xv, void* yv, int R, void* stream, std::string& err) override {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    launch_near(reinterpret_cast<const CT*>(xv), reinterpret_cast<CT*>(yv), R, zinv_.template as<CT>(),
+    Pending none;
+    launch_near(none, reinterpret_cast<const CT*>(xv), reinterpret_cast<CT*>(yv), R, zinv_.template as<CT>(),
                 self_nbr_.template as<int>(), self_slot_.template as<int>(), self_tile_slot_.template as<int>(), 1, st);
     HIP_TRY(hipGetLastError());
     return 0;
   }
 
-  void launch_near(const CT* x, CT* y, int R, const CT* mats, const int* nbr, const int* slot, const int* tile_slot,
-                   int nsp, hipStream_t st) {
+  void launch_near(Pending& pr, const CT* x, CT* y, int R, const CT* mats, const int* nbr, const int* slot,
+                   const int* tile_slot, int nsp, hipStream_t st) {
     dim3 grid((P_ + kTPN - 1) / kTPN, R);
     const size_t xs_bytes = (size_t)kTPN * n_ * sizeof(CT);
     const size_t m_bytes = (size_t)n_ * n_ * sizeof(CT);
     if (xs_bytes + m_bytes <= 64 * 1024)
-      hipLaunchKernelGGL((k_near<T, kTPN, true>), grid, dim3(kBlock), xs_bytes + m_bytes, st, n_, P_, nsp, x, y, mats,
-                         nbr, slot, tile_slot);
+      launch(pr, k_near<T, kTPN, true>, grid, dim3(kBlock), (uint32_t)(xs_bytes + m_bytes), st, n_, P_, nsp, x, y,
+             mats, nbr, slot, tile_slot);
     else
-      hipLaunchKernelGGL((k_near<T, kTPN, false>), grid, dim3(kBlock), xs_bytes, st, n_, P_, nsp, x, y, mats, nbr,
-                         slot, tile_slot);
+      launch(pr, k_near<T, kTPN, false>, grid, dim3(kBlock), (uint32_t)xs_bytes, st, n_, P_, nsp, x, y, mats, nbr,
+             slot, tile_slot);
   }
 
   int rhs(const std::vector<cd>& pat, const std::vector<V3>& khat, int R, void* b, void* stream,
@@ -1459,6 +1540,7 @@ class EngineT final : public Engine {
  private:
   static constexpr int kTP = sizeof(T) == 4 ? 16 : 8;
   static constexpr int kTPN = 16;
+  static constexpr int kRT = 4;  // MFMA GEMM row tiles (of 16) per block
   static constexpr size_t kLdsBudget = 48 * 1024;
   static constexpr size_t kMinBlocks = 1024;
 
@@ -1493,8 +1575,6 @@ class EngineT final : public Engine {
   };
   std::vector<hipEvent_t> pool_;
   std::vector<Rec> rec_;
-  hipEvent_t cur_a_{};
-  hipStream_t cur_st_{};
 
   void register_stage(const std::string& name, double bytes, double flops) {
     auto it = stage_index_.find(name);
@@ -1545,20 +1625,24 @@ class EngineT final : public Engine {
   }
 
  private:
-  // Profiling: launches are bracketed by HIP events on the launch stream
-  // (direct launches only; the product is not graph-captured while
-  // profiling).
-  void begin(const std::string& name, double bytes, double flops) {
-    if (!prof_on_) return;
+  // Profiling: each stage is one kernel launch; while profiling it goes
+  // through hipExtLaunchKernel with a start and a stop event, which time the
+  // dispatch itself on the launch stream (direct launches only; the product
+  // is not graph-captured while profiling).
+  Pending begin(const std::string& name, double bytes, double flops) {
+    if (!prof_on_) return {};
     register_stage(name, bytes, flops);
-    cur_a_ = take_event();
-    (void)hipEventRecord(cur_a_, cur_st_);
+    return {cur_stage_, take_event(), take_event()};
   }
-  void end(hipStream_t st) {
-    if (!prof_on_) return;
-    hipEvent_t b = take_event();
-    (void)hipEventRecord(b, st);
-    rec_.push_back({cur_stage_, cur_a_, b});
+  template <typename F, typename... Args>
+  void launch(Pending& p, F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t st, Args... args) {
+    if (p.a) {
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, p.a, p.b, 0, args...);
+      rec_.push_back({p.stage, p.a, p.b});
+      p = Pending{};
+    } else {
+      hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+    }
   }
   hipEvent_t take_event() {
     if (!pool_.empty()) {
@@ -1578,8 +1662,9 @@ class EngineT final : public Engine {
   DevMem Rm_, Qm_, rm_off_, qm_off_;
   DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;
   bool mfma_ = false, near_uniform_ = false;
-  DevMem A_proj_, A_recv_, A_near_, proj_part_, proj_box_, iota_;
-  std::vector<int> cls_start_, cls_count_;
+  DevMem A_proj_, A_recv_, A_near_, iota_;
+  DevMem gcol_part_, gcol_box_, a_off_proj_, a_off_recv_;  // class-grouped GEMM columns
+  int ncols_pad_ = 0;
   std::vector<V3> centers_;
   int nslots_ = 0;
   long long nnear_ = 0;
