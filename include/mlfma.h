@@ -225,13 +225,18 @@ const char* mlfma_last_error(const mlfma_ctx* ctx);
  * complex), for tests.  Host-only.
  *  near_block: Z^{mu nu} for a particle of class cp observing one of class
  *    cq displaced by (dx, dy) lattice steps (dx = dy = 0 and cp == cq: the
- *    self block); out [2N][2N] row-major.  Computed on demand.
+ *    self block); out [2N][2N] row-major.  Computed on demand by host
+ *    quadrature, or after mlfma_prepare the block the product uses.
  *  leaf_pattern: receiving pattern psi_hat of class c at the finest-level
  *    directions, out [K0][2 (theta, phi)][N].
  *  level_grid: directions khat [K][3] and quadrature weights w [K] of level l.
  *  translation: T_L of eq. translation_fun at level l for the source box
  *    displaced by (dx, dy) boxes, out [K]. */
 int mlfma_debug_near_block(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_t dx, int32_t dy, double* out);
+/* The same block between distinct sites (dx, dy) != (0, 0) as
+ * mlfma_debug_near_block, assembled by the GPU quadrature that prepare uses
+ * (FP64; needs a GPU).  out: [2N][2N] complex row-major. */
+int mlfma_debug_pair_block_device(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_t dx, int32_t dy, double* out);
 int mlfma_debug_leaf_pattern(mlfma_ctx* ctx, int32_t c, double* out);
 int mlfma_debug_level_grid(mlfma_ctx* ctx, int32_t level, double* khat, double* w);
 int mlfma_debug_translation(mlfma_ctx* ctx, int32_t level, int32_t dx, int32_t dy, double* out);

@@ -6,6 +6,7 @@
 
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <new>
 #include <stdexcept>
@@ -108,6 +109,37 @@ const std::vector<cd>& near_block(mlfma_ctx* ctx, int cp, int cq, int dx, int dy
   return ctx->near_cache[key] = assemble_pair(T, K, N);
 }
 
+// Computes on the GPU every block between distinct particles in `keys` that
+// neither the cache nor its reciprocal partner already holds.
+int device_pair_blocks(mlfma_ctx* ctx, const std::vector<NearKey>& keys) {
+  std::vector<NearKey> todo;
+  std::set<NearKey> seen;
+  for (const NearKey& key : keys) {
+    const auto [cp, cq, dx, dy] = key;
+    if (dx == 0 && dy == 0) continue;
+    const NearKey rev{cq, cp, -dx, -dy};
+    if (ctx->near_cache.count(key) || ctx->near_cache.count(rev) || seen.count(key) || seen.count(rev)) continue;
+    seen.insert(key);
+    todo.push_back(key);
+  }
+  if (todo.empty()) return MLFMA_OK;
+  std::vector<PairSamples> smp(ctx->C);
+  for (int c = 0; c < ctx->C; ++c)
+    if (ctx->classes[c].set) smp[c] = {&ctx->classes[c].mesh.qp, &ctx->classes[c].mesh.qw, &ctx->classes[c].smp.val,
+                                       ctx->N};
+  std::vector<PairRequest> req;
+  const double s = ctx->tp.leaf_size;
+  for (const NearKey& key : todo) {
+    const auto [cp, cq, dx, dy] = key;
+    req.push_back({cp, cq, V3{dx * s, dy * s, 0.0}});
+  }
+  std::vector<std::vector<cd>> T, K;
+  std::string err;
+  if (int rc = gpu_pair_blocks(smp, req, kK0, T, K, err)) return fail(ctx, rc == -1 ? MLFMA_EINVAL : rc, err);
+  for (size_t i = 0; i < todo.size(); ++i) ctx->near_cache[todo[i]] = assemble_pair(T[i], K[i], ctx->N);
+  return MLFMA_OK;
+}
+
 std::vector<cd> transpose(const std::vector<cd>& A, int n) {
   std::vector<cd> B((size_t)n * n);
   for (int i = 0; i < n; ++i)
@@ -149,6 +181,23 @@ int do_prepare(mlfma_ctx* ctx) {
       u.tile_class.push_back(c);
     }
     u.order.insert(u.order.end(), mem.begin(), mem.end());
+  }
+  // near blocks between distinct particles: assembled on the GPU in one pass
+  {
+    std::vector<NearKey> keys;
+    for (int p = 0; p < ctx->P; ++p) {
+      const int ix = ctx->box_of[p] % ctx->nx, iy = ctx->box_of[p] / ctx->nx;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int jx = ix + dx, jy = iy + dy;
+          if ((dx == 0 && dy == 0) || jx < 0 || jy < 0 || jx >= ctx->nx || jy >= ctx->ny) continue;
+          const int q = ctx->part_of_box[jy * ctx->nx + jx];
+          if (q >= 0) keys.push_back(NearKey{ctx->cls[p], ctx->cls[q], dx, dy});
+        }
+    }
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    if (int rc = device_pair_blocks(ctx, keys)) return rc;
   }
   // near blocks and slots
   std::map<NearKey, int> slot_of;
@@ -581,6 +630,25 @@ int mlfma_debug_near_block(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_t dx, i
     if (!ctx->classes[cp].set || !ctx->classes[cq].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
     if (dx == 0 && dy == 0 && cp != cq) return fail(ctx, MLFMA_EINVAL, "two classes on one site");
     const auto& Z = near_block(ctx, cp, cq, dx, dy);
+    std::memcpy(out, Z.data(), Z.size() * sizeof(cd));
+    return MLFMA_OK;
+  });
+}
+
+int mlfma_debug_pair_block_device(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_t dx, int32_t dy, double* out) {
+  if (!ctx || !out) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    if (cp < 0 || cq < 0 || cp >= ctx->C || cq >= ctx->C) return fail(ctx, MLFMA_EINVAL, "class out of range");
+    if (!ctx->classes[cp].set || !ctx->classes[cq].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
+    if (dx == 0 && dy == 0) return fail(ctx, MLFMA_EINVAL, "not a pair of distinct sites");
+    std::vector<PairSamples> smp(ctx->C);
+    for (int c : {cp, cq}) smp[c] = {&ctx->classes[c].mesh.qp, &ctx->classes[c].mesh.qw, &ctx->classes[c].smp.val, ctx->N};
+    const double s = ctx->tp.leaf_size;
+    std::vector<std::vector<cd>> T, K;
+    std::string err;
+    if (int rc = gpu_pair_blocks(smp, {PairRequest{cp, cq, V3{dx * s, dy * s, 0.0}}}, kK0, T, K, err))
+      return fail(ctx, rc == -1 ? MLFMA_EINVAL : rc, err);
+    const auto Z = assemble_pair(T[0], K[0], ctx->N);
     std::memcpy(out, Z.data(), Z.size() * sizeof(cd));
     return MLFMA_OK;
   });

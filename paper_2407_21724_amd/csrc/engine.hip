@@ -287,6 +287,22 @@ __global__ __launch_bounds__(kBlock) void k_gemm_stream(GemmJob j0, GemmJob j1) 
     }
 }
 
+// y[r][p][:] = sum over the neighbours o of p of partial[r][o * P + p][:]
+// (nf floats per particle), in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_near_sum(int P, int nf, const float* __restrict__ partial,
+                                                      const int* __restrict__ has, float* __restrict__ y) {
+  const size_t cnt = (size_t)P * nf;
+  const int r = blockIdx.y;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock) {
+    const int p = (int)(i / nf), m = (int)(i - (size_t)p * nf);
+    const float* pr = partial + (size_t)r * 9 * cnt;
+    float acc = 0.f;
+    for (int o = 0; o < 9; ++o)
+      if (has[p * 9 + o]) acc += pr[((size_t)o * P + p) * nf + m];
+    y[(size_t)r * cnt + i] = acc;
+  }
+}
+
 // ------------------------------------------------------- leaf projection --
 // U[r][box(p)][m] = sum_j Rm[class][j][m] x[r][p][j] for a tile of up to TP
 // particles of one class; one thread per pattern sample m (blocks of 128
@@ -394,21 +410,23 @@ __device__ __forceinline__ int fdiv(int i, float inv_d) { return (int)(((float)i
 
 // S_p[r][P][c][s] = sum over children q: phase_q(s) * (Phi Theta S_child)(s).
 // Block = (parent box, component) x strip of ts parent rows x RHS.  The
-// strip's stencil tables and the needed rows [crow_lo, crow_hi] of all four
-// children (contiguous in each child pattern) are staged in LDS at once;
-// the theta pass writes tmp [4][ts][np_c]; each thread owns up to kAggVPT
-// outputs of the strip and sums the four children in registers.
+// strip's stencil tables and the needed rows [crow_lo, crow_hi] of the
+// children (contiguous in each child pattern) are staged in LDS, all four
+// children at once or, where that does not fit (the largest boxes), one
+// child per pass (nstage = 1); the theta pass writes tmp [nstage][ts][np_c];
+// each thread owns up to kAggVPT outputs of the strip and sums the children
+// in registers.
 constexpr int kAggVPT = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_aggregate(
     int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int crows_max,
     const C2<T>* __restrict__ Sc, C2<T>* __restrict__ Sp, const int* __restrict__ th_row,
     const T* __restrict__ th_w, const int* __restrict__ th_flip, const int* __restrict__ ph_col,
-    const T* __restrict__ ph_w, const C2<T>* __restrict__ phase, const int* __restrict__ strip_crow) {
+    const T* __restrict__ ph_w, const C2<T>* __restrict__ phase, const int* __restrict__ strip_crow, int nstage) {
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* cbuf = reinterpret_cast<C2<T>*>(smem_raw);  // [4][crows_max][npc]
-  C2<T>* tmp = cbuf + (size_t)4 * crows_max * npc;    // [4][ts][npc]
-  T* thw = reinterpret_cast<T*>(tmp + (size_t)4 * ts * npc);
+  C2<T>* cbuf = reinterpret_cast<C2<T>*>(smem_raw);        // [nstage][crows_max][npc]
+  C2<T>* tmp = cbuf + (size_t)nstage * crows_max * npc;    // [nstage][ts][npc]
+  T* thw = reinterpret_cast<T*>(tmp + (size_t)nstage * ts * npc);
   T* phw = thw + ts * order;
   int* thr = reinterpret_cast<int*>(phw + npp * order);  // child row relative to crow_lo; -1-row if flipped
   int* phc = thr + ts * order;
@@ -432,53 +450,59 @@ __global__ __launch_bounds__(kBlock) void k_aggregate(
     phw[i] = ph_w[i];
     phc[i] = ph_col[i];
   }
-  const int cs = crows * npc;
-  for (int i = threadIdx.x; i < 4 * cs; i += kBlock) {
-    const int q = fdiv(i, inv_cs), j = i - q * cs;
-    const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
-    cbuf[q * crows_max * npc + j] =
-        (ci < nxc && cj < nyc) ? Sc[(((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc + (size_t)clo * npc + j]
-                               : C2<T>{0, 0};
-  }
-  __syncthreads();
-  const int tsz = nrow * npc;
-  for (int i = threadIdx.x; i < 4 * tsz; i += kBlock) {
-    const int q = fdiv(i, inv_ts), j = i - q * tsz;
-    const int row = fdiv(j, inv_npc), col = j - row * npc;
-    const int colf = col + half < npc ? col + half : col + half - npc;
-    const C2<T>* cq = cbuf + q * crows_max * npc;
-    C2<T> v{0, 0};
-    for (int a = 0; a < order; ++a) {
-      const int rr = thr[row * order + a];
-      const T w = thw[row * order + a];
-      const C2<T> sv = rr >= 0 ? cq[rr * npc + col] : cq[(-1 - rr) * npc + colf];
-      v.x += w * sv.x;
-      v.y += w * sv.y;
+  const int cs = crows * npc, tsz = nrow * npc, nout = nrow * npp;
+  C2<T> acc[kAggVPT];
+#pragma unroll
+  for (int vv = 0; vv < kAggVPT; ++vv) acc[vv] = C2<T>{0, 0};
+  for (int q0 = 0; q0 < 4; q0 += nstage) {
+    if (q0 > 0) __syncthreads();  // the previous pass has finished with cbuf and tmp
+    for (int i = threadIdx.x; i < nstage * cs; i += kBlock) {
+      const int qs = fdiv(i, inv_cs), j = i - qs * cs, q = q0 + qs;
+      const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
+      cbuf[qs * crows_max * npc + j] =
+          (ci < nxc && cj < nyc) ? Sc[(((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc + (size_t)clo * npc + j]
+                                 : C2<T>{0, 0};
     }
-    tmp[q * ts * npc + j] = v;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nstage * tsz; i += kBlock) {
+      const int qs = fdiv(i, inv_ts), j = i - qs * tsz;
+      const int row = fdiv(j, inv_npc), col = j - row * npc;
+      const int colf = col + half < npc ? col + half : col + half - npc;
+      const C2<T>* cq = cbuf + qs * crows_max * npc;
+      C2<T> v{0, 0};
+      for (int a = 0; a < order; ++a) {
+        const int rr = thr[row * order + a];
+        const T w = thw[row * order + a];
+        const C2<T> sv = rr >= 0 ? cq[rr * npc + col] : cq[(-1 - rr) * npc + colf];
+        v.x += w * sv.x;
+        v.y += w * sv.y;
+      }
+      tmp[qs * ts * npc + j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int vv = 0; vv < kAggVPT; ++vv) {
+      const int i = threadIdx.x + vv * kBlock;
+      if (i >= nout) continue;
+      const int row = fdiv(i, inv_npp), ip = i - row * npp;
+      for (int qs = 0; qs < nstage; ++qs) {
+        C2<T> sv{0, 0};
+        const C2<T>* tq = tmp + qs * ts * npc + row * npc;
+        for (int b = 0; b < order; ++b) {
+          const T w = phw[ip * order + b];
+          const C2<T> t = tq[phc[ip * order + b]];
+          sv.x += w * t.x;
+          sv.y += w * t.y;
+        }
+        cfma(acc[vv], phase[(size_t)(q0 + qs) * Kp + (size_t)(r0 + row) * npp + ip], sv);
+      }
+    }
   }
-  __syncthreads();
-  const int nout = nrow * npp;
   C2<T>* __restrict__ dst = Sp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)r0 * npp;
 #pragma unroll
   for (int vv = 0; vv < kAggVPT; ++vv) {
     const int i = threadIdx.x + vv * kBlock;
-    if (i >= nout) continue;
-    const int row = fdiv(i, inv_npp), ip = i - row * npp;
-    C2<T> acc{0, 0};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      C2<T> sv{0, 0};
-      const C2<T>* tq = tmp + q * ts * npc + row * npc;
-      for (int b = 0; b < order; ++b) {
-        const T w = phw[ip * order + b];
-        const C2<T> t = tq[phc[ip * order + b]];
-        sv.x += w * t.x;
-        sv.y += w * t.y;
-      }
-      cfma(acc, phase[(size_t)q * Kp + (size_t)(r0 + row) * npp + ip], sv);
-    }
-    dst[i] = acc;
+    if (i < nout) dst[i] = acc[vv];
   }
 }
 
@@ -890,7 +914,7 @@ class EngineT final : public Engine {
     DevMem S, G;  // pattern buffers, sized for R_alloc
   };
   struct Itp {
-    int order, tmax, pmax, ts_agg, ts_dis, crows_max, prows_max;
+    int order, tmax, pmax, ts_agg, ts_dis, crows_max, prows_max, agg_stage;
     size_t lds_dis, lds_agg;
     DevMem strip_crow, strip_prow;
     DevMem th_row, th_w, th_flip, ph_col, ph_w, tth_row, tth_w, tth_flip, tth_lo, tth_hi, tph_col, tph_w, phase;
@@ -966,6 +990,7 @@ class EngineT final : public Engine {
         return -1;
       }
       const int order = T0.order;
+      int nstage = 4;  // children staged per pass
       auto agg_plan = [&](int ts, std::vector<int>& rng, int& cmax) {
         rng.clear();
         cmax = 0;
@@ -980,7 +1005,7 @@ class EngineT final : public Engine {
           rng.push_back(hi);
           cmax = std::max(cmax, hi - lo + 1);
         }
-        return (size_t)4 * (cmax + ts) * C.np * sizeof(CT) + (size_t)ts * order * (sizeof(T) + 4) +
+        return (size_t)nstage * (cmax + ts) * C.np * sizeof(CT) + (size_t)ts * order * (sizeof(T) + 4) +
                (size_t)Pp.np * order * (sizeof(T) + 4);
       };
       // strip height: bounded by the per-thread outputs; split further only
@@ -991,11 +1016,16 @@ class EngineT final : public Engine {
       int cmax = 0;
       size_t lds = agg_plan(ts, rng, cmax);
       while (ts > 1 && lds > kLdsBudget) lds = agg_plan(--ts, rng, cmax);
-      if (lds > kLdsBudget) {
-        err = "aggregation tile exceeds the LDS budget at level " + std::to_string(l);
+      if (lds > kLdsBudget) {  // largest boxes: one child per pass
+        nstage = 1;
+        lds = agg_plan(ts, rng, cmax);
+      }
+      if (lds > kLdsMax) {
+        err = "aggregation tile exceeds the LDS limit at level " + std::to_string(l);
         return -1;
       }
       I.ts_agg = ts;
+      I.agg_stage = nstage;
       I.crows_max = cmax;
       I.lds_agg = lds;
       if (int rc = put_i(I.strip_crow, rng, err)) return rc;
@@ -1023,8 +1053,8 @@ class EngineT final : public Engine {
       int pmr = 0;
       size_t ldsd = dis_plan(tsd, prng, pmr);
       while (tsd > 1 && ldsd > kLdsBudget) ldsd = dis_plan(--tsd, prng, pmr);
-      if (ldsd > kLdsBudget) {
-        err = "disaggregation tile exceeds the LDS budget at level " + std::to_string(l);
+      if (ldsd > kLdsMax) {
+        err = "disaggregation tile exceeds the LDS limit at level " + std::to_string(l);
         return -1;
       }
       I.ts_dis = tsd;
@@ -1206,8 +1236,74 @@ class EngineT final : public Engine {
       std::vector<int> iota(P_);
       for (int p = 0; p < P_; ++p) iota[p] = p;
       if (int rc = put_i(iota_, iota, err)) return rc;
+    } else {
+      // class-pair blocks differ between particles: one GEMM column per
+      // (particle, neighbour) pair, grouped by block (slot) and padded to
+      // whole 16-column tiles, each tile multiplying its slot's matrix; the
+      // products land in partial[(o * P + p)] and k_near_sum adds the nine.
+      const int ns = (int)u.near_mats.size();
+      std::vector<float> Aall((size_t)ns * nf * nf, 0.f);
+      for (int sl2 = 0; sl2 < ns; ++sl2) {
+        const cd* Zt = u.near_mats[sl2].data();
+        std::vector<float> a((size_t)nf * nf, 0.f);
+        for (int j = 0; j < n; ++j)
+          for (int k = 0; k < n; ++k) block2(a, nf, 2 * j, 2 * k, Zt[(size_t)k * n + j]);
+        std::copy(a.begin(), a.end(), Aall.begin() + (size_t)sl2 * nf * nf);
+      }
+      std::vector<std::vector<std::pair<int, int>>> by_slot(ns);  // (neighbour q, o * P + p)
+      for (int p = 0; p < P_; ++p)
+        for (int o = 0; o < 9; ++o) {
+          const int q = u.near_nbr[(size_t)p * 9 + o];
+          if (q >= 0) by_slot[u.near_slot[(size_t)p * 9 + o]].push_back({q, o * P_ + p});
+        }
+      std::vector<int> bq, cq, aoff;
+      for (int sl2 = 0; sl2 < ns; ++sl2) {
+        if (by_slot[sl2].empty()) continue;
+        for (auto& e : by_slot[sl2]) {
+          bq.push_back(e.first);
+          cq.push_back(e.second);
+        }
+        while (bq.size() % 16) {
+          bq.push_back(-1);
+          cq.push_back(-1);
+        }
+        while (aoff.size() < bq.size() / 16) aoff.push_back(sl2 * nf * nf);
+      }
+      ngcols_ = (int)bq.size();
+      if (int rc = put_f(A_near_, Aall)) return rc;
+      if (int rc = put_i(ng_bcol_, bq, err)) return rc;
+      if (int rc = put_i(ng_ccol_, cq, err)) return rc;
+      if (int rc = put_i(ng_aoff_, aoff, err)) return rc;
+      std::vector<int> has((size_t)P_ * 9);
+      for (size_t i = 0; i < has.size(); ++i) has[i] = u.near_nbr[i] >= 0;
+      if (int rc = put_i(ng_has_, has, err)) return rc;
     }
     return 0;
+  }
+
+  // near-field products of the class-pair GEMM: partial[r][o * P + p][:]
+  GemmJob near_group_job(const CT* x) const {
+    const int nf = 2 * n_;
+    GemmJob j{};
+    j.A = A_near_.template as<float>();
+    j.a_off = ng_aoff_.template as<int>();
+    j.B = reinterpret_cast<const float*>(x);
+    j.bcol = ng_bcol_.template as<int>();
+    j.C = near_part_.template as<float>();
+    j.ccol = ng_ccol_.template as<int>();
+    j.sB = (size_t)P_ * nf;
+    j.sC = (size_t)9 * P_ * nf;
+    j.M = nf;
+    j.ncols = ngcols_;
+    j.nseg = 1;
+    j.kseg = nf;
+    j.lda = nf;
+    j.ldb = nf;
+    j.ldc = nf;
+    j.acc = 0;
+    j.tiles_m = (nf + 16 * kRT - 1) / (16 * kRT);
+    j.tiles = j.tiles_m * (ngcols_ / 16);
+    return j;
   }
 
   int ensure(int R, std::string& err) {
@@ -1220,6 +1316,7 @@ class EngineT final : public Engine {
       HIP_TRY(hipMemset(L.S.p, 0, bytes));  // empty leaf boxes stay zero
       HIP_TRY(hipMemset(L.G.p, 0, bytes));
     }
+    if (mfma_ && !near_uniform_) HIP_TRY(near_part_.alloc((size_t)R * 9 * P_ * 2 * n_ * sizeof(float)));
     HIP_TRY(hipDeviceSynchronize());
     R_alloc_ = R;
     return 0;
@@ -1364,16 +1461,24 @@ class EngineT final : public Engine {
     const Lvl* L0 = far ? &lv_[0] : nullptr;
     const int nb0 = far ? L0->nx * L0->ny : 0;
     const GemmJob none{};
-    const bool near_mfma = mfma_ && near_uniform_;
-    if (near && far && near_mfma) {
+    const bool near_mfma = mfma_ && near_uniform_, near_grouped = mfma_ && !near_uniform_;
+    auto near_sum = [&]() {
+      const int nf = 2 * n_;
+      auto pr = begin("near_sum", 4.0 * R * (9.0 + 1.0) * P_ * nf, 0.0);
+      launch(pr, k_near_sum, dim3(std::min(grid1d((size_t)P_ * nf), 2048), R), blk, 0, st, P_, nf,
+             (const float*)near_part_.template as<float>(), (const int*)ng_has_.template as<int>(),
+             reinterpret_cast<float*>(y));
+    };
+    if (near && far && (near_mfma || near_grouped)) {
       auto pr = begin("near+project", near_bytes + proj_bytes, near_flops + proj_flops);
-      launch_gemm<0>(pr, near_job(x, y, R), project_job(x), R, st);
+      launch_gemm<0>(pr, near_grouped ? near_group_job(x) : near_job(x, y, R), project_job(x), R, st);
     } else {
       if (near) {
         auto pr = begin("near", near_bytes, near_flops);
-        if (near_mfma)
-          launch_gemm<1>(pr, near_job(x, y, R), none, R, st);
-        else
+        if (near_mfma || near_grouped) {
+          launch_gemm<1>(pr, near_grouped ? near_group_job(x) : near_job(x, y, R), none, R, st);
+          if (near_grouped) near_sum();
+        } else
           launch_near(pr, x, y, R, near_mats_.template as<CT>(), near_nbr_.template as<int>(),
                       near_slot_.template as<int>(), near_tile_slot_.template as<int>(), 9, st);
       } else {
@@ -1409,7 +1514,7 @@ class EngineT final : public Engine {
                            Pp.np, I.ts_agg, I.crows_max, C.S.template as<CT>(), Pp.S.template as<CT>(),
                            I.th_row.template as<int>(), I.th_w.template as<T>(), I.th_flip.template as<int>(),
                            I.ph_col.template as<int>(), I.ph_w.template as<T>(), I.phase.template as<CT>(),
-                           I.strip_crow.template as<int>());
+                           I.strip_crow.template as<int>(), I.agg_stage);
       }
       for (int l = ntl_ - 1; l >= 0; --l) {
         const Lvl& L = lv_[l];
@@ -1438,6 +1543,7 @@ class EngineT final : public Engine {
                              I.tph_w.template as<T>(), I.phase.template as<CT>(), nstrips, R);
         }
       }
+      if (near && near_grouped) near_sum();
       {
         auto pr = begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
                         8.0 * R * P_ * (double)n_ * M2_);
@@ -1541,7 +1647,8 @@ class EngineT final : public Engine {
   static constexpr int kTP = sizeof(T) == 4 ? 16 : 8;
   static constexpr int kTPN = 16;
   static constexpr int kRT = 4;  // MFMA GEMM row tiles (of 16) per block
-  static constexpr size_t kLdsBudget = 48 * 1024;
+  static constexpr size_t kLdsBudget = 48 * 1024;  // preferred tile size (occupancy)
+  static constexpr size_t kLdsMax = 64 * 1024;     // hard limit per block
   static constexpr size_t kMinBlocks = 1024;
 
   template <typename U>
@@ -1664,6 +1771,8 @@ class EngineT final : public Engine {
   bool mfma_ = false, near_uniform_ = false;
   DevMem A_proj_, A_recv_, A_near_, iota_;
   DevMem gcol_part_, gcol_box_, a_off_proj_, a_off_recv_;  // class-grouped GEMM columns
+  DevMem ng_bcol_, ng_ccol_, ng_aoff_, ng_has_, near_part_;  // class-pair near GEMM
+  int ngcols_ = 0;
   int ncols_pad_ = 0;
   std::vector<V3> centers_;
   int nslots_ = 0;
@@ -1914,11 +2023,317 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
   return 0;
 }
 
+// ------------------------------------------------ device pair assembly --
+// Galerkin blocks between separated particles (Sec. II.A entries of
+// Z^{pq}, exterior medium), FP64.  For observation points a and source
+// points b the sums
+//   SG[a][f][n] = sum_b w_b g(R_ab) v_b[f][n]            f: psi x,y,z, div
+//   SH[a][f][n] = sum_b w_b h(R_ab) v_b[f'][n]           f': psi, psi x r_b
+// with g = exp(-jkR)/(4 pi R) and grad g = h (r_a - r_b), are a complex-by-
+// real matrix product whose left operand is generated on the fly: an FP64
+// MFMA GEMM (16 observation points x 4 source points per step, the lane
+// that holds A[i][k] evaluates g and h for that point pair).  Lane layout of
+// v_mfma_f64_16x16x4f64: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k,
+// result register v of lane l is row l/16 + 4v, column l % 16.  A second pass
+// contracts the sums with the observation functions into T and K.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kPairWaves = 4;
+constexpr int kPairTPW = 8;  // column tiles per wave: 10 * npad / 16 <= 32, i.e. N <= 48
+
+struct PairJobDev {
+  const double* qa;  // [Qa][3] observation points
+  const double* wa;  // [Qa] observation weights
+  const double* va;  // [Qa][7][Na] observation values
+  const double* qb;  // [Qb][3] source points (local to the source particle)
+  const double* Vb;  // [Qb][ncol] source values with the source weight folded in
+  double* acc;       // [Qa][ncol][2] sums (re, im)
+  double ox, oy, oz; // source centre relative to the observation centre
+  int Qa, Qb, Na;
+};
+
+__global__ __launch_bounds__(kPairWaves * 64) void k_pair_sums(const PairJobDev* __restrict__ jobs, int npad,
+                                                                double k) {
+  __shared__ double gh[2][kPairWaves][4][64];  // [buffer][b-step][g re, g im, h re, h im][lane]
+  const PairJobDev J = jobs[blockIdx.y];
+  const int a0 = blockIdx.x * 16;
+  if (a0 >= J.Qa) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  const int ntile = 10 * npad / 16, ntg = 4 * npad / 16, ncol = 16 * ntile;
+  const int a = a0 + i;
+  double xa = 0, ya = 0, za = 0;
+  if (a < J.Qa) {
+    xa = J.qa[3 * a] - J.ox;
+    ya = J.qa[3 * a + 1] - J.oy;
+    za = J.qa[3 * a + 2] - J.oz;
+  }
+  f64x4 accr[kPairTPW], acci[kPairTPW];
+#pragma unroll
+  for (int t = 0; t < kPairTPW; ++t) {
+    accr[t] = f64x4{0, 0, 0, 0};
+    acci[t] = f64x4{0, 0, 0, 0};
+  }
+  const double inv4pi = 1.0 / (4.0 * 3.14159265358979323846);
+  int buf = 0;
+  // each iteration covers 4 * kPairWaves source points: wave w evaluates the
+  // kernel for b-step w into LDS, then every wave runs all kPairWaves steps
+  for (int b0 = 0; b0 < J.Qb; b0 += 4 * kPairWaves, buf ^= 1) {
+    {
+      const int b = b0 + 4 * wave + kq;
+      double gr = 0, gi = 0, hr = 0, hi = 0;
+      if (a < J.Qa && b < J.Qb) {
+        const double dx = xa - J.qb[3 * b], dy = ya - J.qb[3 * b + 1], dz = za - J.qb[3 * b + 2];
+        const double R = sqrt(dx * dx + dy * dy + dz * dz);
+        const double kR = k * R;
+        double sn, cs;
+        sincos(kR, &sn, &cs);
+        const double inv = inv4pi / R, inv3 = inv / (R * R);
+        gr = cs * inv;
+        gi = -sn * inv;
+        hr = -(cs + kR * sn) * inv3;
+        hi = -(kR * cs - sn) * inv3;
+      }
+      gh[buf][wave][0][lane] = gr;
+      gh[buf][wave][1][lane] = gi;
+      gh[buf][wave][2][lane] = hr;
+      gh[buf][wave][3][lane] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < kPairWaves; ++st) {
+      const int b = b0 + 4 * st + kq;
+      const double gr = gh[buf][st][0][lane], gi = gh[buf][st][1][lane];
+      const double hr = gh[buf][st][2][lane], hi = gh[buf][st][3][lane];
+      const double* __restrict__ vrow = J.Vb + (size_t)(b < J.Qb ? b : 0) * ncol;
+#pragma unroll
+      for (int t = 0; t < kPairTPW; ++t) {
+        const int jt = wave + kPairWaves * t;
+        if (jt < ntile) {
+          const double bv = b < J.Qb ? vrow[jt * 16 + i] : 0.0;
+          const bool isg = jt < ntg;
+          accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(isg ? gr : hr, bv, accr[t], 0, 0, 0);
+          acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(isg ? gi : hi, bv, acci[t], 0, 0, 0);
+        }
+      }
+    }
+    // the buffer written next iteration was last read before this barrier
+  }
+#pragma unroll
+  for (int t = 0; t < kPairTPW; ++t) {
+    const int jt = wave + kPairWaves * t;
+    if (jt >= ntile) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ar = a0 + kq + 4 * v;  // FP64 16x16x4 result: register v of lane l is row l/16 + 4v
+      if (ar < J.Qa) {
+        double* o = J.acc + ((size_t)ar * ncol + jt * 16 + i) * 2;
+        o[0] = accr[t][v];
+        o[1] = acci[t][v];
+      }
+    }
+  }
+}
+
+// T[m][n] = sum_a w_a (-jk psi_m . SG[0..2] + (j/k) div psi_m SG[3])
+// K[m][n] = sum_a w_a (r_a x psi_m . SH[0..2] - psi_m . (SH[3..5] + SH[0..2] x offset))
+// Block = (source function n, job); threads stride over a; 8 observation
+// functions per pass.
+constexpr int kPairMC = 8;
+__global__ __launch_bounds__(kBlock) void k_pair_contract(const PairJobDev* __restrict__ jobs, int npad, double k,
+                                                           double* __restrict__ TK) {
+  const PairJobDev J = jobs[blockIdx.y];
+  const int n = blockIdx.x;
+  const int Na = J.Na, ncol = 10 * npad;
+  __shared__ double red[kBlock / 64][4 * kPairMC];
+  for (int m0 = 0; m0 < Na; m0 += kPairMC) {
+    double acc[4 * kPairMC];  // T re, T im, K re, K im per m
+#pragma unroll
+    for (int q = 0; q < 4 * kPairMC; ++q) acc[q] = 0;
+    for (int a = threadIdx.x; a < J.Qa; a += kBlock) {
+      const double* s = J.acc + (size_t)a * ncol * 2;
+      double g[4][2], h[6][2];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        g[f][0] = s[(f * npad + n) * 2];
+        g[f][1] = s[(f * npad + n) * 2 + 1];
+      }
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        h[f][0] = s[((4 + f) * npad + n) * 2];
+        h[f][1] = s[((4 + f) * npad + n) * 2 + 1];
+      }
+      // psi_q x r_b with r_b measured from the observation centre
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double ux = h[0][c], uy = h[1][c], uz = h[2][c];
+        h[3][c] += uy * J.oz - uz * J.oy;
+        h[4][c] += uz * J.ox - ux * J.oz;
+        h[5][c] += ux * J.oy - uy * J.ox;
+      }
+      const double w = J.wa[a];
+      const double rx = J.qa[3 * a], ry = J.qa[3 * a + 1], rz = J.qa[3 * a + 2];
+      const double* va = J.va + (size_t)a * 7 * Na;
+#pragma unroll
+      for (int mm = 0; mm < kPairMC; ++mm) {
+        const int m = m0 + mm;
+        if (m >= Na) break;
+        const double px = va[m], py = va[Na + m], pz = va[2 * Na + m], dm = va[3 * Na + m];
+        const double qx = ry * pz - rz * py, qy = rz * px - rx * pz, qz = rx * py - ry * px;  // r_a x psi_m
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const double vec = px * g[0][c] + py * g[1][c] + pz * g[2][c];
+          const double dv = dm * g[3][c];
+          const double ku = qx * h[0][c] + qy * h[1][c] + qz * h[2][c] - (px * h[3][c] + py * h[4][c] + pz * h[5][c]);
+          // T: -jk vec + (j/k) dv  ->  (re, im) contributions
+          if (c == 0) {
+            acc[4 * mm + 1] += w * (-k * vec + dv / k);
+            acc[4 * mm + 2] += w * ku;
+          } else {
+            acc[4 * mm + 0] += w * (k * vec - dv / k);
+            acc[4 * mm + 3] += w * ku;
+          }
+        }
+      }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 4 * kPairMC; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 * kPairMC) {
+      const int q = threadIdx.x, mm = q / 4, part = q % 4;
+      const int m = m0 + mm;
+      if (m < Na) {
+        double v = 0;
+        for (int w2 = 0; w2 < kBlock / 64; ++w2) v += red[w2][q];
+        // TK layout per job: [2 (T, K)][Na][Na][2 (re, im)]
+        const int which = part / 2, ri = part % 2;
+        TK[(((size_t)blockIdx.y * 2 + which) * Na * Na + (size_t)m * Na + n) * 2 + ri] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 Engine* make_engine(int precision) {
   if (precision == 1) return new EngineT<double>();
   return new EngineT<float>();
+}
+
+int gpu_pair_blocks(const std::vector<PairSamples>& cls, const std::vector<PairRequest>& req, double k,
+                    std::vector<std::vector<cd>>& T, std::vector<std::vector<cd>>& K, std::string& err) {
+  T.assign(req.size(), {});
+  K.assign(req.size(), {});
+  if (req.empty()) return 0;
+  int N = -1;
+  for (const auto& c : cls)
+    if (c.val) N = std::max(N, c.N);
+  const int npad = (N + 15) / 16 * 16;
+  if (10 * npad / 16 > kPairWaves * kPairTPW) {
+    err = "device pair assembly supports at most 48 functions per class";
+    return -1;
+  }
+  const int ncol = 10 * npad;
+  // per-class device samples
+  struct Dev {
+    DevMem qp, qw, val, Vb;
+    int Q = 0;
+  };
+  std::vector<Dev> dev(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) {
+    const PairSamples& S = cls[c];
+    if (!S.val) continue;
+    if (S.N != N) {
+      err = "pair assembly: classes differ in their number of functions";
+      return -1;
+    }
+    const int Q = (int)S.qp->size();
+    std::vector<double> qp((size_t)Q * 3), Vb((size_t)Q * ncol, 0.0);
+    for (int q = 0; q < Q; ++q) {
+      qp[3 * q] = (*S.qp)[q].x;
+      qp[3 * q + 1] = (*S.qp)[q].y;
+      qp[3 * q + 2] = (*S.qp)[q].z;
+      const double w = (*S.qw)[q];
+      const double* v = &(*S.val)[(size_t)q * 7 * N];
+      double* o = &Vb[(size_t)q * ncol];
+      for (int n = 0; n < N; ++n) {
+        for (int f = 0; f < 4; ++f) o[f * npad + n] = w * v[f * N + n];
+        for (int f = 0; f < 3; ++f) o[(4 + f) * npad + n] = w * v[f * N + n];
+        for (int f = 0; f < 3; ++f) o[(7 + f) * npad + n] = w * v[(4 + f) * N + n];
+      }
+    }
+    Dev& d = dev[c];
+    d.Q = Q;
+    auto put = [&](DevMem& m, const std::vector<double>& h) -> hipError_t {
+      hipError_t e = m.alloc(h.size() * sizeof(double));
+      if (e == hipSuccess) e = hipMemcpy(m.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+      return e;
+    };
+    HIP_TRY(put(d.qp, qp));
+    HIP_TRY(put(d.qw, *S.qw));
+    HIP_TRY(put(d.val, *S.val));
+    HIP_TRY(put(d.Vb, Vb));
+  }
+  int Qmax = 0;
+  for (const auto& d : dev) Qmax = std::max(Qmax, d.Q);
+  const size_t per_job = (size_t)Qmax * ncol * 2;
+  const int batch = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 30) / (per_job * sizeof(double))));
+  DevMem acc, jobs, tk;
+  HIP_TRY(acc.alloc((size_t)batch * per_job * sizeof(double)));
+  HIP_TRY(jobs.alloc((size_t)batch * sizeof(PairJobDev)));
+  HIP_TRY(tk.alloc((size_t)batch * 2 * N * N * 2 * sizeof(double)));
+  std::vector<double> htk((size_t)batch * 2 * N * N * 2);
+  for (size_t j0 = 0; j0 < req.size(); j0 += batch) {
+    const int nb = (int)std::min<size_t>(batch, req.size() - j0);
+    std::vector<PairJobDev> hj(nb);
+    int Qa_max = 0;
+    for (int j = 0; j < nb; ++j) {
+      const PairRequest& r = req[j0 + j];
+      if (r.cp < 0 || r.cq < 0 || r.cp >= (int)cls.size() || r.cq >= (int)cls.size() || !cls[r.cp].val ||
+          !cls[r.cq].val) {
+        err = "pair assembly: class without samples";
+        return -1;
+      }
+      const Dev &A = dev[r.cp], &B = dev[r.cq];
+      PairJobDev& J = hj[j];
+      J.qa = A.qp.as<double>();
+      J.wa = A.qw.as<double>();
+      J.va = A.val.as<double>();
+      J.qb = B.qp.as<double>();
+      J.Vb = B.Vb.as<double>();
+      J.acc = acc.as<double>() + (size_t)j * per_job;
+      J.ox = r.offset.x;
+      J.oy = r.offset.y;
+      J.oz = r.offset.z;
+      J.Qa = A.Q;
+      J.Qb = B.Q;
+      J.Na = N;
+      Qa_max = std::max(Qa_max, A.Q);
+    }
+    HIP_TRY(hipMemcpy(jobs.p, hj.data(), nb * sizeof(PairJobDev), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_pair_sums, dim3((Qa_max + 15) / 16, nb), dim3(kPairWaves * 64), 0, 0,
+                       jobs.as<PairJobDev>(), npad, k);
+    hipLaunchKernelGGL(k_pair_contract, dim3(N, nb), dim3(kBlock), 0, 0, jobs.as<PairJobDev>(), npad, k,
+                       tk.as<double>());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpy(htk.data(), tk.p, (size_t)nb * 2 * N * N * 2 * sizeof(double), hipMemcpyDeviceToHost));
+    for (int j = 0; j < nb; ++j) {
+      std::vector<cd>& Tj = T[j0 + j];
+      std::vector<cd>& Kj = K[j0 + j];
+      Tj.resize((size_t)N * N);
+      Kj.resize((size_t)N * N);
+      const double* base = &htk[(size_t)j * 2 * N * N * 2];
+      for (int e = 0; e < N * N; ++e) {
+        Tj[e] = cd(base[2 * e], base[2 * e + 1]);
+        Kj[e] = cd(base[2 * (N * N + e)], base[2 * (N * N + e) + 1]);
+      }
+    }
+  }
+  return 0;
 }
 
 }  // namespace mlfma

@@ -70,4 +70,25 @@ class Engine {
 
 Engine* make_engine(int precision);
 
+// Quadrature samples of one particle class for the device pair assembler:
+// points qp [Q] (particle-local), weights qw [Q], and the values
+// val [Q][7][N] (psi x, y, z, div, (psi x r) x, y, z) of the N functions.
+struct PairSamples {
+  const std::vector<V3>* qp = nullptr;
+  const std::vector<double>* qw = nullptr;
+  const std::vector<double>* val = nullptr;
+  int N = 0;
+};
+// One block between distinct particles: observation class cp, source class
+// cq whose centre sits at `offset` from the observation particle's centre.
+struct PairRequest {
+  int cp = 0, cq = 0;
+  V3 offset{0, 0, 0};
+};
+// Galerkin T and K (N x N, row-major, exterior wavenumber k) of every
+// request on the GPU in FP64: the same point-pair quadrature as
+// galerkin_TK for particles that share no triangle.  T[i], K[i] are filled.
+int gpu_pair_blocks(const std::vector<PairSamples>& cls, const std::vector<PairRequest>& req, double k,
+                    std::vector<std::vector<cd>>& T, std::vector<std::vector<cd>>& K, std::string& err);
+
 }  // namespace mlfma

@@ -60,7 +60,7 @@ EXPORTS = [
     "mlfma_default_params", "mlfma_build_tree", "mlfma_static_modes", "mlfma_set_static_modes",
     "mlfma_prepare", "mlfma_plane_wave_rhs", "mlfma_matvec", "mlfma_matvec_parts",
     "mlfma_precondition", "mlfma_gmres_solve", "mlfma_info", "mlfma_destroy", "mlfma_last_error",
-    "mlfma_debug_near_block", "mlfma_debug_leaf_pattern", "mlfma_debug_level_grid",
+    "mlfma_debug_near_block", "mlfma_debug_pair_block_device", "mlfma_debug_leaf_pattern", "mlfma_debug_level_grid",
     "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read",
 ]
 
@@ -90,6 +90,7 @@ def load_library(path: str = _LIB_PATH):
         "mlfma_destroy": (None, [ctxp]),
         "mlfma_last_error": (C.c_char_p, [ctxp]),
         "mlfma_debug_near_block": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp]),
+        "mlfma_debug_pair_block_device": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp]),
         "mlfma_debug_leaf_pattern": (C.c_int, [ctxp, C.c_int32, dp]),
         "mlfma_debug_level_grid": (C.c_int, [ctxp, C.c_int32, dp, dp]),
         "mlfma_debug_translation": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, dp]),
@@ -290,6 +291,16 @@ class Context:
         out = np.zeros((n, n), complex)
         self._check(lib().mlfma_debug_near_block(self._h, cp, cq, dx, dy, out.ctypes.data_as(C.POINTER(C.c_double))),
                     "debug_near_block")
+        return out
+
+    def debug_pair_block_device(self, cp, cq, dx, dy):
+        if self.n_modes is None:
+            raise MlfmaError(ENOTREADY, "no class has static modes")
+        n = 2 * self.n_modes
+        out = np.zeros((n, n), complex)
+        self._check(lib().mlfma_debug_pair_block_device(self._h, cp, cq, dx, dy,
+                                                        out.ctypes.data_as(C.POINTER(C.c_double))),
+                    "debug_pair_block_device")
         return out
 
     def debug_leaf_pattern(self, c):

@@ -12,6 +12,9 @@ y = Z x for the seeded x = workloads.random_complex((P, 2N), seed=1):
   c2_12x12.npz      all 144 particles (three translation levels)
   c2_40x40_rows.npz rows of 4 interior particles of the full 40 x 40
                     array (the bench workload; all six levels contribute)
+  c4_8x8.npz        all 64 particles of an 8 x 8 metalens of the c4 recipe
+                    (several diameter classes; M holds each used class's
+                    modes, `classes` their class ids)
 """
 from __future__ import annotations
 
@@ -35,7 +38,31 @@ def _cylinder_class(wl):
     return ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r)
 
 
+def make_lens(name: str):
+    t0 = time.time()
+    nx = int(name.split("_")[1].split("x")[0])
+    wl = w.workload("c4", nx, nx)
+    used = sorted(set(wl.class_id.tolist()))
+    pcs = []
+    for c in used:
+        v, t, e = wl.meshes[c]
+        pcs.append(ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r))
+    compact = np.array([used.index(c) for c in wl.class_id], np.int32)
+    prob = DenseProblem(pcs, wl.centers, compact)
+    P, n = wl.n_particles, pcs[0].n
+    x = w.random_complex((P, n), SEED)
+    rows = np.arange(P)
+    prob.prefetch([(mu, nu) for mu in rows for nu in range(P)])
+    y = prob.matvec_rows(x, rows)
+    out = os.path.join(HERE, name + ".npz")
+    np.savez_compressed(out, M=np.stack([pc.M for pc in pcs]), classes=np.array(used, np.int32), rows=rows, y=y,
+                        seed=SEED, eps_r=wl.eps_r, n_perp=wl.n_perp, n_par=wl.n_par, nx=nx, ny=nx)
+    print(f"{name}: {P} rows, classes {used} in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
 def make(name: str):
+    if name.startswith("c4_"):
+        return make_lens(name)
     t0 = time.time()
     if name in ("c2_6x6", "c2_12x12"):
         nx = 6 if name == "c2_6x6" else 12

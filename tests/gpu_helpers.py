@@ -16,11 +16,19 @@ def rel_err(a, b):
 
 
 def make_ctx(wl, M, precision, **params):
+    """M: one basis for every class, a list per class, or a dict {class: M}
+    for the classes in use (the others stay unset)."""
     from paper_2407_21724_amd import mlfma
     tp = mlfma.default_params(precision=precision, **params)
     ctx = mlfma.Context(wl.centers, wl.class_id, len(wl.meshes), tp)
     for c, (v, t, e) in enumerate(wl.meshes):
-        ctx.set_static_modes(c, v, t, e, wl.n_perp, wl.n_par, M[c] if isinstance(M, list) else M, wl.eps_r)
+        if isinstance(M, dict):
+            if c not in M:
+                continue
+            Mc = M[c]
+        else:
+            Mc = M[c] if isinstance(M, list) else M
+        ctx.set_static_modes(c, v, t, e, wl.n_perp, wl.n_par, Mc, wl.eps_r)
     return ctx
 
 

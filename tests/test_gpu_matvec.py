@@ -141,6 +141,26 @@ def test_c2_subarrays_vs_golden(name, prec):
     assert err_near < (1e-5 if prec == mlfma.C64 else 1e-12)
 
 
+@pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C128])
+def test_c4_lens_vs_golden(prec):
+    """8 x 8 metalens with six diameter classes: class-grouped projection and
+    receive, per-class-pair neighbour blocks, against the oracle."""
+    path = os.path.join(GOLDEN, "c4_8x8.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path)
+    nx = int(g["nx"])
+    wl = w.workload("c4", nx, nx)
+    M = {int(c): g["M"][i] for i, c in enumerate(g["classes"])}
+    note(f"c4 8x8 lens precision={prec} classes={sorted(M)}")
+    ctx = make_ctx(wl, M, prec)
+    x = w.random_complex((1, wl.n_particles, 2 * (wl.n_perp + wl.n_par)), int(g["seed"]))
+    y = ctx.matvec(to_dev(x, ctx)).cpu().numpy()[0]
+    err = rel_err(y[g["rows"]], g["y"])
+    note(f"  rel err {err:.3e}")
+    assert err < TOL
+
+
 def test_c2_full_size_sampled_rows():
     """The bench workload (40 x 40 cylinders, FP32, one RHS, default
     parameters): rows of 4 interior particles against the oracle."""

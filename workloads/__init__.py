@@ -288,7 +288,12 @@ def workload(name: str, nx: int | None = None, ny: int | None = None) -> Workloa
     triangles, 20+20 static modes, pitch 0.5, normal x-polarised incidence.
     ``c2``: 40x40 dielectric cylinders (D 0.3, H 0.6, eps 6.25), 600-triangle
     jittered mesh (seed 2407), 15+15 modes, pitch 0.5.  ``nx``/``ny`` shrink
-    the array for small parity cases.  ``c3`` is c2 with 64 incidences."""
+    the array for small parity cases.  ``c3`` is c2 with 64 incidences.
+    ``c4``: 80x80 metalens of the same cylinders (H 0.6, eps 6.25) with
+    diameters from the focusing profile of ``lens_diameters`` (focal length
+    20), 32 diameter classes, one mesh per class (jitter seed 2407 + class).
+    ``c5``: the 200x200 lens (focal length 50) with 16 incidences tilted up
+    to 20 degrees.  ``nx``/``ny`` give a smaller lens of the same recipe."""
     name = name.lower()
     if name == "c1":
         nx, ny = nx or 4, ny or 4
@@ -301,4 +306,13 @@ def workload(name: str, nx: int | None = None, ny: int | None = None) -> Workloa
         inc = [normal_incidence_x()] if name == "c2" else c3_incidences()
         return Workload(name, lattice(nx, ny, 0.5), np.zeros(nx * ny, np.int32),
                         [mesh], 6.25 + 0j, 15, 15, 0.5, inc)
+    if name in ("c4", "c5"):
+        # metalens: diameters from the hyperbolic focusing profile, 32 classes
+        nx = nx or (80 if name == "c4" else 200)
+        ny = ny or nx
+        focal = 20.0 if name == "c4" else 50.0
+        cls, dia = lens_diameters(nx, ny, 0.5, focal)
+        meshes = [_mesh_with_edges(cylinder(float(d), 0.6, seed=2407 + c)) for c, d in enumerate(dia)]
+        inc = [normal_incidence_x()] if name == "c4" else tilted_incidences(16, 20.0)
+        return Workload(name, lattice(nx, ny, 0.5), cls, meshes, 6.25 + 0j, 15, 15, 0.5, inc)
     raise ValueError(f"unknown workload {name}")
