@@ -177,6 +177,15 @@ int mlfma_matvec(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void
 int mlfma_matvec_parts(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, int32_t parts,
                        void* stream);
 
+/* dst uses src's per-class setup (modes, self blocks, patterns) and its
+ * cache of neighbour blocks from now on, so that many arrays of the same
+ * particle classes are prepared without repeating the per-class work.  Both
+ * contexts must have the same class count and tree parameters.  The shared
+ * data stays alive while either context does; mlfma_set_static_modes on
+ * either context changes it for both, and the two must not be used from
+ * different threads at once. */
+int mlfma_share_setup(mlfma_ctx* dst, const mlfma_ctx* src);
+
 /* Block-diagonal preconditioner y_p = Z_s^-1 x_p (Sec. V stage v), same
  * layout and precision as mlfma_matvec. */
 int mlfma_precondition(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream);
@@ -240,6 +249,63 @@ int mlfma_debug_pair_block_device(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_
 int mlfma_debug_leaf_pattern(mlfma_ctx* ctx, int32_t c, double* out);
 int mlfma_debug_level_grid(mlfma_ctx* ctx, int32_t level, double* khat, double* w);
 int mlfma_debug_translation(mlfma_ctx* ctx, int32_t level, int32_t dx, int32_t dy, double* out);
+
+/* ------------------------------------------------ learned initial guess --
+ * A fully connected ReLU network, trained on solutions the method itself
+ * produces on small arrays, maps each particle's class, its eight
+ * neighbours' geometry parameters and the incidence direction to its
+ * static-mode coefficients; the prediction is the GMRES initial guess (with
+ * the zero start as fallback, mlfma_gmres_solve with MLFMA_SOLVE_USE_X0).
+ * The paper has no such network: this is an addition around its solver (the
+ * solution vector of Sec. V stage v).  All network arithmetic is FP32 on
+ * the GPU.  A network is not tied to a context. */
+typedef struct mlfma_mlp mlfma_mlp;
+
+/* sizes[0..n_layers]: inputs, hidden widths, outputs; weights He-normal
+ * from `seed` (splitmix64 + Box-Muller), biases zero.  EINVAL on bad sizes. */
+int mlfma_mlp_create(int32_t n_layers, const int32_t* sizes, uint64_t seed, mlfma_mlp** out);
+void mlfma_mlp_destroy(mlfma_mlp* net);
+const char* mlfma_mlp_last_error(const mlfma_mlp* net);
+/* Parameters as one FP32 vector: for each layer W [out][in] row-major, then
+ * b [out].  set_params also clears the Adam moments. */
+int64_t mlfma_mlp_num_params(const mlfma_mlp* net);
+int mlfma_mlp_get_params(const mlfma_mlp* net, float* host);
+int mlfma_mlp_set_params(mlfma_mlp* net, const float* host);
+/* Y [n][out] = net(X [n][in]); device FP32 pointers; asynchronous on stream. */
+int mlfma_mlp_forward(mlfma_mlp* net, const float* X_dev, int32_t n, float* Y_dev, void* stream);
+/* loss = 0.5/n * sum over samples and outputs of (net(X) - T)^2, T [n][out]
+ * on the device; the gradient (parameter layout) is copied to grads_host
+ * when not NULL.  Synchronous. */
+int mlfma_mlp_loss_grad(mlfma_mlp* net, const float* X_dev, const float* T_dev, int32_t n, double* loss,
+                        float* grads_host, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * minibatch; *loss = the loss before the step.  Synchronous. */
+int mlfma_mlp_train_step(mlfma_mlp* net, const float* X_dev, const float* T_dev, int32_t n, float lr,
+                         double* loss, void* stream);
+
+/* Writes the network's prediction for R plane-wave incidences (directions
+ * khat [R][3]) into x_dev [R][P][2][N] (context precision).  Features of
+ * particle p, in this order: class_param[class of p] / scale, the same for
+ * the 8 neighbouring sites (dy, dx in -1..1 row-major, centre skipped; 0
+ * where a site holds no particle), khat_x, khat_y.  The network outputs
+ * (re, im) of the 2N coefficients with the incident phase removed; the
+ * guess multiplies them by exp(-j k khat . r_p).  EINVAL if the network
+ * does not have 11 inputs and 4N outputs.  Synchronous. */
+/* The features described below, [R][P][n_classes + 10] FP32, on the host
+ * (the inputs a network for mlfma_learned_guess is trained on).  Host-only. */
+int mlfma_guess_features(mlfma_ctx* ctx, const double* class_param, double scale, int32_t R, const double* khat,
+                         float* X_host);
+/* Writes the network's prediction for R plane-wave incidences (directions
+ * khat [R][3]) into x_dev [R][P][2][N] (context precision).  Features of
+ * particle p, in this order: one-hot of its class (n_classes entries; the
+ * static-mode basis differs between classes), class_param[class] / scale
+ * of the 8 neighbouring sites (dy, dx in -1..1 row-major, centre skipped;
+ * 0 where a site holds no particle), khat_x, khat_y.  The network outputs
+ * (re, im) of the 2N coefficients with the incident phase removed; the
+ * guess multiplies them by exp(-j k khat . r_p).  EINVAL if the network
+ * does not have n_classes + 10 inputs and 4N outputs.  Synchronous. */
+int mlfma_learned_guess(mlfma_ctx* ctx, mlfma_mlp* net, const double* class_param, double scale, int32_t R,
+                        const double* khat, void* x_dev, void* stream);
 
 #ifdef __cplusplus
 }

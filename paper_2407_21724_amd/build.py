@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmlfma.so")
 
-SOURCES = ["api.cpp", "host_setup.cpp", "host_tree.cpp", "engine.hip"]
+SOURCES = ["api.cpp", "host_setup.cpp", "host_tree.cpp", "engine.hip", "mlp.hip"]
 ARCH = "gfx950"
 
 

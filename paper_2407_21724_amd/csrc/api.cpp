@@ -13,6 +13,7 @@
 #include <tuple>
 
 #include "engine.hpp"
+#include "mlp.hpp"
 #include "host_linalg.hpp"
 #include "host_setup.hpp"
 #include "host_tree.hpp"
@@ -48,11 +49,14 @@ struct mlfma_ctx {
   int nx = 0, ny = 0;
   std::vector<int> box_of, part_of_box;
   Tree tree;
-  std::vector<ClassData> classes;
+  // per-class setup and the neighbour-block cache; shared between contexts
+  // by mlfma_share_setup
+  std::shared_ptr<std::vector<ClassData>> classes = std::make_shared<std::vector<ClassData>>();
   int N = -1;
   bool prepared = false;
   bool tl_built = false;
-  std::map<NearKey, std::vector<cd>> near_cache;  // n x n row-major blocks
+  std::shared_ptr<std::map<NearKey, std::vector<cd>>> near_cache =
+      std::make_shared<std::map<NearKey, std::vector<cd>>>();  // n x n row-major blocks
   std::unique_ptr<Engine> eng;
 };
 
@@ -85,28 +89,28 @@ std::vector<cd> assemble_pair(const std::vector<cd>& T, const std::vector<cd>& K
 
 const std::vector<cd>& near_block(mlfma_ctx* ctx, int cp, int cq, int dx, int dy) {
   NearKey key{cp, cq, dx, dy};
-  auto it = ctx->near_cache.find(key);
-  if (it != ctx->near_cache.end()) return it->second;
+  auto it = ctx->near_cache->find(key);
+  if (it != ctx->near_cache->end()) return it->second;
   const int N = ctx->N, n = 2 * N;
   if (dx == 0 && dy == 0 && cp == cq) {
-    return ctx->near_cache[key] = ctx->classes[cp].Zs;
+    return (*ctx->near_cache)[key] = (*ctx->classes)[cp].Zs;
   }
   // reciprocity: Z^{nu mu}(-d) = D (Z^{mu nu}(d))^T D, D = diag(I, -I)
-  auto rev = ctx->near_cache.find(NearKey{cq, cp, -dx, -dy});
-  if (rev != ctx->near_cache.end()) {
+  auto rev = ctx->near_cache->find(NearKey{cq, cp, -dx, -dy});
+  if (rev != ctx->near_cache->end()) {
     std::vector<cd> Z((size_t)n * n);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) {
         const double s = ((i < N) == (j < N)) ? 1.0 : -1.0;
         Z[(size_t)i * n + j] = s * rev->second[(size_t)j * n + i];
       }
-    return ctx->near_cache[key] = Z;
+    return (*ctx->near_cache)[key] = Z;
   }
-  const ClassData &A = ctx->classes[cp], &B = ctx->classes[cq];
+  const ClassData &A = (*ctx->classes)[cp], &B = (*ctx->classes)[cq];
   std::vector<cd> T, K;
   const double s = ctx->tp.leaf_size;
   galerkin_TK(A.mesh, A.smp, B.mesh, B.smp, V3{dx * s, dy * s, 0.0}, cd(kK0, 0.0), nullptr, T, K);
-  return ctx->near_cache[key] = assemble_pair(T, K, N);
+  return (*ctx->near_cache)[key] = assemble_pair(T, K, N);
 }
 
 // Computes on the GPU every block between distinct particles in `keys` that
@@ -118,14 +122,14 @@ int device_pair_blocks(mlfma_ctx* ctx, const std::vector<NearKey>& keys) {
     const auto [cp, cq, dx, dy] = key;
     if (dx == 0 && dy == 0) continue;
     const NearKey rev{cq, cp, -dx, -dy};
-    if (ctx->near_cache.count(key) || ctx->near_cache.count(rev) || seen.count(key) || seen.count(rev)) continue;
+    if (ctx->near_cache->count(key) || ctx->near_cache->count(rev) || seen.count(key) || seen.count(rev)) continue;
     seen.insert(key);
     todo.push_back(key);
   }
   if (todo.empty()) return MLFMA_OK;
   std::vector<PairSamples> smp(ctx->C);
   for (int c = 0; c < ctx->C; ++c)
-    if (ctx->classes[c].set) smp[c] = {&ctx->classes[c].mesh.qp, &ctx->classes[c].mesh.qw, &ctx->classes[c].smp.val,
+    if ((*ctx->classes)[c].set) smp[c] = {&(*ctx->classes)[c].mesh.qp, &(*ctx->classes)[c].mesh.qw, &(*ctx->classes)[c].smp.val,
                                        ctx->N};
   std::vector<PairRequest> req;
   const double s = ctx->tp.leaf_size;
@@ -136,7 +140,7 @@ int device_pair_blocks(mlfma_ctx* ctx, const std::vector<NearKey>& keys) {
   std::vector<std::vector<cd>> T, K;
   std::string err;
   if (int rc = gpu_pair_blocks(smp, req, kK0, T, K, err)) return fail(ctx, rc == -1 ? MLFMA_EINVAL : rc, err);
-  for (size_t i = 0; i < todo.size(); ++i) ctx->near_cache[todo[i]] = assemble_pair(T[i], K[i], ctx->N);
+  for (size_t i = 0; i < todo.size(); ++i) (*ctx->near_cache)[todo[i]] = assemble_pair(T[i], K[i], ctx->N);
   return MLFMA_OK;
 }
 
@@ -150,7 +154,7 @@ std::vector<cd> transpose(const std::vector<cd>& A, int n) {
 int do_prepare(mlfma_ctx* ctx) {
   if (ctx->prepared) return MLFMA_OK;
   for (int p = 0; p < ctx->P; ++p)
-    if (!ctx->classes[ctx->cls[p]].set)
+    if (!(*ctx->classes)[ctx->cls[p]].set)
       return fail(ctx, MLFMA_ENOTREADY, "class " + std::to_string(ctx->cls[p]) + " has no static modes");
   const int N = ctx->N, n = 2 * N;
   if (!ctx->tl_built) {
@@ -232,7 +236,7 @@ int do_prepare(mlfma_ctx* ctx) {
   u.Zinv.resize(ctx->C);
   const bool far = ctx->tree.ntl > 0;
   for (int c = 0; c < ctx->C; ++c) {
-    const ClassData& cdt = ctx->classes[c];
+    const ClassData& cdt = (*ctx->classes)[c];
     if (!cdt.set) {
       u.Zinv[c].assign((size_t)n * n, 0.0);
       if (far) {
@@ -369,7 +373,7 @@ int mlfma_build_tree(const mlfma_problem* pb, const mlfma_tree_params* tp, mlfma
   try {
     std::string e = build_tree(ctx->nx, ctx->ny, s, tp->L_leaf, tp->L_rule, tp->digits, tp->interp_order, kK0, ctx->tree);
     if (!e.empty()) return MLFMA_EINVAL;
-    ctx->classes.resize(ctx->C);
+    ctx->classes->resize(ctx->C);
   } catch (...) {
     return MLFMA_EINVAL;
   }
@@ -446,17 +450,37 @@ int mlfma_set_static_modes(mlfma_ctx* ctx, int32_t class_id, int32_t nv, const d
     if (!complex_inverse(cdt.Zinv, n)) return fail(ctx, MLFMA_ENONFINITE, "self block is singular");
     if (ctx->tree.ntl > 0) kspace_patterns(cdt.mesh, cdt.smp, kK0, ctx->tree.lv[0].khat, cdt.leafpat);
     cdt.set = true;
-    ctx->classes[class_id] = std::move(cdt);
+    (*ctx->classes)[class_id] = std::move(cdt);
     ctx->N = N;
     ctx->prepared = false;
     ctx->eng.reset();
     // blocks involving this class must be recomputed
-    for (auto it = ctx->near_cache.begin(); it != ctx->near_cache.end();) {
+    for (auto it = ctx->near_cache->begin(); it != ctx->near_cache->end();) {
       if (std::get<0>(it->first) == class_id || std::get<1>(it->first) == class_id)
-        it = ctx->near_cache.erase(it);
+        it = ctx->near_cache->erase(it);
       else
         ++it;
     }
+    return MLFMA_OK;
+  });
+}
+
+int mlfma_share_setup(mlfma_ctx* dst, const mlfma_ctx* src) {
+  if (!dst || !src || dst == src) return MLFMA_EINVAL;
+  return guarded(dst, [&]() -> int {
+    const mlfma_tree_params &a = dst->tp, &b = src->tp;
+    if (dst->C != src->C || a.leaf_size != b.leaf_size || a.L_leaf != b.L_leaf || a.L_rule != b.L_rule ||
+        a.digits != b.digits || a.outer_levels != b.outer_levels)
+      return fail(dst, MLFMA_EINVAL, "contexts differ in class count or tree parameters");
+    if (dst->tree.ntl > 0)
+      for (const ClassData& c : *src->classes)
+        if (c.set && c.leafpat.empty())
+          return fail(dst, MLFMA_EINVAL, "source context has no far-field patterns (build it with far levels)");
+    dst->classes = src->classes;
+    dst->near_cache = src->near_cache;
+    dst->N = src->N;
+    dst->prepared = false;
+    dst->eng.reset();
     return MLFMA_OK;
   });
 }
@@ -483,9 +507,9 @@ int mlfma_plane_wave_rhs(mlfma_ctx* ctx, int32_t R, const double* khat, const do
     }
     std::vector<cd> pat((size_t)ctx->C * R * n, 0.0);
     for (int c = 0; c < ctx->C; ++c) {
-      if (!ctx->classes[c].set) continue;
+      if (!(*ctx->classes)[c].set) continue;
       std::vector<cd> ps;
-      kspace_patterns(ctx->classes[c].mesh, ctx->classes[c].smp, kK0, dirs, ps);
+      kspace_patterns((*ctx->classes)[c].mesh, (*ctx->classes)[c].smp, kK0, dirs, ps);
       for (int r = 0; r < R; ++r) {
         const cd e[3] = {cd(pol[6 * r], pol[6 * r + 1]), cd(pol[6 * r + 2], pol[6 * r + 3]),
                          cd(pol[6 * r + 4], pol[6 * r + 5])};
@@ -627,7 +651,7 @@ int mlfma_debug_near_block(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_t dx, i
   if (!ctx || !out) return MLFMA_EINVAL;
   return guarded(ctx, [&]() -> int {
     if (cp < 0 || cq < 0 || cp >= ctx->C || cq >= ctx->C) return fail(ctx, MLFMA_EINVAL, "class out of range");
-    if (!ctx->classes[cp].set || !ctx->classes[cq].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
+    if (!(*ctx->classes)[cp].set || !(*ctx->classes)[cq].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
     if (dx == 0 && dy == 0 && cp != cq) return fail(ctx, MLFMA_EINVAL, "two classes on one site");
     const auto& Z = near_block(ctx, cp, cq, dx, dy);
     std::memcpy(out, Z.data(), Z.size() * sizeof(cd));
@@ -639,10 +663,10 @@ int mlfma_debug_pair_block_device(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_
   if (!ctx || !out) return MLFMA_EINVAL;
   return guarded(ctx, [&]() -> int {
     if (cp < 0 || cq < 0 || cp >= ctx->C || cq >= ctx->C) return fail(ctx, MLFMA_EINVAL, "class out of range");
-    if (!ctx->classes[cp].set || !ctx->classes[cq].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
+    if (!(*ctx->classes)[cp].set || !(*ctx->classes)[cq].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
     if (dx == 0 && dy == 0) return fail(ctx, MLFMA_EINVAL, "not a pair of distinct sites");
     std::vector<PairSamples> smp(ctx->C);
-    for (int c : {cp, cq}) smp[c] = {&ctx->classes[c].mesh.qp, &ctx->classes[c].mesh.qw, &ctx->classes[c].smp.val, ctx->N};
+    for (int c : {cp, cq}) smp[c] = {&(*ctx->classes)[c].mesh.qp, &(*ctx->classes)[c].mesh.qw, &(*ctx->classes)[c].smp.val, ctx->N};
     const double s = ctx->tp.leaf_size;
     std::vector<std::vector<cd>> T, K;
     std::string err;
@@ -656,11 +680,11 @@ int mlfma_debug_pair_block_device(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_
 
 int mlfma_debug_leaf_pattern(mlfma_ctx* ctx, int32_t c, double* out) {
   if (!ctx || !out) return MLFMA_EINVAL;
-  if (c < 0 || c >= ctx->C || !ctx->classes[c].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
+  if (c < 0 || c >= ctx->C || !(*ctx->classes)[c].set) return fail(ctx, MLFMA_ENOTREADY, "class not set");
   if (ctx->tree.ntl < 1) return fail(ctx, MLFMA_EINVAL, "no far-field levels");
   const LevelGrid& g = ctx->tree.lv[0];
   const int N = ctx->N;
-  const auto& pat = ctx->classes[c].leafpat;
+  const auto& pat = (*ctx->classes)[c].leafpat;
   cd* o = reinterpret_cast<cd*>(out);
   for (int s = 0; s < g.K; ++s)
     for (int m = 0; m < N; ++m) {
@@ -698,3 +722,162 @@ int mlfma_debug_translation(mlfma_ctx* ctx, int32_t level, int32_t dx, int32_t d
 }
 
 }  // extern "C"
+
+struct mlfma_mlp {
+  mlfma::Mlp* m = nullptr;
+  std::string err;
+};
+
+namespace {
+int mlp_fail(mlfma_mlp* net, int code, const std::string& msg) {
+  if (net) net->err = msg;
+  return code;
+}
+template <typename F>
+int mlp_guarded(mlfma_mlp* net, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return mlp_fail(net, MLFMA_ENOMEM, "out of host memory");
+  } catch (const std::exception& e) {
+    return mlp_fail(net, MLFMA_EINVAL, e.what());
+  }
+}
+}  // namespace
+
+int mlfma_mlp_create(int32_t n_layers, const int32_t* sizes, uint64_t seed, mlfma_mlp** out) {
+  if (!out || !sizes || n_layers < 1 || n_layers > 64) return MLFMA_EINVAL;
+  *out = nullptr;
+  auto* net = new (std::nothrow) mlfma_mlp();
+  if (!net) return MLFMA_ENOMEM;
+  std::vector<int> sz(sizes, sizes + n_layers + 1);
+  std::string err;
+  net->m = mlp_create(sz, seed, err);
+  if (!net->m) {
+    delete net;
+    return err.find("failed") != std::string::npos ? MLFMA_EHIP : MLFMA_EINVAL;
+  }
+  *out = net;
+  return MLFMA_OK;
+}
+
+void mlfma_mlp_destroy(mlfma_mlp* net) {
+  if (!net) return;
+  mlp_destroy(net->m);
+  delete net;
+}
+
+const char* mlfma_mlp_last_error(const mlfma_mlp* net) { return net ? net->err.c_str() : "null network"; }
+
+int64_t mlfma_mlp_num_params(const mlfma_mlp* net) { return net ? mlp_num_params(net->m) : -1; }
+
+int mlfma_mlp_get_params(const mlfma_mlp* net, float* host) {
+  if (!net || !host) return MLFMA_EINVAL;
+  std::string err;
+  int rc = mlp_get_params(net->m, host, err);
+  return rc ? mlp_fail(const_cast<mlfma_mlp*>(net), rc, err) : MLFMA_OK;
+}
+
+int mlfma_mlp_set_params(mlfma_mlp* net, const float* host) {
+  if (!net || !host) return MLFMA_EINVAL;
+  for (int64_t i = 0; i < mlp_num_params(net->m); ++i)
+    if (!std::isfinite(host[i])) return mlp_fail(net, MLFMA_ENONFINITE, "non-finite parameter");
+  std::string err;
+  int rc = mlp_set_params(net->m, host, err);
+  return rc ? mlp_fail(net, rc, err) : MLFMA_OK;
+}
+
+int mlfma_mlp_forward(mlfma_mlp* net, const float* X_dev, int32_t n, float* Y_dev, void* stream) {
+  if (!net || !X_dev || !Y_dev || n < 1) return MLFMA_EINVAL;
+  return mlp_guarded(net, [&]() -> int {
+    std::string err;
+    int rc = mlp_forward(net->m, X_dev, n, Y_dev, stream, err);
+    return rc ? mlp_fail(net, rc, err) : MLFMA_OK;
+  });
+}
+
+int mlfma_mlp_loss_grad(mlfma_mlp* net, const float* X_dev, const float* T_dev, int32_t n, double* loss,
+                        float* grads_host, void* stream) {
+  if (!net || !X_dev || !T_dev || n < 1) return MLFMA_EINVAL;
+  return mlp_guarded(net, [&]() -> int {
+    std::string err;
+    int rc = mlp_loss_grad(net->m, X_dev, T_dev, n, loss, grads_host, stream, err);
+    return rc ? mlp_fail(net, rc, err) : MLFMA_OK;
+  });
+}
+
+int mlfma_mlp_train_step(mlfma_mlp* net, const float* X_dev, const float* T_dev, int32_t n, float lr,
+                         double* loss, void* stream) {
+  if (!net || !X_dev || !T_dev || n < 1 || !(lr > 0)) return MLFMA_EINVAL;
+  return mlp_guarded(net, [&]() -> int {
+    std::string err;
+    int rc = mlp_train_step(net->m, X_dev, T_dev, n, lr, loss, stream, err);
+    if (rc) return mlp_fail(net, rc, err);
+    if (loss && !std::isfinite(*loss)) return mlp_fail(net, MLFMA_ENONFINITE, "non-finite loss");
+    return MLFMA_OK;
+  });
+}
+
+namespace {
+// features [R][P][C + 10] and incident phases [R][P] of the learned guess:
+// one-hot class of p, class_param / scale of the 8 neighbouring sites (0 if
+// empty), khat_x, khat_y
+int guess_nfeat(const mlfma_ctx* ctx) { return ctx->C + 10; }
+void guess_features(const mlfma_ctx* ctx, const double* class_param, double scale, int R, const double* khat,
+                    std::vector<float>& X, std::vector<cd>& phase) {
+  const int P = ctx->P, nf = guess_nfeat(ctx);
+  X.assign((size_t)R * P * nf, 0.f);
+  phase.assign((size_t)R * P, cd(1.0, 0.0));
+  for (int r = 0; r < R; ++r) {
+    const V3 kh{khat[3 * r], khat[3 * r + 1], khat[3 * r + 2]};
+    for (int p = 0; p < P; ++p) {
+      float* f = &X[((size_t)r * P + p) * nf];
+      const int ix = ctx->box_of[p] % ctx->nx, iy = ctx->box_of[p] / ctx->nx;
+      f[ctx->cls[p]] = 1.f;
+      int slot = ctx->C;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (dx == 0 && dy == 0) continue;
+          const int jx = ix + dx, jy = iy + dy;
+          int q = -1;
+          if (jx >= 0 && jy >= 0 && jx < ctx->nx && jy < ctx->ny) q = ctx->part_of_box[jy * ctx->nx + jx];
+          f[slot++] = q >= 0 ? (float)(class_param[ctx->cls[q]] / scale) : 0.f;
+        }
+      f[slot++] = (float)kh.x;
+      f[slot] = (float)kh.y;
+      const double a = -kK0 * dot(kh, ctx->centers[p]);
+      phase[(size_t)r * P + p] = cd(std::cos(a), std::sin(a));
+    }
+  }
+}
+}  // namespace
+
+int mlfma_guess_features(mlfma_ctx* ctx, const double* class_param, double scale, int32_t R, const double* khat,
+                         float* X_host) {
+  if (!ctx || !class_param || !khat || !X_host || R < 1 || !(scale > 0)) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    std::vector<float> X;
+    std::vector<cd> phase;
+    guess_features(ctx, class_param, scale, R, khat, X, phase);
+    std::memcpy(X_host, X.data(), X.size() * sizeof(float));
+    return MLFMA_OK;
+  });
+}
+
+int mlfma_learned_guess(mlfma_ctx* ctx, mlfma_mlp* net, const double* class_param, double scale, int32_t R,
+                        const double* khat, void* x_dev, void* stream) {
+  if (!ctx || !net || !class_param || !khat || !x_dev || R < 1 || !(scale > 0)) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    if (ctx->N < 0) return fail(ctx, MLFMA_ENOTREADY, "no class has static modes");
+    const int N = ctx->N, n = 2 * N, P = ctx->P;
+    if (mlp_inputs(net->m) != guess_nfeat(ctx) || mlp_outputs(net->m) != 2 * n)
+      return fail(ctx, MLFMA_EINVAL, "network must have n_classes + 10 inputs and 4N outputs");
+    std::vector<float> X;
+    std::vector<cd> phase;
+    guess_features(ctx, class_param, scale, R, khat, X, phase);
+    std::string err;
+    int rc = mlp_guess(net->m, X, phase, R, P, N * 2, ctx->tp.precision == MLFMA_C128 ? 1 : 0, x_dev, stream,
+                       err);
+    return rc ? fail(ctx, rc == -1 ? MLFMA_EINVAL : rc, err) : MLFMA_OK;
+  });
+}

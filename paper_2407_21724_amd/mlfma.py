@@ -61,7 +61,10 @@ EXPORTS = [
     "mlfma_prepare", "mlfma_plane_wave_rhs", "mlfma_matvec", "mlfma_matvec_parts",
     "mlfma_precondition", "mlfma_gmres_solve", "mlfma_info", "mlfma_destroy", "mlfma_last_error",
     "mlfma_debug_near_block", "mlfma_debug_pair_block_device", "mlfma_debug_leaf_pattern", "mlfma_debug_level_grid",
-    "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read",
+    "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read", "mlfma_share_setup",
+    "mlfma_mlp_create", "mlfma_mlp_destroy", "mlfma_mlp_last_error", "mlfma_mlp_num_params",
+    "mlfma_mlp_get_params", "mlfma_mlp_set_params", "mlfma_mlp_forward", "mlfma_mlp_loss_grad",
+    "mlfma_mlp_train_step", "mlfma_learned_guess", "mlfma_guess_features",
 ]
 
 
@@ -94,6 +97,18 @@ def load_library(path: str = _LIB_PATH):
         "mlfma_debug_leaf_pattern": (C.c_int, [ctxp, C.c_int32, dp]),
         "mlfma_debug_level_grid": (C.c_int, [ctxp, C.c_int32, dp, dp]),
         "mlfma_debug_translation": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, dp]),
+        "mlfma_share_setup": (C.c_int, [ctxp, ctxp]),
+        "mlfma_mlp_create": (C.c_int, [C.c_int32, ip, C.c_uint64, C.POINTER(C.c_void_p)]),
+        "mlfma_mlp_destroy": (None, [vp]),
+        "mlfma_mlp_last_error": (C.c_char_p, [vp]),
+        "mlfma_mlp_num_params": (C.c_int64, [vp]),
+        "mlfma_mlp_get_params": (C.c_int, [vp, C.POINTER(C.c_float)]),
+        "mlfma_mlp_set_params": (C.c_int, [vp, C.POINTER(C.c_float)]),
+        "mlfma_mlp_forward": (C.c_int, [vp, vp, C.c_int32, vp, vp]),
+        "mlfma_mlp_loss_grad": (C.c_int, [vp, vp, vp, C.c_int32, dp, C.POINTER(C.c_float), vp]),
+        "mlfma_mlp_train_step": (C.c_int, [vp, vp, vp, C.c_int32, C.c_float, dp, vp]),
+        "mlfma_learned_guess": (C.c_int, [ctxp, vp, dp, C.c_double, C.c_int32, dp, vp, vp]),
+        "mlfma_guess_features": (C.c_int, [ctxp, dp, C.c_double, C.c_int32, dp, C.POINTER(C.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -164,6 +179,7 @@ class Context:
             raise MlfmaError(rc, "build_tree rejected the problem")
         self._h = h
         self.n_particles = len(self._centers)
+        self.n_classes = int(n_classes)
         self.n_modes = None
 
     @property
@@ -186,6 +202,37 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def share_setup(self, src: "Context"):
+        """Use src's per-class setup and neighbour-block cache (mlfma_share_setup)."""
+        self._check(lib().mlfma_share_setup(self._h, src._h), "share_setup")
+        self.n_modes = src.n_modes
+        self._shared_from = src          # keeps the source alive for readability; the data is refcounted
+
+    def guess_features(self, class_param, scale, khat):
+        """Network inputs [R][P][n_classes + 10] of mlfma_learned_guess (host)."""
+        khat = np.ascontiguousarray(np.atleast_2d(khat), np.float64)
+        cp = np.ascontiguousarray(class_param, np.float64)
+        if len(cp) != self.n_classes:
+            raise ValueError("class_param needs one entry per class")
+        out = np.zeros((len(khat), self.n_particles, self.n_classes + 10), np.float32)
+        self._check(lib().mlfma_guess_features(self._h, _dptr(cp), float(scale), len(khat), _dptr(khat),
+                                               out.ctypes.data_as(C.POINTER(C.c_float))), "guess_features")
+        return out
+
+    def learned_guess(self, net: "Mlp", class_param, scale, khat, out=None, stream=None):
+        """x0 [R][P][2N] predicted by `net` for directions khat [R][3]."""
+        import torch
+        khat = np.ascontiguousarray(np.atleast_2d(khat), np.float64)
+        cp = np.ascontiguousarray(class_param, np.float64)
+        if len(cp) != self.n_classes:
+            raise ValueError("class_param needs one entry per class")
+        R = len(khat)
+        if out is None:
+            out = torch.empty(self._shape(R), dtype=self.dtype, device="cuda")
+        self._check(lib().mlfma_learned_guess(self._h, net._h, _dptr(cp), float(scale), R, _dptr(khat),
+                                              self._dev(out, R), _stream_ptr(stream)), "learned_guess")
+        return out
 
     def set_static_modes(self, class_id, verts, tris, edges, n_perp, n_par, M, eps):
         v = np.ascontiguousarray(verts, np.float64)
@@ -323,3 +370,83 @@ class Context:
         self._check(lib().mlfma_debug_translation(self._h, level, dx, dy, out.ctypes.data_as(C.POINTER(C.c_double))),
                     "debug_translation")
         return out
+
+
+class Mlp:
+    """The learned initial guess's network (mlfma_mlp_*): FP32 on the GPU."""
+
+    def __init__(self, sizes, seed: int = 0):
+        arr = np.ascontiguousarray(sizes, np.int32)
+        h = C.c_void_p()
+        rc = lib().mlfma_mlp_create(len(arr) - 1, _iptr(arr), C.c_uint64(seed), C.byref(h))
+        if rc != OK:
+            raise MlfmaError(rc, "mlp_create rejected the sizes")
+        self._h = h
+        self.sizes = [int(v) for v in arr]
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise MlfmaError(rc, f"{what}: {lib().mlfma_mlp_last_error(self._h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mlfma_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(lib().mlfma_mlp_num_params(self._h))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, np.float32)
+        self._check(lib().mlfma_mlp_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))), "get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        if p.size != self.num_params:
+            raise ValueError("parameter vector size")
+        self._check(lib().mlfma_mlp_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float))), "set_params")
+
+    def layers(self, p=None):
+        """Split a flat parameter vector into [(W [out][in], b [out]), ...]."""
+        p = self.get_params() if p is None else p
+        out, o = [], 0
+        for i, j in zip(self.sizes[:-1], self.sizes[1:]):
+            W = p[o:o + i * j].reshape(j, i)
+            o += i * j
+            b = p[o:o + j]
+            o += j
+            out.append((W, b))
+        return out
+
+    def forward(self, X, out=None, stream=None):
+        import torch
+        n = X.shape[0]
+        if out is None:
+            out = torch.empty((n, self.sizes[-1]), dtype=torch.float32, device=X.device)
+        self._check(lib().mlfma_mlp_forward(self._h, C.c_void_p(X.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                            _stream_ptr(stream)), "forward")
+        return out
+
+    def loss_grad(self, X, T, stream=None):
+        loss = C.c_double()
+        g = np.zeros(self.num_params, np.float32)
+        self._check(lib().mlfma_mlp_loss_grad(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                              X.shape[0], C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float)),
+                                              _stream_ptr(stream)), "loss_grad")
+        return loss.value, g
+
+    def train_step(self, X, T, lr, stream=None):
+        loss = C.c_double()
+        self._check(lib().mlfma_mlp_train_step(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+                                               X.shape[0], C.c_float(lr), C.byref(loss), _stream_ptr(stream)),
+                    "train_step")
+        return loss.value

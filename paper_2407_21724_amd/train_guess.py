@@ -1,0 +1,79 @@
+"""Train the learned initial guess for the metalens recipe and write its
+checkpoint (needs a GPU).
+
+    python -m paper_2407_21724_amd.train_guess [--patches 2000] [--out PATH]
+
+The 32 diameter classes of the c4/c5 lens recipe (workloads.lens_diameters
+bin centres, cylinders of height 0.6, eps 6.25, 15 + 15 static modes) are
+set once; 6 x 6 patches of them (random and lens-like, see learned.py) are
+solved by GPU GMRES (rtol 1e-5)
+for x-polarised plane waves tilted up to 20 degrees in the xz plane; the
+network is trained on the solutions with the library's kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CHECKPOINT = os.path.join(HERE, "checkpoints", "lens_guess.npz")
+
+
+def class_setup(params=None):
+    """A 6 x 6 context holding the 32 lens classes (per-class setup shared
+    by the patch contexts).  Returns (ctx, diameters)."""
+    import numpy as np
+
+    import workloads as w
+    from paper_2407_21724_amd import mlfma
+    wl = w.workload("c4", 6, 6)
+    _, dia = w.lens_diameters(2, 2, 0.5, 20.0)
+    ctx = mlfma.Context(wl.centers, wl.class_id, len(wl.meshes), params or mlfma.default_params())
+    for c, (v, t, e) in enumerate(wl.meshes):
+        M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+        ctx.set_static_modes(c, v, t, e, wl.n_perp, wl.n_par, M, wl.eps_r)
+    return ctx, np.asarray(dia)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--patches", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--seed", type=int, default=2407)
+    ap.add_argument("--out", default=CHECKPOINT)
+    args = ap.parse_args()
+    import torch
+
+    from paper_2407_21724_amd import learned, mlfma
+    torch.cuda.set_device(0)
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    lib_ctx, dia = class_setup()
+    log(f"class setup: {len(dia)} classes in {time.perf_counter() - t0:.1f} s")
+    t1 = time.perf_counter()
+    X, T, pid = learned.solve_patches(lib_ctx, dia, 0.4, len(dia), args.patches, seed=args.seed, log=log)
+    gen_s = time.perf_counter() - t1
+    log(f"{len(X)} samples from {args.patches} patches in {gen_s:.1f} s")
+    net = mlfma.Mlp(learned.sizes(len(dia), 2 * 30), seed=args.seed)
+    t2 = time.perf_counter()
+    hist = learned.train(net, X, T, epochs=args.epochs, seed=args.seed, log=log)
+    train_s = time.perf_counter() - t2
+    meta = {"patches": args.patches, "samples": int(len(X)), "epochs": args.epochs, "seed": args.seed,
+            "generation_s": gen_s, "training_s": train_s, "history": hist,
+            "recipe": "6x6 patches of the 32 lens classes, theta in [0, 20] deg (xz plane, E along theta-hat), "
+                      "GMRES rtol 1e-5"}
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    learned.save(args.out, net, dia, 0.4, meta)
+    log(json.dumps({k: v for k, v in meta.items() if k != "history"}))
+    log(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()
