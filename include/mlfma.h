@@ -291,7 +291,7 @@ int mlfma_mlp_train_step(mlfma_mlp* net, const float* X_dev, const float* T_dev,
  * (re, im) of the 2N coefficients with the incident phase removed; the
  * guess multiplies them by exp(-j k khat . r_p).  EINVAL if the network
  * does not have 11 inputs and 4N outputs.  Synchronous. */
-/* The features described below, [R][P][n_classes + 10] FP32, on the host
+/* The features described below, [R][P][n_classes + 11] FP32, on the host
  * (the inputs a network for mlfma_learned_guess is trained on).  Host-only. */
 int mlfma_guess_features(mlfma_ctx* ctx, const double* class_param, double scale, int32_t R, const double* khat,
                          float* X_host);
@@ -300,10 +300,12 @@ int mlfma_guess_features(mlfma_ctx* ctx, const double* class_param, double scale
  * particle p, in this order: one-hot of its class (n_classes entries; the
  * static-mode basis differs between classes), class_param[class] / scale
  * of the 8 neighbouring sites (dy, dx in -1..1 row-major, centre skipped;
- * 0 where a site holds no particle), khat_x, khat_y.  The network outputs
+ * 0 where a site holds no particle), khat_x, khat_y, and the distance in
+ * sites from p to the nearest edge of the lattice, capped at 6, over 6.
+ * The network outputs
  * (re, im) of the 2N coefficients with the incident phase removed; the
  * guess multiplies them by exp(-j k khat . r_p).  EINVAL if the network
- * does not have n_classes + 10 inputs and 4N outputs.  Synchronous. */
+ * does not have n_classes + 11 inputs and 4N outputs.  Synchronous. */
 int mlfma_learned_guess(mlfma_ctx* ctx, mlfma_mlp* net, const double* class_param, double scale, int32_t R,
                         const double* khat, void* x_dev, void* stream);
 

@@ -819,10 +819,12 @@ int mlfma_mlp_train_step(mlfma_mlp* net, const float* X_dev, const float* T_dev,
 }
 
 namespace {
-// features [R][P][C + 10] and incident phases [R][P] of the learned guess:
+// features [R][P][C + 11] and incident phases [R][P] of the learned guess:
 // one-hot class of p, class_param / scale of the 8 neighbouring sites (0 if
-// empty), khat_x, khat_y
-int guess_nfeat(const mlfma_ctx* ctx) { return ctx->C + 10; }
+// empty), khat_x, khat_y, and the distance in sites to the nearest edge of
+// the lattice, capped at kEdgeCap and divided by it
+constexpr int kEdgeCap = 6;
+int guess_nfeat(const mlfma_ctx* ctx) { return ctx->C + 11; }
 void guess_features(const mlfma_ctx* ctx, const double* class_param, double scale, int R, const double* khat,
                     std::vector<float>& X, std::vector<cd>& phase) {
   const int P = ctx->P, nf = guess_nfeat(ctx);
@@ -844,7 +846,9 @@ void guess_features(const mlfma_ctx* ctx, const double* class_param, double scal
           f[slot++] = q >= 0 ? (float)(class_param[ctx->cls[q]] / scale) : 0.f;
         }
       f[slot++] = (float)kh.x;
-      f[slot] = (float)kh.y;
+      f[slot++] = (float)kh.y;
+      const int edge = std::min(std::min(ix, iy), std::min(ctx->nx - 1 - ix, ctx->ny - 1 - iy));
+      f[slot] = (float)std::min(edge, kEdgeCap) / kEdgeCap;
       const double a = -kK0 * dot(kh, ctx->centers[p]);
       phase[(size_t)r * P + p] = cd(std::cos(a), std::sin(a));
     }
@@ -871,7 +875,7 @@ int mlfma_learned_guess(mlfma_ctx* ctx, mlfma_mlp* net, const double* class_para
     if (ctx->N < 0) return fail(ctx, MLFMA_ENOTREADY, "no class has static modes");
     const int N = ctx->N, n = 2 * N, P = ctx->P;
     if (mlp_inputs(net->m) != guess_nfeat(ctx) || mlp_outputs(net->m) != 2 * n)
-      return fail(ctx, MLFMA_EINVAL, "network must have n_classes + 10 inputs and 4N outputs");
+      return fail(ctx, MLFMA_EINVAL, "network must have n_classes + 11 inputs and 4N outputs");
     std::vector<float> X;
     std::vector<cd> phase;
     guess_features(ctx, class_param, scale, R, khat, X, phase);

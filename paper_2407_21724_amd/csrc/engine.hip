@@ -519,10 +519,10 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
     int prows_max, const C2<T>* __restrict__ Gp, C2<T>* __restrict__ Gc, const int* __restrict__ tth_row,
     const T* __restrict__ tth_w, const int* __restrict__ tth_flip, const int* __restrict__ strip_prow,
     const int* __restrict__ tph_col, const T* __restrict__ tph_w, const C2<T>* __restrict__ phase, int nstrips,
-    int R) {
+    int R, int stage_par) {
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* par = reinterpret_cast<C2<T>*>(smem_raw);    // [prows_max][npp]
-  C2<T>* tmp = par + (size_t)prows_max * npp;           // [prows_max][npc]
+  C2<T>* par = reinterpret_cast<C2<T>*>(smem_raw);                         // [prows_max][npp] if staged
+  C2<T>* tmp = par + (stage_par ? (size_t)prows_max * npp : (size_t)0);     // [prows_max][npc]
   T* ttw = reinterpret_cast<T*>(tmp + (size_t)prows_max * npc);
   T* tpw = ttw + ts * tmax;
   int* ttr = reinterpret_cast<int*>(tpw + npc * pmax);  // parent row relative to plo; -1-row if flipped
@@ -554,14 +554,16 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
   }
   const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)plo * npp;
   const C2<T>* __restrict__ src = Gp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)plo * npp;
-  for (int i = threadIdx.x; i < prows * npp; i += kBlock) par[i] = cmul_conj_a(ph[i], src[i]);
+  if (stage_par)
+    for (int i = threadIdx.x; i < prows * npp; i += kBlock) par[i] = cmul_conj_a(ph[i], src[i]);
   __syncthreads();
   for (int i = threadIdx.x; i < prows * npc; i += kBlock) {
     const int row = fdiv(i, inv_npc), col = i - row * npc;
     C2<T> v{0, 0};
     for (int e = 0; e < pmax; ++e) {
       const T w = tpw[col * pmax + e];
-      const C2<T> t = par[row * npp + tpc[col * pmax + e]];
+      const int c = row * npp + tpc[col * pmax + e];
+      const C2<T> t = stage_par ? par[c] : cmul_conj_a(ph[c], src[c]);  // largest boxes: parent from L2
       v.x += w * t.x;
       v.y += w * t.y;
     }
@@ -914,7 +916,7 @@ class EngineT final : public Engine {
     DevMem S, G;  // pattern buffers, sized for R_alloc
   };
   struct Itp {
-    int order, tmax, pmax, ts_agg, ts_dis, crows_max, prows_max, agg_stage;
+    int order, tmax, pmax, ts_agg, ts_dis, crows_max, prows_max, agg_stage, dis_stage;
     size_t lds_dis, lds_agg;
     DevMem strip_crow, strip_prow;
     DevMem th_row, th_w, th_flip, ph_col, ph_w, tth_row, tth_w, tth_flip, tth_lo, tth_hi, tph_col, tph_w, phase;
@@ -1031,6 +1033,7 @@ class EngineT final : public Engine {
       if (int rc = put_i(I.strip_crow, rng, err)) return rc;
       // disaggregation strips: at most kDisRows child rows; the staged parent
       // rows ([rows][np_p + np_c]) and tables within the LDS budget
+      int stage_par = 1;  // parent rows staged in LDS
       auto dis_plan = [&](int tsd, std::vector<int>& prng, int& pmax_rows) {
         prng.clear();
         pmax_rows = 0;
@@ -1044,8 +1047,8 @@ class EngineT final : public Engine {
           prng.push_back(hi);
           pmax_rows = std::max(pmax_rows, hi - lo + 1);
         }
-        return (size_t)pmax_rows * (Pp.np + C.np) * sizeof(CT) + (size_t)tsd * T0.tmax * (sizeof(T) + 4) +
-               (size_t)C.np * T0.pmax * (sizeof(T) + 4);
+        return (size_t)pmax_rows * ((stage_par ? Pp.np : 0) + C.np) * sizeof(CT) +
+               (size_t)tsd * T0.tmax * (sizeof(T) + 4) + (size_t)C.np * T0.pmax * (sizeof(T) + 4);
       };
       int tsd = C.nt;
       while (tsd > 1 && (size_t)C.nx * C.ny * 2 * ((C.nt + tsd - 1) / tsd) < kMinBlocks) tsd = (tsd + 1) / 2;
@@ -1053,11 +1056,16 @@ class EngineT final : public Engine {
       int pmr = 0;
       size_t ldsd = dis_plan(tsd, prng, pmr);
       while (tsd > 1 && ldsd > kLdsBudget) ldsd = dis_plan(--tsd, prng, pmr);
+      if (ldsd > kLdsBudget) {  // largest boxes: read the parent rows through L2 instead
+        stage_par = 0;
+        ldsd = dis_plan(tsd, prng, pmr);
+      }
       if (ldsd > kLdsMax) {
         err = "disaggregation tile exceeds the LDS limit at level " + std::to_string(l);
         return -1;
       }
       I.ts_dis = tsd;
+      I.dis_stage = stage_par;
       I.prows_max = pmr;
       I.lds_dis = ldsd;
       if (int rc = put_i(I.strip_prow, prng, err)) return rc;
@@ -1540,7 +1548,7 @@ class EngineT final : public Engine {
                              I.ts_dis, I.tmax, I.pmax, I.prows_max, Pp.G.template as<CT>(), L.G.template as<CT>(),
                              I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
                              I.strip_prow.template as<int>(), I.tph_col.template as<int>(),
-                             I.tph_w.template as<T>(), I.phase.template as<CT>(), nstrips, R);
+                             I.tph_w.template as<T>(), I.phase.template as<CT>(), nstrips, R, I.dis_stage);
         }
       }
       if (near && near_grouped) near_sum();

@@ -1,15 +1,16 @@
 """Learned initial guess for GMRES (network kernels in libmlfma).
 
-A fully connected ReLU network (C + 10 -> 256 -> 256 -> 256 -> 4N) maps a
+A fully connected ReLU network (C + 11 -> 256 -> 256 -> 256 -> 4N) maps a
 particle's class (one-hot: each class has its own static-mode basis), its
-eight neighbours' diameters (0 where a site is empty) and the incidence
-direction (khat_x, khat_y) to its static-mode coefficients with the incident
+eight neighbours' diameters (0 where a site is empty), the incidence
+direction (khat_x, khat_y) and its distance to the array edge (capped at 6
+sites) to its static-mode coefficients with the incident
 phase exp(-j k khat . r_p) removed (mlfma_guess_features /
 mlfma_learned_guess).  It is trained on solutions the method itself
 produces: nx x nx patches of the particle classes, each solved by GPU GMRES,
 for plane waves in the xz plane (polar angle up to theta_max, E along
-theta-hat, i.e. x-polarised at normal incidence).  Half of the patches draw
-every site's class at random; the other half vary slowly around a random
+theta-hat, i.e. x-polarised at normal incidence).  A quarter of the patches
+draw every site's class at random; the rest vary slowly around a random
 base class (a random gradient plus +-1 class of noise), like a lens.  The
 training runs on the GPU through the library's own forward, backward and
 Adam kernels; this module only moves arrays.
@@ -29,15 +30,15 @@ HIDDEN = (256, 256, 256)
 
 def sizes(n_classes: int, n_unknowns: int):
     """Layer sizes for C classes and 2N unknowns per particle."""
-    return (n_classes + 10,) + HIDDEN + (2 * n_unknowns,)
+    return (n_classes + 11,) + HIDDEN + (2 * n_unknowns,)
 
 
 def patch_classes(rng, nx, n_classes):
     """Class map of one training patch (see the module docstring)."""
-    if rng.random() < 0.5:
+    if rng.random() < 0.25:
         return rng.integers(0, n_classes, nx * nx)
     base = rng.integers(0, n_classes)
-    gx, gy = rng.uniform(-1.5, 1.5, 2)
+    gx, gy = rng.uniform(-1.0, 1.0, 2) * (6.0 / nx)
     iy, ix = np.meshgrid(np.arange(nx), np.arange(nx), indexing="ij")
     c = base + gx * (ix - nx / 2) + gy * (iy - nx / 2) + rng.uniform(-1, 1, (nx, nx))
     return np.clip(np.rint(c), 0, n_classes - 1).astype(np.int64).ravel()
@@ -61,7 +62,7 @@ def targets(x, centers, khat):
 
 
 def solve_patches(lib_ctx, class_param, scale, n_classes, n_patches, seed=0, nx=6, theta_max_deg=20.0,
-                  rtol=1e-5, params=None, log=None):
+                  rtol=1e-4, params=None, log=None):
     """Solve n_patches random nx x nx patches (classes uniform over
     0..n_classes-1, all set in lib_ctx) and return features X [S][11],
     targets T [S][4N] and the patch index of every sample."""
@@ -78,9 +79,12 @@ def solve_patches(lib_ctx, class_param, scale, n_classes, n_patches, seed=0, nx=
         ctx.share_setup(lib_ctx)
         ctx.prepare()
         b = ctx.plane_wave_rhs(khat[None], pol[None])
-        x, st, rc = ctx.gmres_solve(b, rtol=rtol, max_iter=1000, restart=200)
-        if rc != mlfma.OK:
-            raise mlfma.MlfmaError(rc, f"patch {i} did not converge: {st[0]}")
+        x, st, rc = ctx.gmres_solve(b, rtol=rtol, max_iter=3000, restart=300)
+        if rc != mlfma.OK and not st[0]["true_rel_res"] < 10 * rtol:
+            if log:
+                log(f"patch {i} skipped: {st[0]}")
+            ctx.close()
+            continue
         iters.append(st[0]["iterations"])
         Xs.append(ctx.guess_features(class_param, scale, khat)[0])
         Ts.append(targets(x.cpu().numpy()[0].astype(complex), centers, khat))

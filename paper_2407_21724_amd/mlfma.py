@@ -210,12 +210,12 @@ class Context:
         self._shared_from = src          # keeps the source alive for readability; the data is refcounted
 
     def guess_features(self, class_param, scale, khat):
-        """Network inputs [R][P][n_classes + 10] of mlfma_learned_guess (host)."""
+        """Network inputs [R][P][n_classes + 11] of mlfma_learned_guess (host)."""
         khat = np.ascontiguousarray(np.atleast_2d(khat), np.float64)
         cp = np.ascontiguousarray(class_param, np.float64)
         if len(cp) != self.n_classes:
             raise ValueError("class_param needs one entry per class")
-        out = np.zeros((len(khat), self.n_particles, self.n_classes + 10), np.float32)
+        out = np.zeros((len(khat), self.n_particles, self.n_classes + 11), np.float32)
         self._check(lib().mlfma_guess_features(self._h, _dptr(cp), float(scale), len(khat), _dptr(khat),
                                                out.ctypes.data_as(C.POINTER(C.c_float))), "guess_features")
         return out

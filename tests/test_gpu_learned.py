@@ -74,11 +74,11 @@ def test_adam_step_matches_reference():
 
 def test_training_fits_a_teacher_network():
     rng = np.random.default_rng(9)
-    teacher = mlfma.Mlp((11, 32, 8), seed=11)
-    X = rng.standard_normal((4096, 11)).astype(np.float32)
+    teacher = mlfma.Mlp((12, 32, 8), seed=11)
+    X = rng.standard_normal((4096, 12)).astype(np.float32)
     Xd = torch.as_tensor(X, device="cuda")
     T = teacher.forward(Xd).clone()
-    net = mlfma.Mlp((11, 64, 64, 8), seed=12)
+    net = mlfma.Mlp((12, 64, 64, 8), seed=12)
     first = None
     for step in range(400):
         idx = torch.as_tensor(rng.integers(0, 4096, 256), device="cuda")
