@@ -83,7 +83,8 @@ def measured_traffic(sym):
         return None
     if rec.get("source_sha256") != source_digest():
         return None
-    k = rec.get("kernels", {}).get(sym)
+    ks = rec.get("kernels", {})
+    k = ks.get(sym, ks.get(sym + "<float>"))     # counter files name template kernels with their arguments
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
@@ -91,7 +92,8 @@ def pmc_digest(fetch_csv, write_csv, copy_mib, out_path):
     """Turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE; KiB per
     dispatch) into HBM bytes per launch per kernel symbol.  Each counter is
     scaled by the ratio of known bytes to its reading on the plain copy
-    kernel of the calibration (the largest dispatch of the run)."""
+    kernel of the calibration (the runtime's device copy of copy_mib MiB that
+    --copy-calibration makes, the largest copy dispatch of the run)."""
     import csv
     from collections import defaultdict
 
@@ -106,8 +108,14 @@ def pmc_digest(fetch_csv, write_csv, copy_mib, out_path):
 
     fetch, write = read(fetch_csv, "FETCH_SIZE"), read(write_csv, "WRITE_SIZE")
     copy_bytes = copy_mib * 2 ** 20
-    cal_f = max(max(v) for v in fetch.values()) * 1024.0
-    cal_w = max(max(v) for v in write.values()) * 1024.0
+
+    def calib(per):   # the largest dispatch of the runtime's device-to-device copy kernel
+        vals = [max(v) for k, v in per.items() if "copyBuffer" in k]
+        if not vals:
+            raise RuntimeError("no copy kernel in the counter file (run bench.py with --copy-calibration)")
+        return max(vals) * 1024.0
+
+    cal_f, cal_w = calib(fetch), calib(write)
     sf, sw = copy_bytes / cal_f, copy_bytes / cal_w
     kernels = {}
     for name in fetch:
@@ -166,6 +174,46 @@ def cpu_baseline(wl, M):
                        f"{P * P} block products = {T:.0f} s per product")}
 
 
+def lens_gmres(torch, w, mlfma):
+    """80 x 80 metalens (32 diameter classes, 384,000 unknowns, FP32 product):
+    GMRES(300) time to a 1e-4 true residual from zero and from the learned
+    initial guess of the committed checkpoint."""
+    from paper_2407_21724_amd import learned
+    ckpt = os.path.join(ROOT, "paper_2407_21724_amd", "checkpoints", "lens_guess.npz")
+    wl = w.workload("c4")
+    t0 = time.perf_counter()
+    ctx = mlfma.Context(wl.centers, wl.class_id, len(wl.meshes), mlfma.default_params(precision=mlfma.C64))
+    for c in sorted(set(wl.class_id.tolist())):
+        v, t, e = wl.meshes[c]
+        M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+        ctx.set_static_modes(c, v, t, e, wl.n_perp, wl.n_par, M, wl.eps_r)
+    ctx.prepare()
+    setup_s = time.perf_counter() - t0
+    inc = wl.incidences[0]
+    b = ctx.plane_wave_rhs(inc.khat[None], inc.pol[None])
+    res = {"workload": "80x80 metalens, 32 classes, 384000 unknowns, normal incidence, FP32 product",
+           "restart": 300, "setup_s": setup_s}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st, _ = ctx.gmres_solve(b, rtol=1e-4, max_iter=4000, restart=300)
+    torch.cuda.synchronize()
+    res["plain"] = {"time_to_1e-4_s": time.perf_counter() - t0, "iterations": st[0]["iterations"],
+                    "true_rel_res": st[0]["true_rel_res"], "converged": st[0]["converged"]}
+    if os.path.exists(ckpt):
+        net, dia, scale, meta = learned.load(ckpt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x0 = ctx.learned_guess(net, dia, scale, inc.khat[None])
+        _, st, _ = ctx.gmres_solve(b, x=x0, rtol=1e-4, max_iter=4000, restart=300, use_x0=True)
+        torch.cuda.synchronize()
+        res["learned"] = {"time_to_1e-4_s": time.perf_counter() - t0, "iterations": st[0]["iterations"],
+                          "true_rel_res": st[0]["true_rel_res"], "converged": st[0]["converged"],
+                          "includes": "feature build + network inference + GMRES",
+                          "checkpoint": {k: meta[k] for k in ("patches", "patch_side", "samples")}}
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +222,8 @@ def main():
     ap.add_argument("--rhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-lens", action="store_true",
+                    help="skip the 80 x 80 metalens GMRES comparison (zero start vs learned start)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--pmc-digest", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -285,6 +335,8 @@ def main():
                         "true_rel_res": st[0]["true_rel_res"], "converged": st[0]["converged"],
                         "restart": 100, "rhs": 1, "initial_guess": "zero", "reorth": st[0]["reorth"],
                         "cycles": st[0]["cycles"]}
+    if not args.no_gmres and not args.no_lens:
+        out["gmres_lens"] = lens_gmres(torch, w, mlfma)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
