@@ -222,6 +222,7 @@ def main():
     ap.add_argument("--rhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default interpolation tile shapes")
     ap.add_argument("--no-lens", action="store_true",
                     help="skip the 80 x 80 metalens GMRES comparison (zero start vs learned start)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -266,6 +267,13 @@ def main():
     setup_s = time.perf_counter() - t0 + modes_s
     info = ctx.info()
     R = args.rhs
+    tuning = None
+    if not args.no_autotune:
+        from paper_2407_21724_amd import autotune
+        t0 = time.perf_counter()
+        rep = autotune.autotune(ctx, R=R, reps=3)
+        tuning = {"seconds": time.perf_counter() - t0, "agg_rows": rep["tuned"][0], "dis_rows": rep["tuned"][1],
+                  "default_agg_rows": rep["default"][0], "default_dis_rows": rep["default"][1]}
     P, n = wl.n_particles, 2 * (wl.n_perp + wl.n_par)
     x = torch.as_tensor(w.random_complex((R, P, n), 1)).to("cuda", torch.complex64).contiguous()
     y = torch.empty_like(x)
@@ -323,6 +331,7 @@ def main():
         "stages_us": {s["name"]: round(1e3 * s["total_ms"] / s["launches"], 2) for s in stages},
         "kernels_us": {g["kernel"]: round(1e3 * g["total_ms"] / g["launches"], 2) for g in groups.values()},
         "setup_s": setup_s,
+        "autotune": tuning,
     }
     if not args.no_gmres:
         inc = w.normal_incidence_x()

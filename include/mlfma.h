@@ -211,6 +211,22 @@ int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R,
                       int32_t max_iter, int32_t restart, int32_t flags, mlfma_solve_stats* stats,
                       void* stream);
 
+/* Tile shapes of the interpolation kernels: agg_rows[l] parent theta rows
+ * per block of the aggregation into level l (l >= 1), dis_rows[l] child
+ * theta rows per block of the disaggregation into level l (l < n_levels - 1);
+ * 0 selects the built-in planner.  set re-plans the strips (the product's
+ * arithmetic is unchanged, only its blocking) and fails with EINVAL if a
+ * tile does not fit in LDS; get returns the heights in use.  Prepares the
+ * context if needed.  Used by the autotuner of the binding. */
+#define MLFMA_MAX_LEVELS 16
+typedef struct {
+  int32_t n_levels;
+  int32_t agg_rows[MLFMA_MAX_LEVELS];
+  int32_t dis_rows[MLFMA_MAX_LEVELS];
+} mlfma_tuning;
+int mlfma_set_tuning(mlfma_ctx* ctx, const mlfma_tuning* t);
+int mlfma_get_tuning(mlfma_ctx* ctx, mlfma_tuning* t);
+
 /* Per-kernel timing: while enabled, every kernel launch of mlfma_matvec is
  * bracketed by HIP events recorded on the launch stream.  Enabling clears
  * the accumulated table. */

@@ -1,0 +1,75 @@
+"""Autotuner of the interpolation kernels' tile shapes.
+
+For every level it times the aggregation and the disaggregation with each
+candidate strip height (theta rows per block), using the library's
+dispatch-timed profiling of real products, and keeps the fastest.  A strip
+height changes only how the kernels block the work, not any output value
+(each output is computed by the same arithmetic in the same order), so the
+tuned product is bitwise identical to the default one.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import mlfma
+
+CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48)
+
+
+def _stage_times(ctx, x, y, reps):
+    ctx.profile(True)
+    for _ in range(reps):
+        ctx.matvec(x, out=y)
+    st = ctx.profile_read()
+    ctx.profile(False)
+    return {s["name"]: s["total_ms"] / s["launches"] for s in st}
+
+
+def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDATES, log=None):
+    """Tune ctx in place for products with R right-hand sides.  Returns
+    {"default": (agg, dis), "tuned": (agg, dis), "stage_us": {...}}."""
+    import torch
+    L = ctx.info()["n_levels"]
+    if L < 2:
+        return {"default": ctx.get_tuning(), "tuned": ctx.get_tuning(), "stage_us": {}}
+    n = 2 * ctx.n_modes
+    rng = np.random.default_rng(0)
+    x = torch.as_tensor(rng.standard_normal((R, ctx.n_particles, n)) + 1j * rng.standard_normal(
+        (R, ctx.n_particles, n))).to("cuda", ctx.dtype).contiguous()
+    y = torch.empty_like(x)
+    default = ctx.get_tuning()
+    agg, dis = [list(v) for v in default]
+    ctx.matvec(x, out=y)
+    base = _stage_times(ctx, x, y, reps)
+    report = {}
+    for kind, idx_range in (("aggregate", range(1, L)), ("disaggregate", range(0, L - 1))):
+        for l in idx_range:
+            name = f"{kind}_l{l}"
+            cur = agg if kind == "aggregate" else dis
+            best_h, best_t = cur[l], base.get(name, float("inf"))
+            tried = {cur[l]: best_t}
+            for h in candidates:
+                if h in tried:
+                    continue
+                trial = list(cur)
+                trial[l] = h
+                try:
+                    if kind == "aggregate":
+                        ctx.set_tuning(trial, dis)
+                    else:
+                        ctx.set_tuning(agg, trial)
+                except mlfma.MlfmaError:
+                    continue           # tile does not fit (or taller than the level)
+                t = _stage_times(ctx, x, y, reps).get(name, float("inf"))
+                tried[h] = t
+                if t < best_t:
+                    best_h, best_t = h, t
+            cur[l] = best_h
+            ctx.set_tuning(agg, dis)
+            report[name] = {"default_us": 1e3 * base.get(name, float("nan")), "tuned_us": 1e3 * best_t,
+                            "rows": best_h, "tried_us": {int(k): round(1e3 * v, 2) for k, v in tried.items()}}
+            if log:
+                log(f"{name}: {report[name]['default_us']:.1f} us -> {report[name]['tuned_us']:.1f} us "
+                    f"({best_h} rows)")
+    ctx.set_tuning(agg, dis)
+    return {"default": default, "tuned": (agg, dis), "stage_us": report}

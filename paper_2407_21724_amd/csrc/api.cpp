@@ -465,6 +465,40 @@ int mlfma_set_static_modes(mlfma_ctx* ctx, int32_t class_id, int32_t nv, const d
   });
 }
 
+int mlfma_set_tuning(mlfma_ctx* ctx, const mlfma_tuning* t) {
+  if (!ctx || !t) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    if (int rc = do_prepare(ctx)) return rc;
+    const int L = ctx->tree.ntl;
+    if (t->n_levels != L || L > MLFMA_MAX_LEVELS) return fail(ctx, MLFMA_EINVAL, "n_levels does not match the tree");
+    std::vector<int> a(L, 0), d(L, 0);
+    for (int l = 0; l < L; ++l) {
+      if (t->agg_rows[l] < 0 || t->dis_rows[l] < 0) return fail(ctx, MLFMA_EINVAL, "negative strip height");
+      a[l] = t->agg_rows[l];
+      d[l] = t->dis_rows[l];
+    }
+    std::string err;
+    int rc = ctx->eng->set_tuning(a, d, err);
+    return rc ? fail(ctx, rc == -1 ? MLFMA_EINVAL : rc, err) : MLFMA_OK;
+  });
+}
+
+int mlfma_get_tuning(mlfma_ctx* ctx, mlfma_tuning* t) {
+  if (!ctx || !t) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    if (int rc = do_prepare(ctx)) return rc;
+    std::vector<int> a, d;
+    ctx->eng->get_tuning(a, d);
+    std::memset(t, 0, sizeof(*t));
+    t->n_levels = ctx->tree.ntl;
+    for (int l = 0; l < ctx->tree.ntl && l < MLFMA_MAX_LEVELS; ++l) {
+      t->agg_rows[l] = a[l];
+      t->dis_rows[l] = d[l];
+    }
+    return MLFMA_OK;
+  });
+}
+
 int mlfma_share_setup(mlfma_ctx* dst, const mlfma_ctx* src) {
   if (!dst || !src || dst == src) return MLFMA_EINVAL;
   return guarded(dst, [&]() -> int {

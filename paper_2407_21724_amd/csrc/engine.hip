@@ -929,6 +929,7 @@ class EngineT final : public Engine {
     P_ = u.P;
     nc_ = u.n_classes;
     const Tree& tr = *u.tree;
+    tree_ = u.tree;
     ntl_ = tr.ntl;
     lv_.clear();
     lv_.resize(ntl_);
@@ -983,92 +984,7 @@ class EngineT final : public Engine {
       if (int rc = put_i(I.tph_col, T0.tph_col, err)) return rc;
       if (int rc = put_r(I.tph_w, T0.tph_w, err)) return rc;
       if (int rc = put_c(I.phase, T0.phase, err)) return rc;
-      // aggregation strips: each thread owns at most kAggVPT outputs; the
-      // strip's child rows and stencil tables are staged in LDS
-      const Lvl &C = lv_[l - 1], &Pp = lv_[l];
-      if (Pp.np > kBlock * kAggVPT) {
-        err = "aggregation: more than " + std::to_string(kBlock * kAggVPT) + " phi samples per row at level " +
-              std::to_string(l);
-        return -1;
-      }
-      const int order = T0.order;
-      int nstage = 4;  // children staged per pass
-      auto agg_plan = [&](int ts, std::vector<int>& rng, int& cmax) {
-        rng.clear();
-        cmax = 0;
-        for (int r0 = 0; r0 < Pp.nt; r0 += ts) {
-          int lo = C.nt, hi = -1;
-          for (int it = r0; it < std::min(Pp.nt, r0 + ts); ++it)
-            for (int a2 = 0; a2 < order; ++a2) {
-              lo = std::min(lo, T0.th_row[(size_t)it * order + a2]);
-              hi = std::max(hi, T0.th_row[(size_t)it * order + a2]);
-            }
-          rng.push_back(lo);
-          rng.push_back(hi);
-          cmax = std::max(cmax, hi - lo + 1);
-        }
-        return (size_t)nstage * (cmax + ts) * C.np * sizeof(CT) + (size_t)ts * order * (sizeof(T) + 4) +
-               (size_t)Pp.np * order * (sizeof(T) + 4);
-      };
-      // strip height: bounded by the per-thread outputs; split further only
-      // while the grid has fewer than kMinBlocks blocks
-      int ts = std::max(1, std::min(Pp.nt, (kBlock * kAggVPT) / Pp.np));
-      while (ts > 1 && (size_t)Pp.nx * Pp.ny * 2 * ((Pp.nt + ts - 1) / ts) < kMinBlocks) ts = (ts + 1) / 2;
-      std::vector<int> rng;
-      int cmax = 0;
-      size_t lds = agg_plan(ts, rng, cmax);
-      while (ts > 1 && lds > kLdsBudget) lds = agg_plan(--ts, rng, cmax);
-      if (lds > kLdsBudget) {  // largest boxes: one child per pass
-        nstage = 1;
-        lds = agg_plan(ts, rng, cmax);
-      }
-      if (lds > kLdsMax) {
-        err = "aggregation tile exceeds the LDS limit at level " + std::to_string(l);
-        return -1;
-      }
-      I.ts_agg = ts;
-      I.agg_stage = nstage;
-      I.crows_max = cmax;
-      I.lds_agg = lds;
-      if (int rc = put_i(I.strip_crow, rng, err)) return rc;
-      // disaggregation strips: at most kDisRows child rows; the staged parent
-      // rows ([rows][np_p + np_c]) and tables within the LDS budget
-      int stage_par = 1;  // parent rows staged in LDS
-      auto dis_plan = [&](int tsd, std::vector<int>& prng, int& pmax_rows) {
-        prng.clear();
-        pmax_rows = 0;
-        for (int c0 = 0; c0 < C.nt; c0 += tsd) {
-          int lo = Pp.nt, hi = -1;
-          for (int rr = c0; rr < std::min(C.nt, c0 + tsd); ++rr) {
-            lo = std::min(lo, T0.tth_lo[rr]);
-            hi = std::max(hi, T0.tth_hi[rr]);
-          }
-          prng.push_back(lo);
-          prng.push_back(hi);
-          pmax_rows = std::max(pmax_rows, hi - lo + 1);
-        }
-        return (size_t)pmax_rows * ((stage_par ? Pp.np : 0) + C.np) * sizeof(CT) +
-               (size_t)tsd * T0.tmax * (sizeof(T) + 4) + (size_t)C.np * T0.pmax * (sizeof(T) + 4);
-      };
-      int tsd = C.nt;
-      while (tsd > 1 && (size_t)C.nx * C.ny * 2 * ((C.nt + tsd - 1) / tsd) < kMinBlocks) tsd = (tsd + 1) / 2;
-      std::vector<int> prng;
-      int pmr = 0;
-      size_t ldsd = dis_plan(tsd, prng, pmr);
-      while (tsd > 1 && ldsd > kLdsBudget) ldsd = dis_plan(--tsd, prng, pmr);
-      if (ldsd > kLdsBudget) {  // largest boxes: read the parent rows through L2 instead
-        stage_par = 0;
-        ldsd = dis_plan(tsd, prng, pmr);
-      }
-      if (ldsd > kLdsMax) {
-        err = "disaggregation tile exceeds the LDS limit at level " + std::to_string(l);
-        return -1;
-      }
-      I.ts_dis = tsd;
-      I.dis_stage = stage_par;
-      I.prows_max = pmr;
-      I.lds_dis = ldsd;
-      if (int rc = put_i(I.strip_prow, prng, err)) return rc;
+      if (int rc = plan_level(l, 0, 0, err)) return rc;
     }
     // leaf data
     nx0_ = u.nx0;
@@ -1287,6 +1203,142 @@ class EngineT final : public Engine {
       if (int rc = put_i(ng_has_, has, err)) return rc;
     }
     return 0;
+  }
+
+  // Strip plans of the interpolation kernels into level l (aggregation
+  // l-1 -> l) and out of it (disaggregation l -> l-1): agg_rows parent rows
+  // and dis_rows child rows per block, 0 for the default planner (the
+  // tallest strip whose tile fits the preferred LDS size while the grid keeps
+  // at least kMinBlocks blocks).
+  int plan_level(int l, int agg_rows, int dis_rows, std::string& err) {
+    // aggregation strips: each thread owns at most kAggVPT outputs; the
+    // strip's child rows and stencil tables are staged in LDS
+    const Lvl &C = lv_[l - 1], &Pp = lv_[l];
+    const InterpTables& T0 = tree_->it[l];
+    Itp& I = it_[l];
+    if (Pp.np > kBlock * kAggVPT) {
+      err = "aggregation: more than " + std::to_string(kBlock * kAggVPT) + " phi samples per row at level " +
+            std::to_string(l);
+      return -1;
+    }
+    const int order = T0.order;
+    int nstage = 4;  // children staged per pass
+    auto agg_plan = [&](int ts, std::vector<int>& rng, int& cmax) {
+      rng.clear();
+      cmax = 0;
+      for (int r0 = 0; r0 < Pp.nt; r0 += ts) {
+        int lo = C.nt, hi = -1;
+        for (int it = r0; it < std::min(Pp.nt, r0 + ts); ++it)
+          for (int a2 = 0; a2 < order; ++a2) {
+            lo = std::min(lo, T0.th_row[(size_t)it * order + a2]);
+            hi = std::max(hi, T0.th_row[(size_t)it * order + a2]);
+          }
+        rng.push_back(lo);
+        rng.push_back(hi);
+        cmax = std::max(cmax, hi - lo + 1);
+      }
+      return (size_t)nstage * (cmax + ts) * C.np * sizeof(CT) + (size_t)ts * order * (sizeof(T) + 4) +
+             (size_t)Pp.np * order * (sizeof(T) + 4);
+    };
+    // strip height: bounded by the per-thread outputs; split further only
+    // while the grid has fewer than kMinBlocks blocks
+    const int ts_cap = std::max(1, std::min(Pp.nt, (kBlock * kAggVPT) / Pp.np));
+    int ts = ts_cap;
+    while (ts > 1 && (size_t)Pp.nx * Pp.ny * 2 * ((Pp.nt + ts - 1) / ts) < kMinBlocks) ts = (ts + 1) / 2;
+    if (agg_rows > 0) {
+      if (agg_rows > ts_cap) {
+        err = "aggregation strip of " + std::to_string(agg_rows) + " rows exceeds " + std::to_string(ts_cap) +
+              " at level " + std::to_string(l);
+        return -1;
+      }
+      ts = agg_rows;
+    }
+    std::vector<int> rng;
+    int cmax = 0;
+    size_t lds = agg_plan(ts, rng, cmax);
+    if (agg_rows == 0)
+      while (ts > 1 && lds > kLdsBudget) lds = agg_plan(--ts, rng, cmax);
+    if (lds > kLdsBudget) {  // largest boxes: one child per pass
+      nstage = 1;
+      lds = agg_plan(ts, rng, cmax);
+    }
+    if (lds > kLdsMax) {
+      err = "aggregation tile exceeds the LDS limit at level " + std::to_string(l);
+      return -1;
+    }
+    I.ts_agg = ts;
+    I.agg_stage = nstage;
+    I.crows_max = cmax;
+    I.lds_agg = lds;
+    if (int rc = put_i(I.strip_crow, rng, err)) return rc;
+    // disaggregation strips: at most kDisRows child rows; the staged parent
+    // rows ([rows][np_p + np_c]) and tables within the LDS budget
+    int stage_par = 1;  // parent rows staged in LDS
+    auto dis_plan = [&](int tsd, std::vector<int>& prng, int& pmax_rows) {
+      prng.clear();
+      pmax_rows = 0;
+      for (int c0 = 0; c0 < C.nt; c0 += tsd) {
+        int lo = Pp.nt, hi = -1;
+        for (int rr = c0; rr < std::min(C.nt, c0 + tsd); ++rr) {
+          lo = std::min(lo, T0.tth_lo[rr]);
+          hi = std::max(hi, T0.tth_hi[rr]);
+        }
+        prng.push_back(lo);
+        prng.push_back(hi);
+        pmax_rows = std::max(pmax_rows, hi - lo + 1);
+      }
+      return (size_t)pmax_rows * ((stage_par ? Pp.np : 0) + C.np) * sizeof(CT) +
+             (size_t)tsd * T0.tmax * (sizeof(T) + 4) + (size_t)C.np * T0.pmax * (sizeof(T) + 4);
+    };
+    int tsd = C.nt;
+    while (tsd > 1 && (size_t)C.nx * C.ny * 2 * ((C.nt + tsd - 1) / tsd) < kMinBlocks) tsd = (tsd + 1) / 2;
+    if (dis_rows > 0) tsd = std::min(dis_rows, C.nt);
+    std::vector<int> prng;
+    int pmr = 0;
+    size_t ldsd = dis_plan(tsd, prng, pmr);
+    if (dis_rows == 0)
+      while (tsd > 1 && ldsd > kLdsBudget) ldsd = dis_plan(--tsd, prng, pmr);
+    if (ldsd > kLdsBudget) {  // largest boxes: read the parent rows through L2 instead
+      stage_par = 0;
+      ldsd = dis_plan(tsd, prng, pmr);
+    }
+    if (ldsd > kLdsMax) {
+      err = "disaggregation tile exceeds the LDS limit at level " + std::to_string(l);
+      return -1;
+    }
+    I.ts_dis = tsd;
+    I.dis_stage = stage_par;
+    I.prows_max = pmr;
+    I.lds_dis = ldsd;
+    if (int rc = put_i(I.strip_prow, prng, err)) return rc;
+    return 0;
+  }
+
+  // All levels or none: on a tile that does not fit, the previous plan is
+  // restored.
+  int set_tuning(const std::vector<int>& agg_rows, const std::vector<int>& dis_rows, std::string& err) override {
+    std::vector<int> pa, pd;
+    get_tuning(pa, pd);
+    clear_graphs();
+    for (int l = 1; l < ntl_; ++l) {
+      const int a = l < (int)agg_rows.size() ? agg_rows[l] : 0;
+      const int d = l - 1 < (int)dis_rows.size() ? dis_rows[l - 1] : 0;
+      if (int rc = plan_level(l, a, d, err)) {
+        std::string ignored;
+        for (int k = 1; k < ntl_; ++k) (void)plan_level(k, pa[k], pd[k - 1], ignored);
+        return rc;
+      }
+    }
+    return 0;
+  }
+
+  void get_tuning(std::vector<int>& agg_rows, std::vector<int>& dis_rows) const override {
+    agg_rows.assign(std::max(ntl_, 1), 0);
+    dis_rows.assign(std::max(ntl_, 1), 0);
+    for (int l = 1; l < ntl_; ++l) {
+      agg_rows[l] = it_[l].ts_agg;
+      dis_rows[l - 1] = it_[l].ts_dis;
+    }
   }
 
   // near-field products of the class-pair GEMM: partial[r][o * P + p][:]
@@ -1773,6 +1825,7 @@ class EngineT final : public Engine {
   int N_ = 0, n_ = 0, P_ = 0, nc_ = 0, ntl_ = 0, nx0_ = 0, ny0_ = 0, ntiles_ = 0, tp_ = 0, M2_ = 0, R_alloc_ = 0;
   std::vector<Lvl> lv_;
   std::vector<Itp> it_;
+  const Tree* tree_ = nullptr;
   DevMem box_of_, class_of_, order_, tile_start_, tile_count_, tile_class_;
   DevMem Rm_, Qm_, rm_off_, qm_off_;
   DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;

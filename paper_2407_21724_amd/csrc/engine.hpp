@@ -66,6 +66,10 @@ class Engine {
   virtual int gmres(const void* b, void* x, int R, double rtol, int max_iter, int restart, bool use_x0,
                     bool always_reorth, std::vector<GmresResult>& res, void* stream, std::string& err) = 0;
   virtual long long device_bytes() const = 0;
+  // interpolation strip heights per level (0 = default planner); agg_rows
+  // indexed by the parent level, dis_rows by the child level
+  virtual int set_tuning(const std::vector<int>& agg_rows, const std::vector<int>& dis_rows, std::string& err) = 0;
+  virtual void get_tuning(std::vector<int>& agg_rows, std::vector<int>& dis_rows) const = 0;
 };
 
 Engine* make_engine(int precision);

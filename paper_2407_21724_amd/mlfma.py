@@ -51,6 +51,10 @@ class StageTime(C.Structure):
                 ("bytes_per_launch", C.c_double), ("flops_per_launch", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("agg_rows", C.c_int32 * 16), ("dis_rows", C.c_int32 * 16)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("true_rel_res", C.c_double), ("time_s", C.c_double),
                 ("converged", C.c_int32), ("reorth", C.c_int32), ("cycles", C.c_int32)]
@@ -64,7 +68,8 @@ EXPORTS = [
     "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read", "mlfma_share_setup",
     "mlfma_mlp_create", "mlfma_mlp_destroy", "mlfma_mlp_last_error", "mlfma_mlp_num_params",
     "mlfma_mlp_get_params", "mlfma_mlp_set_params", "mlfma_mlp_forward", "mlfma_mlp_loss_grad",
-    "mlfma_mlp_train_step", "mlfma_learned_guess", "mlfma_guess_features",
+    "mlfma_mlp_train_step", "mlfma_learned_guess", "mlfma_guess_features", "mlfma_set_tuning",
+    "mlfma_get_tuning",
 ]
 
 
@@ -98,6 +103,8 @@ def load_library(path: str = _LIB_PATH):
         "mlfma_debug_level_grid": (C.c_int, [ctxp, C.c_int32, dp, dp]),
         "mlfma_debug_translation": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, dp]),
         "mlfma_share_setup": (C.c_int, [ctxp, ctxp]),
+        "mlfma_set_tuning": (C.c_int, [ctxp, C.POINTER(Tuning)]),
+        "mlfma_get_tuning": (C.c_int, [ctxp, C.POINTER(Tuning)]),
         "mlfma_mlp_create": (C.c_int, [C.c_int32, ip, C.c_uint64, C.POINTER(C.c_void_p)]),
         "mlfma_mlp_destroy": (None, [vp]),
         "mlfma_mlp_last_error": (C.c_char_p, [vp]),
@@ -202,6 +209,20 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def get_tuning(self):
+        """(agg_rows, dis_rows): interpolation strip heights per level."""
+        t = Tuning()
+        self._check(lib().mlfma_get_tuning(self._h, C.byref(t)), "get_tuning")
+        return list(t.agg_rows[:t.n_levels]), list(t.dis_rows[:t.n_levels])
+
+    def set_tuning(self, agg_rows, dis_rows):
+        t = Tuning()
+        t.n_levels = len(agg_rows)
+        for i, (a, d) in enumerate(zip(agg_rows, dis_rows)):
+            t.agg_rows[i] = int(a)
+            t.dis_rows[i] = int(d)
+        self._check(lib().mlfma_set_tuning(self._h, C.byref(t)), "set_tuning")
 
     def share_setup(self, src: "Context"):
         """Use src's per-class setup and neighbour-block cache (mlfma_share_setup)."""

@@ -15,6 +15,11 @@ y = Z x for the seeded x = workloads.random_complex((P, 2N), seed=1):
   c4_8x8.npz        all 64 particles of an 8 x 8 metalens of the c4 recipe
                     (several diameter classes; M holds each used class's
                     modes, `classes` their class ids)
+  c5_10x10_fields.npz  a 10 x 10 lens of the c5 recipe solved densely for the
+                    normal-incidence x-polarised wave: the solution, the
+                    scattered near field on the plane z = 1 over the array
+                    (21 x 21 points) and the far-field amplitude on a
+                    16 x 32 sphere grid
 """
 from __future__ import annotations
 
@@ -60,7 +65,39 @@ def make_lens(name: str):
     print(f"{name}: {P} rows, classes {used} in {time.time() - t0:.1f} s -> {out}", flush=True)
 
 
+def make_lens_fields(name: str):
+    from oracle.fields import far_amplitude, near_field, sphere_grid
+    from oracle.pmchwt import solve_dense
+    t0 = time.time()
+    wl = w.workload("c5", 10, 10)
+    used = sorted(set(wl.class_id.tolist()))
+    pcs = []
+    for c in used:
+        v, t, e = wl.meshes[c]
+        pcs.append(ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r))
+    compact = np.array([used.index(c) for c in wl.class_id], np.int32)
+    prob = DenseProblem(pcs, wl.centers, compact)
+    P = wl.n_particles
+    prob.prefetch([(mu, nu) for mu in range(P) for nu in range(P)])
+    inc = wl.incidences[0]
+    V = prob.rhs(inc.khat, inc.pol)
+    J = solve_dense(prob, V)
+    g = np.linspace(-0.5, 5.0, 21)
+    X, Y = np.meshgrid(g, g)
+    pts = np.stack([X.ravel(), Y.ravel(), np.full(X.size, 1.0)], -1)
+    near = near_field(prob, J, pts)
+    rhat, _ = sphere_grid(16, 32)
+    far = far_amplitude(prob, J, rhat)
+    out = os.path.join(HERE, name + ".npz")
+    np.savez_compressed(out, M=np.stack([pc.M for pc in pcs]), classes=np.array(used, np.int32), J=J, V=V,
+                        pts=pts, near=near, rhat=rhat, far=far, khat=inc.khat, pol=inc.pol, eps_r=wl.eps_r,
+                        n_perp=wl.n_perp, n_par=wl.n_par, nx=10, ny=10)
+    print(f"{name}: classes {used}, solved and fields in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
 def make(name: str):
+    if name == "c5_10x10_fields":
+        return make_lens_fields(name)
     if name.startswith("c4_"):
         return make_lens(name)
     t0 = time.time()

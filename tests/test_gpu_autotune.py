@@ -1,0 +1,35 @@
+"""The autotuner changes only the blocking of the interpolation kernels:
+the tuned product is bitwise identical to the default one, and invalid
+tile shapes are rejected."""
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_helpers import make_ctx, note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2407_21724_amd import autotune, mlfma  # noqa: E402
+
+
+def test_tuned_product_is_bitwise_identical():
+    wl = w.workload("c2", 16, 16)
+    v, t, e = wl.meshes[0]
+    M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+    ctx = make_ctx(wl, M, mlfma.C64)
+    x = torch.as_tensor(w.random_complex((2, wl.n_particles, 60), 3)).to("cuda", torch.complex64).contiguous()
+    y0 = ctx.matvec(x).cpu().numpy()
+    rep = autotune.autotune(ctx, R=2, reps=2, candidates=(1, 2, 4, 8))
+    note(f"tuned {rep['tuned']} from {rep['default']}")
+    y1 = ctx.matvec(x).cpu().numpy()
+    assert np.array_equal(y0, y1)
+    agg, dis = ctx.get_tuning()
+    with pytest.raises(mlfma.MlfmaError):
+        ctx.set_tuning([a + 10000 for a in agg], dis)      # taller than any level
+    ctx.set_tuning([0] * len(agg), [0] * len(dis))
+    assert ctx.get_tuning() == rep["default"]
+    assert np.array_equal(ctx.matvec(x).cpu().numpy(), y0)
