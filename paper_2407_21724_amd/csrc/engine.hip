@@ -587,6 +587,78 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
   }
 }
 
+// Two-pass disaggregation for the largest boxes, where a strip of parent
+// rows does not fit in LDS.  Pass 1 (phi): for every parent box, component,
+// child quadrant q and parent row,
+//   H[q][row][c] = sum_e tph_w[c][e] conj(phase_q[row][tph_col[c][e]]) G_p[row][tph_col[c][e]]
+// Pass 2 (theta): G_c[row][c] += sum_e tth_w[row][e] H[q][tth_row[row][e]][c or c + np/2 if flipped].
+// Block = one parent row of one (RHS, box, component): the row is multiplied
+// by the four quadrants' conjugate phases into LDS ([4][npp]) and every
+// thread forms outputs of all four H rows from it.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dis_phi(int nbp, int ntp, int npp, int npc, int pmax, int R,
+                                                    const C2<T>* __restrict__ Gp, const int* __restrict__ tph_col,
+                                                    const T* __restrict__ tph_w, const C2<T>* __restrict__ phase,
+                                                    C2<T>* __restrict__ H) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* pq = reinterpret_cast<C2<T>*>(smem_raw);  // [4][npp]
+  const long Kp = (long)ntp * npp;
+  const int row = blockIdx.x % ntp;
+  const long bc = blockIdx.x / ntp;  // (r * nbp + pb) * 2 + comp
+  const C2<T>* __restrict__ src = Gp + bc * Kp + (long)row * npp;
+  for (int i = threadIdx.x; i < 4 * npp; i += kBlock) {
+    const int q = i / npp, c = i - q * npp;
+    pq[i] = cmul_conj_a(phase[(long)q * Kp + (long)row * npp + c], src[c]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * npc; i += kBlock) {
+    const int q = i / npc, c = i - q * npc;
+    const C2<T>* __restrict__ pr = pq + q * npp;
+    C2<T> v{0, 0};
+    for (int e = 0; e < pmax; ++e) {
+      const T w = tph_w[c * pmax + e];
+      const C2<T> z = pr[tph_col[c * pmax + e]];
+      v.x += w * z.x;
+      v.y += w * z.y;
+    }
+    H[((bc * 4 + q) * ntp + row) * npc + c] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dis_theta(int nxc, int nyc, int ntc, int npc, int nxp, int ntp,
+                                                      int tmax, int R, const C2<T>* __restrict__ H,
+                                                      const int* __restrict__ tth_row, const T* __restrict__ tth_w,
+                                                      const int* __restrict__ tth_flip, C2<T>* __restrict__ Gc,
+                                                      int nyp) {
+  const int nbc = nxc * nyc, nbp = nxp * nyp;
+  const long Kc = (long)ntc * npc;
+  const long total = (long)R * nbc * 2 * Kc;
+  const int half = npc / 2;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long)gridDim.x * kBlock) {
+    const int s = (int)(i % Kc);
+    long t = i / Kc;
+    const int comp = (int)(t % 2);
+    t /= 2;
+    const int cb = (int)(t % nbc), r = (int)(t / nbc);
+    const int row = s / npc, col = s - row * npc;
+    const int ci = cb % nxc, cj = cb / nxc;
+    const int pb = (cj >> 1) * nxp + (ci >> 1), q = (cj & 1) * 2 + (ci & 1);
+    const C2<T>* __restrict__ hq = H + ((((long)r * nbp + pb) * 2 + comp) * 4 + q) * ntp * npc;
+    const int colf = col + half < npc ? col + half : col + half - npc;
+    C2<T> v{0, 0};
+    for (int e = 0; e < tmax; ++e) {
+      const int pr = tth_row[row * tmax + e];
+      const T w = tth_w[row * tmax + e];
+      const C2<T> z = hq[(long)pr * npc + (tth_flip[row * tmax + e] ? colf : col)];
+      v.x += w * z.x;
+      v.y += w * z.y;
+    }
+    const C2<T> o = Gc[i];
+    Gc[i] = {o.x + v.x, o.y + v.y};
+  }
+}
+
 // -------------------------------------------------------------- translate --
 // G[r][p][c][s] = sum over the interaction list of TL[offset][s] S[r][q][c][s].
 // The list of box p (at most 27 (source box, offset) pairs, built on the
@@ -1298,7 +1370,7 @@ class EngineT final : public Engine {
     size_t ldsd = dis_plan(tsd, prng, pmr);
     if (dis_rows == 0)
       while (tsd > 1 && ldsd > kLdsBudget) ldsd = dis_plan(--tsd, prng, pmr);
-    if (ldsd > kLdsBudget) {  // largest boxes: read the parent rows through L2 instead
+    if (ldsd > kLdsBudget || force_two_pass_) {  // largest boxes: two-pass path
       stage_par = 0;
       ldsd = dis_plan(tsd, prng, pmr);
     }
@@ -1329,7 +1401,7 @@ class EngineT final : public Engine {
         return rc;
       }
     }
-    return 0;
+    return R_alloc_ > 0 ? size_dis_tmp(R_alloc_, err) : 0;
   }
 
   void get_tuning(std::vector<int>& agg_rows, std::vector<int>& dis_rows) const override {
@@ -1363,7 +1435,18 @@ class EngineT final : public Engine {
     j.acc = 0;
     j.tiles_m = (nf + 16 * kRT - 1) / (16 * kRT);
     j.tiles = j.tiles_m * (ngcols_ / 16);
+    j.xcd = 1;  // consecutive tiles share a block matrix: keep them in one L2
     return j;
+  }
+
+  // two-pass disaggregation intermediate (largest boxes) for R RHS
+  int size_dis_tmp(int R, std::string& err) {
+    size_t tmp_max = 0;
+    for (int l = 0; l + 1 < ntl_; ++l)
+      if (!it_[l + 1].dis_stage)
+        tmp_max = std::max(tmp_max, (size_t)R * lv_[l + 1].nx * lv_[l + 1].ny * 2 * 4 * lv_[l + 1].nt * lv_[l].np);
+    if (tmp_max * sizeof(CT) > dis_tmp_.bytes) HIP_TRY(dis_tmp_.alloc(tmp_max * sizeof(CT)));
+    return 0;
   }
 
   int ensure(int R, std::string& err) {
@@ -1377,6 +1460,7 @@ class EngineT final : public Engine {
       HIP_TRY(hipMemset(L.G.p, 0, bytes));
     }
     if (mfma_ && !near_uniform_) HIP_TRY(near_part_.alloc((size_t)R * 9 * P_ * 2 * n_ * sizeof(float)));
+    if (int rc = size_dis_tmp(R, err)) return rc;
     HIP_TRY(hipDeviceSynchronize());
     R_alloc_ = R;
     return 0;
@@ -1596,6 +1680,22 @@ class EngineT final : public Engine {
                           cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
                           2.0 * R * (double)L.nx * L.ny * 2 *
                               (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K));
+          if (!I.dis_stage) {  // largest boxes: phi pass into dis_tmp_, then theta pass
+            const int nbp = Pp.nx * Pp.ny;
+            const long nrows = (long)R * nbp * 2 * Pp.nt;
+            launch(pr, k_dis_phi<T>, dim3((unsigned)nrows), blk, (uint32_t)(4 * Pp.np * sizeof(CT)), st,
+                   nbp, Pp.nt, Pp.np, L.np, I.pmax, R, (const CT*)Pp.G.template as<CT>(),
+                   (const int*)I.tph_col.template as<int>(), (const T*)I.tph_w.template as<T>(),
+                   (const CT*)I.phase.template as<CT>(), dis_tmp_.template as<CT>());
+            const long nth = (long)R * L.nx * L.ny * 2 * L.K;
+            auto pt = begin("disaggregate_l" + std::to_string(l) + "_theta", 0.0, 0.0);
+            launch(pt, k_dis_theta<T>, dim3((unsigned)std::min<long>((nth + kBlock - 1) / kBlock, 65535)), blk,
+                               0u, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.nt, I.tmax, R,
+                               (const CT*)dis_tmp_.template as<CT>(), (const int*)I.tth_row.template as<int>(),
+                               (const T*)I.tth_w.template as<T>(), (const int*)I.tth_flip.template as<int>(),
+                               L.G.template as<CT>(), Pp.ny);
+            continue;
+          }
           launch(pr, k_disaggregate<T>, g2, blk, sh, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.ny, Pp.nt, Pp.np,
                              I.ts_dis, I.tmax, I.pmax, I.prows_max, Pp.G.template as<CT>(), L.G.template as<CT>(),
                              I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
@@ -1830,9 +1930,12 @@ class EngineT final : public Engine {
   DevMem Rm_, Qm_, rm_off_, qm_off_;
   DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;
   bool mfma_ = false, near_uniform_ = false;
+  // test switch: every disaggregation takes the two-pass path
+  bool force_two_pass_ = std::getenv("MLFMA_DIS_TWO_PASS") != nullptr;
   DevMem A_proj_, A_recv_, A_near_, iota_;
   DevMem gcol_part_, gcol_box_, a_off_proj_, a_off_recv_;  // class-grouped GEMM columns
   DevMem ng_bcol_, ng_ccol_, ng_aoff_, ng_has_, near_part_;  // class-pair near GEMM
+  DevMem dis_tmp_;                                            // two-pass disaggregation
   int ngcols_ = 0;
   int ncols_pad_ = 0;
   std::vector<V3> centers_;

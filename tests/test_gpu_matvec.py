@@ -141,6 +141,30 @@ def test_c2_subarrays_vs_golden(name, prec):
     assert err_near < (1e-5 if prec == mlfma.C64 else 1e-12)
 
 
+def test_two_pass_disaggregation_matches_strip_path():
+    """The two-pass disaggregation (used where a strip of parent rows does
+    not fit in LDS) forced on every level of the 12 x 12 case: the same
+    product as the LDS strip kernel, and the oracle's to the usual bound."""
+    path = os.path.join(GOLDEN, "c2_12x12.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path)
+    wl = w.workload("c2", 12, 12)
+    x = w.random_complex((1, wl.n_particles, 60), int(g["seed"]))
+    ctx = make_ctx(wl, g["M"], mlfma.C64)
+    y_strip = ctx.matvec(to_dev(x, ctx)).cpu().numpy()[0]
+    os.environ["MLFMA_DIS_TWO_PASS"] = "1"
+    try:
+        ctx2 = make_ctx(wl, g["M"], mlfma.C64)
+        y_two = ctx2.matvec(to_dev(x, ctx2)).cpu().numpy()[0]
+    finally:
+        del os.environ["MLFMA_DIS_TWO_PASS"]
+    d = rel_err(y_two, y_strip)
+    err = rel_err(y_two[g["rows"]], g["y"])
+    note(f"two-pass vs strip {d:.2e}; vs oracle {err:.3e}")
+    assert d < 1e-6 and err < TOL
+
+
 @pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C128])
 def test_c4_lens_vs_golden(prec):
     """8 x 8 metalens with six diameter classes: class-grouped projection and
