@@ -273,7 +273,8 @@ def main():
         t0 = time.perf_counter()
         rep = autotune.autotune(ctx, R=R, reps=3)
         tuning = {"seconds": time.perf_counter() - t0, "agg_rows": rep["tuned"][0], "dis_rows": rep["tuned"][1],
-                  "default_agg_rows": rep["default"][0], "default_dis_rows": rep["default"][1]}
+                  "default_agg_rows": rep["default"][0], "default_dis_rows": rep["default"][1],
+                  "gemm_row_tiles": rep["gemm_rows"], "default_gemm_row_tiles": rep["default_gemm_rows"]}
     P, n = wl.n_particles, 2 * (wl.n_perp + wl.n_par)
     x = torch.as_tensor(w.random_complex((R, P, n), 1)).to("cuda", torch.complex64).contiguous()
     y = torch.empty_like(x)

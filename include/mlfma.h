@@ -211,7 +211,8 @@ int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R,
                       int32_t max_iter, int32_t restart, int32_t flags, mlfma_solve_stats* stats,
                       void* stream);
 
-/* Tile shapes of the interpolation kernels: agg_rows[l] parent theta rows
+/* Tile shapes of the interpolation kernels and the matrix-core GEMMs
+ * (FP32 contexts): agg_rows[l] parent theta rows
  * per block of the aggregation into level l (l >= 1), dis_rows[l] child
  * theta rows per block of the disaggregation into level l (l < n_levels - 1);
  * 0 selects the built-in planner.  set re-plans the strips (the product's
@@ -223,6 +224,8 @@ typedef struct {
   int32_t n_levels;
   int32_t agg_rows[MLFMA_MAX_LEVELS];
   int32_t dis_rows[MLFMA_MAX_LEVELS];
+  int32_t gemm_rows_near;     /* 16-row MFMA tiles per block of the near +   */
+  int32_t gemm_rows_receive;  /* projection and receive GEMMs: 1, 2, 4 (0: 4) */
 } mlfma_tuning;
 int mlfma_set_tuning(mlfma_ctx* ctx, const mlfma_tuning* t);
 int mlfma_get_tuning(mlfma_ctx* ctx, mlfma_tuning* t);

@@ -1,11 +1,13 @@
-"""Autotuner of the interpolation kernels' tile shapes.
+"""Autotuner of the product's tile shapes.
 
-For every level it times the aggregation and the disaggregation with each
-candidate strip height (theta rows per block), using the library's
-dispatch-timed profiling of real products, and keeps the fastest.  A strip
-height changes only how the kernels block the work, not any output value
-(each output is computed by the same arithmetic in the same order), so the
-tuned product is bitwise identical to the default one.
+It times, with the library's dispatch-timed profiling of real products:
+the row tiles per block of the two matrix-core GEMM launches (near field +
+projection, receive: 1, 2 or 4 tiles of 16 rows), then for every level the
+aggregation and the disaggregation with each candidate strip height (theta
+rows per block), and keeps the fastest of each.  A tile shape changes only
+how the kernels block the work, not any output value (each output is
+computed by the same arithmetic in the same order), so the tuned product is
+bitwise identical to the default one.
 """
 from __future__ import annotations
 
@@ -31,7 +33,8 @@ def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDA
     import torch
     L = ctx.info()["n_levels"]
     if L < 2:
-        return {"default": ctx.get_tuning(), "tuned": ctx.get_tuning(), "stage_us": {}}
+        return {"default": ctx.get_tuning(), "tuned": ctx.get_tuning(), "gemm_rows": ctx.get_gemm_tiles(),
+                "default_gemm_rows": ctx.get_gemm_tiles(), "stage_us": {}}
     n = 2 * ctx.n_modes
     rng = np.random.default_rng(0)
     x = torch.as_tensor(rng.standard_normal((R, ctx.n_particles, n)) + 1j * rng.standard_normal(
@@ -40,8 +43,26 @@ def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDA
     default = ctx.get_tuning()
     agg, dis = [list(v) for v in default]
     ctx.matvec(x, out=y)
-    base = _stage_times(ctx, x, y, reps)
     report = {}
+    gemm = list(ctx.get_gemm_tiles())
+    default_gemm = tuple(gemm)
+    if ctx.params.precision == mlfma.C64:
+        for gi, names in ((0, ("near+project", "near", "project")), (1, ("receive",))):
+            times = {}
+            for rt in (1, 2, 4):
+                trial = list(gemm)
+                trial[gi] = rt
+                ctx.set_tuning(agg, dis, trial)
+                st = _stage_times(ctx, x, y, reps)
+                times[rt] = sum(st.get(nm, 0.0) for nm in names)
+            best = min(times, key=times.get)
+            gemm[gi] = best
+            ctx.set_tuning(agg, dis, gemm)
+            report["gemm_" + names[0]] = {"rows": best, "tried_us": {k: round(1e3 * v, 2) for k, v in times.items()}}
+            if log:
+                log(f"gemm {names[0]}: {1e3 * times[default_gemm[gi]]:.1f} us -> {1e3 * times[best]:.1f} us "
+                    f"({best} row tiles)")
+    base = _stage_times(ctx, x, y, reps)
     for kind, idx_range in (("aggregate", range(1, L)), ("disaggregate", range(0, L - 1))):
         for l in idx_range:
             name = f"{kind}_l{l}"
@@ -72,4 +93,5 @@ def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDA
                 log(f"{name}: {report[name]['default_us']:.1f} us -> {report[name]['tuned_us']:.1f} us "
                     f"({best_h} rows)")
     ctx.set_tuning(agg, dis)
-    return {"default": default, "tuned": (agg, dis), "stage_us": report}
+    return {"default": default, "tuned": (agg, dis), "gemm_rows": tuple(gemm), "default_gemm_rows": default_gemm,
+            "stage_us": report}

@@ -478,7 +478,8 @@ int mlfma_set_tuning(mlfma_ctx* ctx, const mlfma_tuning* t) {
       d[l] = t->dis_rows[l];
     }
     std::string err;
-    int rc = ctx->eng->set_tuning(a, d, err);
+    int rc = ctx->eng->set_gemm_tiles(t->gemm_rows_near, t->gemm_rows_receive, err);
+    if (!rc) rc = ctx->eng->set_tuning(a, d, err);
     return rc ? fail(ctx, rc == -1 ? MLFMA_EINVAL : rc, err) : MLFMA_OK;
   });
 }
@@ -495,6 +496,10 @@ int mlfma_get_tuning(mlfma_ctx* ctx, mlfma_tuning* t) {
       t->agg_rows[l] = a[l];
       t->dis_rows[l] = d[l];
     }
+    int rn = 0, rr = 0;
+    ctx->eng->get_gemm_tiles(rn, rr);
+    t->gemm_rows_near = rn;
+    t->gemm_rows_receive = rr;
     return MLFMA_OK;
   });
 }

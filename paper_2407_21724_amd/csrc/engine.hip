@@ -1388,6 +1388,22 @@ class EngineT final : public Engine {
 
   // All levels or none: on a tile that does not fit, the previous plan is
   // restored.
+  int set_gemm_tiles(int rt_np, int rt_recv, std::string& err) override {
+    auto ok = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
+    if (!ok(rt_np) || !ok(rt_recv)) {
+      err = "GEMM row tiles must be 1, 2 or 4 (0: default 4)";
+      return -1;
+    }
+    rt_np_ = rt_np ? rt_np : 4;
+    rt_recv_ = rt_recv ? rt_recv : 4;
+    clear_graphs();
+    return 0;
+  }
+  void get_gemm_tiles(int& rt_np, int& rt_recv) const override {
+    rt_np = rt_np_;
+    rt_recv = rt_recv_;
+  }
+
   int set_tuning(const std::vector<int>& agg_rows, const std::vector<int>& dis_rows, std::string& err) override {
     std::vector<int> pa, pd;
     get_tuning(pa, pd);
@@ -1414,7 +1430,7 @@ class EngineT final : public Engine {
   }
 
   // near-field products of the class-pair GEMM: partial[r][o * P + p][:]
-  GemmJob near_group_job(const CT* x) const {
+  GemmJob near_group_job(const CT* x, int rt) const {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_near_.template as<float>();
@@ -1433,7 +1449,7 @@ class EngineT final : public Engine {
     j.ldb = nf;
     j.ldc = nf;
     j.acc = 0;
-    j.tiles_m = (nf + 16 * kRT - 1) / (16 * kRT);
+    j.tiles_m = (nf + 16 * rt - 1) / (16 * rt);
     j.tiles = j.tiles_m * (ngcols_ / 16);
     j.xcd = 1;  // consecutive tiles share a block matrix: keep them in one L2
     return j;
@@ -1512,7 +1528,7 @@ class EngineT final : public Engine {
   }
 
   // GEMM job descriptors of the matrix-core stages (see k_gemm_stream).
-  GemmJob near_job(const CT* x, CT* y, int R) const {
+  GemmJob near_job(const CT* x, CT* y, int R, int rt) const {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_near_.template as<float>();
@@ -1528,13 +1544,13 @@ class EngineT final : public Engine {
     j.lda = 9 * nf;
     j.ldb = j.ldc = nf;
     j.acc = 0;
-    j.tiles_m = (nf + 16 * kRT - 1) / (16 * kRT);
+    j.tiles_m = (nf + 16 * rt - 1) / (16 * rt);
     j.tiles = j.tiles_m * ((P_ + 15) / 16);
     (void)R;
     return j;
   }
   // U0 = radiation matrix of each particle's class times x (eq. kspace_Rap)
-  GemmJob project_job(const CT* x) const {
+  GemmJob project_job(const CT* x, int rt) const {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_proj_.template as<float>();
@@ -1553,12 +1569,12 @@ class EngineT final : public Engine {
     j.ldb = nf;
     j.ldc = 2 * M2_;
     j.acc = 0;
-    j.tiles_m = (j.M + 16 * kRT - 1) / (16 * kRT);
+    j.tiles_m = (j.M + 16 * rt - 1) / (16 * rt);
     j.tiles = j.tiles_m * (ncols_pad_ / 16);
     return j;
   }
   // y += receiving matrix of each particle's class times G0 (eqs. Tmn_fmm, Kmn_fmm)
-  GemmJob receive_job(CT* y) const {
+  GemmJob receive_job(CT* y, int rt) const {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_recv_.template as<float>();
@@ -1577,15 +1593,22 @@ class EngineT final : public Engine {
     j.ldb = 2 * M2_;
     j.ldc = nf;
     j.acc = 1;
-    j.tiles_m = (j.M + 16 * kRT - 1) / (16 * kRT);
+    j.tiles_m = (j.M + 16 * rt - 1) / (16 * rt);
     j.tiles = j.tiles_m * (ncols_pad_ / 16);
     j.xcd = 1;  // the row tiles of one column tile read the same G0 columns
     return j;
   }
+  // rt: 16-row MFMA tiles per block (1, 2 or 4; the jobs' tiles_m must use it)
   template <int Tag>
-  void launch_gemm(Pending& pr, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
+  void launch_gemm(Pending& pr, int rt, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
     const int nt = j0.tiles + j1.tiles;
-    launch(pr, k_gemm_stream<kRT, 1, Tag>, dim3(j0.xcd ? xcd_grid(nt) : nt, 1, R), dim3(kBlock), 0, st, j0, j1);
+    const dim3 grid(j0.xcd ? xcd_grid(nt) : nt, 1, R);
+    if (rt == 1)
+      launch(pr, k_gemm_stream<1, 1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+    else if (rt == 2)
+      launch(pr, k_gemm_stream<2, 1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+    else
+      launch(pr, k_gemm_stream<4, 1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
   }
 
   // One product y = Z x: near-field apply and leaf projection (one launch on
@@ -1615,12 +1638,14 @@ class EngineT final : public Engine {
     };
     if (near && far && (near_mfma || near_grouped)) {
       auto pr = begin("near+project", near_bytes + proj_bytes, near_flops + proj_flops);
-      launch_gemm<0>(pr, near_grouped ? near_group_job(x) : near_job(x, y, R), project_job(x), R, st);
+      launch_gemm<0>(pr, rt_np_, near_grouped ? near_group_job(x, rt_np_) : near_job(x, y, R, rt_np_),
+                     project_job(x, rt_np_), R, st);
     } else {
       if (near) {
         auto pr = begin("near", near_bytes, near_flops);
         if (near_mfma || near_grouped) {
-          launch_gemm<1>(pr, near_grouped ? near_group_job(x) : near_job(x, y, R), none, R, st);
+          launch_gemm<1>(pr, rt_np_, near_grouped ? near_group_job(x, rt_np_) : near_job(x, y, R, rt_np_), none, R,
+                         st);
           if (near_grouped) near_sum();
         } else
           launch_near(pr, x, y, R, near_mats_.template as<CT>(), near_nbr_.template as<int>(),
@@ -1632,7 +1657,7 @@ class EngineT final : public Engine {
       if (far) {
         auto pr = begin("project", proj_bytes, proj_flops);
         if (mfma_) {
-          launch_gemm<2>(pr, project_job(x), none, R, st);
+          launch_gemm<2>(pr, rt_np_, project_job(x, rt_np_), none, R, st);
         } else {
           dim3 grid(ntiles_, (M2_ + kProjBlock - 1) / kProjBlock, R);
           size_t sh = (size_t)kTP * n_ * sizeof(CT);
@@ -1708,7 +1733,7 @@ class EngineT final : public Engine {
         auto pr = begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
                         8.0 * R * P_ * (double)n_ * M2_);
         if (mfma_) {
-          launch_gemm<3>(pr, receive_job(y), none, R, st);
+          launch_gemm<3>(pr, rt_recv_, receive_job(y, rt_recv_), none, R, st);
         } else {
           dim3 grid(ntiles_, R);
           launch(pr, k_receive<T, kTP>, grid, blk, 0, st, n_, P_, M2_, nb0, y, L0->G.template as<CT>(),
@@ -1806,7 +1831,7 @@ class EngineT final : public Engine {
  private:
   static constexpr int kTP = sizeof(T) == 4 ? 16 : 8;
   static constexpr int kTPN = 16;
-  static constexpr int kRT = 4;  // MFMA GEMM row tiles (of 16) per block
+  int rt_np_ = 4, rt_recv_ = 4;  // MFMA GEMM row tiles (of 16) per block: near+projection, receive
   static constexpr size_t kLdsBudget = 48 * 1024;  // preferred tile size (occupancy)
   static constexpr size_t kLdsMax = 64 * 1024;     // hard limit per block
   static constexpr size_t kMinBlocks = 1024;

@@ -70,6 +70,9 @@ class Engine {
   // indexed by the parent level, dis_rows by the child level
   virtual int set_tuning(const std::vector<int>& agg_rows, const std::vector<int>& dis_rows, std::string& err) = 0;
   virtual void get_tuning(std::vector<int>& agg_rows, std::vector<int>& dis_rows) const = 0;
+  // row tiles (of 16) per block of the matrix-core GEMMs: 1, 2 or 4
+  virtual int set_gemm_tiles(int rt_near_project, int rt_receive, std::string& err) = 0;
+  virtual void get_gemm_tiles(int& rt_near_project, int& rt_receive) const = 0;
 };
 
 Engine* make_engine(int precision);

@@ -52,7 +52,8 @@ class StageTime(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("n_levels", C.c_int32), ("agg_rows", C.c_int32 * 16), ("dis_rows", C.c_int32 * 16)]
+    _fields_ = [("n_levels", C.c_int32), ("agg_rows", C.c_int32 * 16), ("dis_rows", C.c_int32 * 16),
+                ("gemm_rows_near", C.c_int32), ("gemm_rows_receive", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -216,12 +217,19 @@ class Context:
         self._check(lib().mlfma_get_tuning(self._h, C.byref(t)), "get_tuning")
         return list(t.agg_rows[:t.n_levels]), list(t.dis_rows[:t.n_levels])
 
-    def set_tuning(self, agg_rows, dis_rows):
+    def get_gemm_tiles(self):
+        """(near+projection, receive) 16-row MFMA tiles per block."""
+        t = Tuning()
+        self._check(lib().mlfma_get_tuning(self._h, C.byref(t)), "get_tuning")
+        return int(t.gemm_rows_near), int(t.gemm_rows_receive)
+
+    def set_tuning(self, agg_rows, dis_rows, gemm_rows=None):
         t = Tuning()
         t.n_levels = len(agg_rows)
         for i, (a, d) in enumerate(zip(agg_rows, dis_rows)):
             t.agg_rows[i] = int(a)
             t.dis_rows[i] = int(d)
+        t.gemm_rows_near, t.gemm_rows_receive = gemm_rows if gemm_rows is not None else self.get_gemm_tiles()
         self._check(lib().mlfma_set_tuning(self._h, C.byref(t)), "set_tuning")
 
     def share_setup(self, src: "Context"):

@@ -30,6 +30,8 @@ def test_tuned_product_is_bitwise_identical():
     agg, dis = ctx.get_tuning()
     with pytest.raises(mlfma.MlfmaError):
         ctx.set_tuning([a + 10000 for a in agg], dis)      # taller than any level
-    ctx.set_tuning([0] * len(agg), [0] * len(dis))
-    assert ctx.get_tuning() == rep["default"]
+    with pytest.raises(mlfma.MlfmaError):
+        ctx.set_tuning(agg, dis, (3, 4))                    # row tiles must be 1, 2 or 4
+    ctx.set_tuning([0] * len(agg), [0] * len(dis), (0, 0))
+    assert ctx.get_tuning() == rep["default"] and ctx.get_gemm_tiles() == (4, 4)
     assert np.array_equal(ctx.matvec(x).cpu().numpy(), y0)
