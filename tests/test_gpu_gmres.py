@@ -89,3 +89,35 @@ def test_gmres_initial_guess_and_zero_rhs(c1_solution):
     x, stats, rc = ctx.gmres_solve(b, rtol=1e-14, max_iter=3, restart=3)
     assert rc == mlfma.NOT_CONVERGED and not stats[0]["converged"]
     assert stats[0]["true_rel_res"] < 1.0
+
+
+def test_lens_subarray_fields_vs_oracle():
+    """A 10 x 10 lens of the full-scale recipe (four diameter classes): FP32
+    product GMRES against the oracle's dense solve, in the unknowns and in
+    the scattered near field (plane z = 1 over the array) and far field."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_10x10_fields.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    g = np.load(path)
+    wl = w.workload("c5", 10, 10)
+    classes = [int(c) for c in g["classes"]]
+    M = {c: g["M"][i] for i, c in enumerate(classes)}
+    ctx = make_ctx(wl, M, mlfma.C64)
+    b = ctx.plane_wave_rhs(g["khat"][None], g["pol"][None])
+    x, stats, rc = ctx.gmres_solve(b, rtol=1e-5, max_iter=2000, restart=300)   # FP32 product: floor ~1e-6
+    note(f"lens 10x10 gmres: {stats[0]}")
+    assert rc == mlfma.OK
+    xs = x.cpu().numpy()[0]
+    # oracle's field evaluation on the GPU solution (same static-mode basis)
+    pcs = []
+    for c in classes:
+        v, t, e = wl.meshes[c]
+        pcs.append(ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r, M=M[c]))
+    compact = np.array([classes.index(c) for c in wl.class_id], np.int32)
+    prob = DenseProblem(pcs, wl.centers, compact)
+    near = near_field(prob, xs, g["pts"])
+    far = far_amplitude(prob, xs, g["rhat"])
+    ex, en, ef = rel_err(xs, g["J"]), rel_err(near, g["near"]), rel_err(far, g["far"])
+    note(f"  unknowns {ex:.3e}, near field {en:.3e}, far field {ef:.3e}")
+    assert en < 1e-2 and ef < 1e-2
