@@ -32,18 +32,25 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_c2_40x40.json")
 
 # product stages (as named by mlfma_profile_read) -> kernel symbol prefix and
 # the roofline that bounds it
+# (the GEMM stages are named by kernel_of from the row tiles in use)
 KERNELS = [
-    ("near+project", "k_gemm_stream<4, 1, 0>", "mfma"),
-    ("near", "k_gemm_stream<4, 1, 1>", "mfma"),
-    ("project", "k_gemm_stream<4, 1, 2>", "mfma"),
-    ("receive", "k_gemm_stream<4, 1, 3>", "mfma"),
     ("aggregate_l", "k_aggregate", "hbm"),
     ("translate_l", "k_translate", "hbm"),
     ("disaggregate_l", "k_disaggregate", "hbm"),
+    ("disaggregate_phi_l", "k_dis_phi", "hbm"),
+    ("disaggregate_theta_l", "k_dis_theta", "hbm"),
+    ("near_sum", "k_near_sum", "hbm"),
 ]
 
 
-def kernel_of(stage):
+def kernel_of(stage, gemm_rows=(4, 4)):
+    """Kernel symbol and roofline bound of a product stage; the GEMM symbols
+    carry the row tiles per block the context runs with."""
+    rn, rr = gemm_rows
+    gemm = {"near+project": f"k_gemm_stream<{rn}, 1, 0>", "near": f"k_gemm_stream<{rn}, 1, 1>",
+            "project": f"k_gemm_stream<{rn}, 1, 2>", "receive": f"k_gemm_stream<{rr}, 1, 3>"}
+    if stage in gemm:
+        return gemm[stage], "mfma"
     for prefix, sym, bound in KERNELS:
         if stage == prefix or (prefix.endswith("_l") and stage.startswith(prefix)):
             return sym, bound
@@ -56,12 +63,12 @@ def source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def kernel_table(stages):
+def kernel_table(stages, gemm_rows=(4, 4)):
     """Group per-stage event timings by kernel symbol (the unit rocprofv3
     reports): total time, launches, algorithmic bytes and flops per launch."""
     groups = {}
     for s in stages:
-        sym, bound = kernel_of(s["name"])
+        sym, bound = kernel_of(s["name"], gemm_rows)
         g = groups.setdefault(sym, {"kernel": sym, "bound": bound, "total_ms": 0.0, "launches": 0,
                                     "bytes": 0.0, "flops": 0.0, "stages": []})
         g["total_ms"] += s["total_ms"]
@@ -223,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default interpolation tile shapes")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-RHS product figure")
     ap.add_argument("--no-lens", action="store_true",
                     help="skip the 80 x 80 metalens GMRES comparison (zero start vs learned start)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -300,9 +308,28 @@ def main():
         stages = ctx.profile_read()
         ctx.profile(False)
     value = wl.n_unknowns * R / (ms * 1e-3)
+    batched = None
+    if R == 1 and not args.no_batched:
+        # the same array with the 64 incidences of the batched configuration per launch
+        xb = torch.as_tensor(w.random_complex((64, P, n), 2)).to("cuda", torch.complex64).contiguous()
+        yb = torch.empty_like(xb)
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                ctx.matvec(xb, out=yb)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                ctx.matvec(xb, out=yb)
+            e1.record()
+            torch.cuda.synchronize()
+        msb = e0.elapsed_time(e1) / 10
+        batched = {"rhs": 64, "ms_per_product": msb, "unknowns_rhs_per_s": wl.n_unknowns * 64 / (msb * 1e-3)}
+        del xb, yb
 
     # roofline of the dominant kernel (largest share of the product's time)
-    groups = kernel_table(stages)
+    groups = kernel_table(stages, ctx.get_gemm_tiles())
     dom = max(groups.values(), key=lambda g: g["total_ms"])
     avg_s = dom["total_ms"] / dom["launches"] * 1e-3
     if dom["bound"] == "hbm":
@@ -333,6 +360,7 @@ def main():
         "kernels_us": {g["kernel"]: round(1e3 * g["total_ms"] / g["launches"], 2) for g in groups.values()},
         "setup_s": setup_s,
         "autotune": tuning,
+        "batched_64_rhs": batched,
     }
     if not args.no_gmres:
         inc = w.normal_incidence_x()

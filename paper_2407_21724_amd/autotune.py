@@ -27,6 +27,16 @@ def _stage_times(ctx, x, y, reps):
     return {s["name"]: s["total_ms"] / s["launches"] for s in st}
 
 
+def _level_time(st, kind, l):
+    """Time of one level's aggregation or disaggregation (the latter may run
+    as the strip kernel or as the two-pass phi + theta kernels)."""
+    if kind == "aggregate":
+        return st.get(f"aggregate_l{l}", float("inf"))
+    names = (f"disaggregate_l{l}", f"disaggregate_phi_l{l}", f"disaggregate_theta_l{l}")
+    found = [st[n] for n in names if n in st]
+    return sum(found) if found else float("inf")
+
+
 def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDATES, log=None):
     """Tune ctx in place for products with R right-hand sides.  Returns
     {"default": (agg, dis), "tuned": (agg, dis), "stage_us": {...}}."""
@@ -67,7 +77,7 @@ def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDA
         for l in idx_range:
             name = f"{kind}_l{l}"
             cur = agg if kind == "aggregate" else dis
-            best_h, best_t = cur[l], base.get(name, float("inf"))
+            best_h, best_t = cur[l], _level_time(base, kind, l)
             tried = {cur[l]: best_t}
             for h in candidates:
                 if h in tried:
@@ -81,13 +91,13 @@ def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDA
                         ctx.set_tuning(agg, trial)
                 except mlfma.MlfmaError:
                     continue           # tile does not fit (or taller than the level)
-                t = _stage_times(ctx, x, y, reps).get(name, float("inf"))
+                t = _level_time(_stage_times(ctx, x, y, reps), kind, l)
                 tried[h] = t
                 if t < best_t:
                     best_h, best_t = h, t
             cur[l] = best_h
             ctx.set_tuning(agg, dis)
-            report[name] = {"default_us": 1e3 * base.get(name, float("nan")), "tuned_us": 1e3 * best_t,
+            report[name] = {"default_us": 1e3 * _level_time(base, kind, l), "tuned_us": 1e3 * best_t,
                             "rows": best_h, "tried_us": {int(k): round(1e3 * v, 2) for k, v in tried.items()}}
             if log:
                 log(f"{name}: {report[name]['default_us']:.1f} us -> {report[name]['tuned_us']:.1f} us "

@@ -1701,7 +1701,7 @@ class EngineT final : public Engine {
           const int nstrips = (L.nt + I.ts_dis - 1) / I.ts_dis;
           dim3 g2(xcd_grid(L.nx * L.ny * 2 * nstrips * R));
           size_t sh = I.lds_dis;
-          auto pr = begin("disaggregate_l" + std::to_string(l),
+          auto pr = begin((I.dis_stage ? "disaggregate_l" : "disaggregate_phi_l") + std::to_string(l),
                           cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
                           2.0 * R * (double)L.nx * L.ny * 2 *
                               (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K));
@@ -1713,7 +1713,7 @@ class EngineT final : public Engine {
                    (const int*)I.tph_col.template as<int>(), (const T*)I.tph_w.template as<T>(),
                    (const CT*)I.phase.template as<CT>(), dis_tmp_.template as<CT>());
             const long nth = (long)R * L.nx * L.ny * 2 * L.K;
-            auto pt = begin("disaggregate_l" + std::to_string(l) + "_theta", 0.0, 0.0);
+            auto pt = begin("disaggregate_theta_l" + std::to_string(l), 0.0, 0.0);
             launch(pt, k_dis_theta<T>, dim3((unsigned)std::min<long>((nth + kBlock - 1) / kBlock, 65535)), blk,
                                0u, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.nt, I.tmax, R,
                                (const CT*)dis_tmp_.template as<CT>(), (const int*)I.tth_row.template as<int>(),
