@@ -234,7 +234,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default interpolation tile shapes")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the tuning file: default tile shapes")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner and write the tuning file that later runs apply")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-RHS product figure")
     ap.add_argument("--no-lens", action="store_true",
                     help="skip the 80 x 80 metalens GMRES comparison (zero start vs learned start)")
@@ -286,14 +288,19 @@ def main():
     setup_s = time.perf_counter() - t0 + modes_s
     info = ctx.info()
     R = args.rhs
-    tuning = None
-    if not args.no_autotune:
-        from paper_2407_21724_amd import autotune
+    from paper_2407_21724_amd import autotune
+    tfile = autotune.tuning_file(args.workload, R)
+    tuning = {"source": "default tile shapes"}
+    if args.autotune:
         t0 = time.perf_counter()
-        rep = autotune.autotune(ctx, R=R, reps=3)
-        tuning = {"seconds": time.perf_counter() - t0, "agg_rows": rep["tuned"][0], "dis_rows": rep["tuned"][1],
-                  "default_agg_rows": rep["default"][0], "default_dis_rows": rep["default"][1],
-                  "gemm_row_tiles": rep["gemm_rows"], "default_gemm_row_tiles": rep["default_gemm_rows"]}
+        rep = autotune.autotune(ctx, R=R, reps=5)
+        autotune.save(tfile, ctx, rep, {"workload": args.workload, "rhs": R})
+        tuning = {"source": "autotuned now (written to the tuning file)", "seconds": time.perf_counter() - t0}
+    elif not args.no_tuning and os.path.exists(tfile):
+        autotune.apply(tfile, ctx)
+        tuning = {"source": os.path.relpath(tfile, ROOT)}
+    agg, dis = ctx.get_tuning()
+    tuning.update({"agg_rows": agg, "dis_rows": dis, "gemm_row_tiles": list(ctx.get_gemm_tiles())})
     P, n = wl.n_particles, 2 * (wl.n_perp + wl.n_par)
     x = torch.as_tensor(w.random_complex((R, P, n), 1)).to("cuda", torch.complex64).contiguous()
     y = torch.empty_like(x)
@@ -374,7 +381,7 @@ def main():
         "stages_us": {s["name"]: round(1e3 * s["total_ms"] / s["launches"], 2) for s in stages},
         "kernels_us": {g["kernel"]: round(1e3 * g["total_ms"] / g["launches"], 2) for g in groups.values()},
         "setup_s": setup_s,
-        "autotune": tuning,
+        "tuning": tuning,
         "batched_64_rhs": batched,
     }
     if not args.no_gmres:

@@ -11,6 +11,9 @@ bitwise identical to the default one.
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 
 from . import mlfma
@@ -105,3 +108,28 @@ def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDA
     ctx.set_tuning(agg, dis)
     return {"default": default, "tuned": (agg, dis), "gemm_rows": tuple(gemm), "default_gemm_rows": default_gemm,
             "stage_us": report}
+
+
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+
+
+def tuning_file(workload: str, R: int) -> str:
+    return os.path.join(TUNING_DIR, f"{workload}_r{R}.json")
+
+
+def save(path, ctx, report, meta: dict):
+    """Write the context's current tile shapes (after autotune) to path."""
+    agg, dis = ctx.get_tuning()
+    rec = dict(meta, agg_rows=agg, dis_rows=dis, gemm_rows=list(ctx.get_gemm_tiles()),
+               stage_us=report.get("stage_us", {}))
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+
+
+def apply(path, ctx):
+    """Apply the tile shapes of a tuning file written by save()."""
+    with open(path) as f:
+        rec = json.load(f)
+    ctx.set_tuning(rec["agg_rows"], rec["dis_rows"], tuple(rec["gemm_rows"]))
+    return rec
