@@ -397,7 +397,15 @@ def main():
                         "true_rel_res": max(s_["true_rel_res"] for s_ in st),
                         "converged": all(s_["converged"] for s_ in st),
                         "restart": restart, "rhs": len(incs), "initial_guess": "zero",
-                        "reorth": st[0]["reorth"], "cycles": st[0]["cycles"]}
+                        "reorth": st[0]["reorth"], "cycles": st[0]["cycles"], "krylov_basis": "fp64"}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=args.max_iter, restart=restart, fp32_basis=True)
+        torch.cuda.synchronize()
+        out["gmres_fp32_basis"] = {"time_to_1e-4_s": time.perf_counter() - t0,
+                                   "iterations": max(s_["iterations"] for s_ in st),
+                                   "true_rel_res": max(s_["true_rel_res"] for s_ in st),
+                                   "converged": all(s_["converged"] for s_ in st), "restart": restart}
     if not args.no_gmres and not args.no_lens and headline:
         out["gmres_lens"] = lens_gmres(torch, w, mlfma)
     if cpu is not None:

@@ -192,14 +192,17 @@ int mlfma_precondition(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R
 
 #define MLFMA_SOLVE_USE_X0 1
 #define MLFMA_SOLVE_ALWAYS_REORTH 2
+#define MLFMA_SOLVE_FP32_BASIS 4
 
 /* Right-preconditioned restarted GMRES (Sec. V stage v; preconditioner
  * blockdiag(Z_s)) for R right-hand sides solved in lock-step.  Arnoldi is
  * classical Gram-Schmidt with a second pass where the first removed more
  * than half of |w|^2 (Daniel-Gragg-Kaufman-Stewart test), or always with
- * flags & MLFMA_SOLVE_ALWAYS_REORTH.  Arnoldi, Givens rotations and the
- * Krylov basis are FP64; the matrix-vector products run in the context
- * precision.
+ * flags & MLFMA_SOLVE_ALWAYS_REORTH.  Arnoldi and Givens rotations are
+ * FP64; the Krylov basis is stored in FP64, or in FP32 with flags &
+ * MLFMA_SOLVE_FP32_BASIS (half the memory and traffic of the Arnoldi
+ * sweeps, basis orthogonal to FP32 rounding); the matrix-vector products run
+ * in the context precision.
  *  b_dev, x_dev: device [R][P][2][N] in the context precision.  x_dev holds
  *  the initial guess if flags & MLFMA_SOLVE_USE_X0 (else zero is used) and
  *  the best iterate on return.  rtol: relative tolerance on the true

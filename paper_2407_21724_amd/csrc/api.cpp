@@ -614,7 +614,8 @@ int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R,
     std::vector<GmresResult> res;
     std::string err;
     int rc = ctx->eng->gmres(b_dev, x_dev, R, rtol, max_iter, restart, (flags & MLFMA_SOLVE_USE_X0) != 0,
-                              (flags & MLFMA_SOLVE_ALWAYS_REORTH) != 0, res, stream, err);
+                              (flags & MLFMA_SOLVE_ALWAYS_REORTH) != 0, (flags & MLFMA_SOLVE_FP32_BASIS) != 0, res,
+                              stream, err);
     if (rc) return fail(ctx, rc, err);
     bool all = true;
     for (int r = 0; r < R; ++r) {

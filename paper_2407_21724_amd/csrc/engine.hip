@@ -717,6 +717,11 @@ __global__ __launch_bounds__(kBlock) void k_to_z(const C2<T>* __restrict__ a, Z*
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
     b[i] = {(double)a[i].x, (double)a[i].y};
 }
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_convert(const C2<S>* __restrict__ a, C2<D>* __restrict__ b, size_t cnt) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
+    b[i] = {(D)a[i].x, (D)a[i].y};
+}
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_from_z(const Z* __restrict__ a, C2<T>* __restrict__ b, size_t cnt) {
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
@@ -733,12 +738,14 @@ constexpr int kDotChunk = 512;      // vector elements per block and sweep (8 pe
 constexpr int kDotMaxBlocks = 512;
 
 // Block partial sums of the inner products conj(V_i) . w (slots i < nv) and,
-// when want_norm, of |w|^2 (slot nv), in one sweep over the basis.  The four
+// when want_norm, of |w|^2 (slot nv), in one sweep over the basis (stored
+// in VB precision, products accumulated in FP64).  The four
 // waves of a block share one stretch of w and take the slots round-robin;
 // partial[((r * ldp) + slot) * gridDim.x + blockIdx.x].  RHS r is skipped
 // where gate[r] == 0.
+template <typename VB>
 __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t Nt, size_t vstride,
-                                                  const Z* __restrict__ V, const Z* __restrict__ w,
+                                                  const C2<VB>* __restrict__ V, const Z* __restrict__ w,
                                                   Z* __restrict__ partial, int ldp, const int* __restrict__ gate) {
   const int r = blockIdx.y;
   if (gate && !gate[r]) return;
@@ -746,14 +753,17 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Z* wr = w + (size_t)r * Nt;
   for (int s = wave; s < nv + want_norm; s += kBlock / 64) {
-    const Z* vr = s == nv ? wr : V + (size_t)s * vstride + (size_t)r * Nt;
+    const bool norm = s == nv;
+    const C2<VB>* vr = V + (size_t)(norm ? 0 : s) * vstride + (size_t)r * Nt;
     double ax = 0, ay = 0;
     for (size_t c0 = (size_t)blk * kDotChunk; c0 < Nt; c0 += (size_t)nblk * kDotChunk) {
 #pragma unroll
       for (int e = 0; e < kDotChunk / 64; ++e) {
         const size_t k = c0 + (size_t)e * 64 + lane;
         if (k < Nt) {
-          const Z a = vr[k], b = wr[k];
+          const Z b = wr[k];
+          Z a = b;
+          if (!norm) a = Z{(double)vr[k].x, (double)vr[k].y};
           ax += a.x * b.x + a.y * b.y;
           ay += a.x * b.y - a.y * b.x;
         }
@@ -798,7 +808,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int nblk, const Z* __restrict
 
 // w[r] -= sum_{i<nv} V_i[r] c[r][i]; block partial sums of |w[r]|^2 after the
 // update go to partial[r * gridDim.x + blockIdx.x] (imaginary part 0).
-__global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, size_t vstride, const Z* __restrict__ V,
+template <typename VB>
+__global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, size_t vstride, const C2<VB>* __restrict__ V,
                                                            const Z* __restrict__ c, int ldc, Z* __restrict__ w,
                                                            Z* __restrict__ partial, const int* __restrict__ gate) {
   const int r = blockIdx.y;
@@ -806,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, siz
   __shared__ double red[kBlock / 64];
   const Z* cr = c + (size_t)r * ldc;
   Z* wr = w + (size_t)r * Nt;
-  const Z* Vr = V + (size_t)r * Nt;
+  const C2<VB>* Vr = V + (size_t)r * Nt;
   double s2 = 0;
   for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
     Z acc = wr[k];
@@ -814,7 +825,10 @@ __global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, siz
     for (; i + 4 <= nv; i += 4) {
       Z v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = Vr[(size_t)(i + u) * vstride + k];
+      for (int u = 0; u < 4; ++u) {
+        const C2<VB> t = Vr[(size_t)(i + u) * vstride + k];
+        v[u] = Z{(double)t.x, (double)t.y};
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const Z q = cr[i + u];
@@ -823,7 +837,8 @@ __global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, siz
       }
     }
     for (; i < nv; ++i) {
-      const Z v = Vr[(size_t)i * vstride + k], q = cr[i];
+      const C2<VB> t = Vr[(size_t)i * vstride + k];
+      const Z v{(double)t.x, (double)t.y}, q = cr[i];
       acc.x -= v.x * q.x - v.y * q.y;
       acc.y -= v.x * q.y + v.y * q.x;
     }
@@ -871,14 +886,15 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_col(int nv, int ld, const Z*
   }
 }
 
-// out[r] = a[r] * s[r] with a real per-RHS factor
+// out[r] = a[r] * s[r] with a real per-RHS factor (rounded to the basis precision)
+template <typename VB>
 __global__ __launch_bounds__(kBlock) void k_scale_real(size_t Nt, const Z* __restrict__ a,
-                                                        const double* __restrict__ s, Z* __restrict__ out) {
+                                                        const double* __restrict__ s, C2<VB>* __restrict__ out) {
   const int r = blockIdx.y;
   const double c = s[r];
   for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
     const Z v = a[(size_t)r * Nt + k];
-    out[(size_t)r * Nt + k] = Z{v.x * c, v.y * c};
+    out[(size_t)r * Nt + k] = C2<VB>{(VB)(v.x * c), (VB)(v.y * c)};
   }
 }
 
@@ -895,13 +911,15 @@ __global__ __launch_bounds__(kBlock) void k_sub(size_t cnt, const Z* __restrict_
 }
 
 // out[r] = sum_i V[i][r] y[r][i] (+ out if accumulate)
-__global__ __launch_bounds__(kBlock) void k_combine(int nv, int ld_r, size_t Nt, size_t vstride, const Z* __restrict__ V,
+template <typename VB>
+__global__ __launch_bounds__(kBlock) void k_combine(int nv, int ld_r, size_t Nt, size_t vstride, const C2<VB>* __restrict__ V,
                                                      const Z* __restrict__ yv, Z* __restrict__ out, int accumulate) {
   const int r = blockIdx.y;
   for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
     Z acc = accumulate ? out[(size_t)r * Nt + k] : Z{0, 0};
     for (int i = 0; i < nv; ++i) {
-      const Z v = V[i * vstride + (size_t)r * Nt + k];
+      const C2<VB> t = V[i * vstride + (size_t)r * Nt + k];
+      const Z v{(double)t.x, (double)t.y};
       const Z c = yv[(size_t)r * ld_r + i];
       acc.x += v.x * c.x - v.y * c.y;
       acc.y += v.x * c.y + v.y * c.x;
@@ -1791,7 +1809,10 @@ class EngineT final : public Engine {
   }
 
   int gmres(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0, bool always_reorth,
-            std::vector<GmresResult>& res, void* stream, std::string& err) override;
+            bool fp32_basis, std::vector<GmresResult>& res, void* stream, std::string& err) override;
+  template <typename VB>
+  int gmres_t(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0, bool always_reorth,
+              std::vector<GmresResult>& res, void* stream, std::string& err);
 
   void profile(bool enable) override {
     prof_on_ = enable;
@@ -1981,7 +2002,18 @@ class EngineT final : public Engine {
 // once, for the Hessenberg column; the next product is already queued.
 template <typename T>
 int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0,
-                      bool always_reorth, std::vector<GmresResult>& res, void* stream, std::string& err) {
+                      bool always_reorth, bool fp32_basis, std::vector<GmresResult>& res, void* stream,
+                      std::string& err) {
+  if (fp32_basis) return gmres_t<float>(bv, xv, R, rtol, max_iter, m, use_x0, always_reorth, res, stream, err);
+  return gmres_t<double>(bv, xv, R, rtol, max_iter, m, use_x0, always_reorth, res, stream, err);
+}
+
+// VB: precision the Krylov basis is stored in (all Arnoldi arithmetic is FP64)
+template <typename T>
+template <typename VB>
+int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_iter, int m, bool use_x0,
+                        bool always_reorth, std::vector<GmresResult>& res, void* stream, std::string& err) {
+  using CV = C2<VB>;
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t Nt = (size_t)P_ * n_;
@@ -1990,7 +2022,7 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
   const int ld = m + 2;        // per-RHS coefficient slots: m + 1 dots/norm + gate
   const int nblk_d = (int)std::min<size_t>(kDotMaxBlocks, (Nt + kDotChunk - 1) / kDotChunk);
   const int nblk_s = (int)std::min<size_t>(1024, (Nt + kBlock - 1) / kBlock);
-  HIP_TRY(gV_.alloc((size_t)(m + 1) * tot * sizeof(Z)));
+  HIP_TRY(gV_.alloc((size_t)(m + 1) * tot * sizeof(CV)));
   HIP_TRY(gw_.alloc(tot * sizeof(Z)));
   HIP_TRY(gx_.alloc(tot * sizeof(Z)));
   HIP_TRY(gb_.alloc(tot * sizeof(Z)));
@@ -2007,7 +2039,7 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
   HIP_TRY(hcol_.alloc((size_t)R * ld * sizeof(Z)));
   HIP_TRY(hy_.alloc((size_t)R * ld * sizeof(Z)));
   if (!col_ev_) HIP_TRY(hipEventCreateWithFlags(&col_ev_, hipEventDisableTiming));
-  Z* V = gV_.as<Z>();
+  CV* V = gV_.as<CV>();
   Z* w = gw_.as<Z>();
   Z* x = gx_.as<Z>();
   Z* b = gb_.as<Z>();
@@ -2028,17 +2060,21 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
   const dim3 gv(grid1d(Nt) > 1024 ? 1024 : grid1d(Nt), R);
   // h[r][0..nv) = V_i^H w_r, and h[r][nv] = |w_r|^2 when want_norm
   auto dots = [&](int nv, int want_norm, const Z* ww, Z* out, int ldo, const int* g) {
-    hipLaunchKernelGGL(k_dots, dim3(nblk_d, R), blk, 0, st, nv, want_norm, Nt, vstride, V, ww, part, ld, g);
+    hipLaunchKernelGGL(k_dots<VB>, dim3(nblk_d, R), blk, 0, st, nv, want_norm, Nt, vstride, (const CV*)V, ww, part,
+                       ld, g);
     hipLaunchKernelGGL(k_reduce, dim3(nv + want_norm, R), blk, 0, st, nblk_d, part, ld, out, ldo, g);
   };
   // ww -= sum_i V_i c_i; nout[r] = |ww_r|^2
   auto subtract = [&](int nv, const Z* c, Z* ww, Z* nout, const int* g) {
-    hipLaunchKernelGGL(k_subtract_norm, dim3(nblk_s, R), blk, 0, st, nv, Nt, vstride, V, c, ld, ww, part, g);
+    hipLaunchKernelGGL(k_subtract_norm<VB>, dim3(nblk_s, R), blk, 0, st, nv, Nt, vstride, (const CV*)V, c, ld, ww,
+                       part, g);
     hipLaunchKernelGGL(k_reduce, dim3(1, R), blk, 0, st, nblk_s, part, 1, nout, 1, g);
   };
-  // operator A z = Z (P^-1 z), z FP64 -> result FP64 in `out`
-  auto apply_A = [&](const Z* z, Z* out, bool precond) -> int {
-    hipLaunchKernelGGL(k_from_z<T>, dim3(grid1d(tot)), blk, 0, st, z, tT, tot);
+  // operator A z = Z (P^-1 z) -> result FP64 in `out`; z is a basis vector
+  // (precond) or an FP64 iterate
+  auto apply_A_from = [&](auto* z, Z* out, bool precond) -> int {
+    using S = typename std::remove_const<typename std::remove_pointer<decltype(z)>::type>::type;
+    hipLaunchKernelGGL((k_convert<decltype(S{}.x), T>), dim3(grid1d(tot)), blk, 0, st, (const S*)z, tT, tot);
     const CT* src = tT;
     if (precond) {
       if (int rc = precondition(tT, tT2, R, stream, err)) return rc;
@@ -2049,6 +2085,7 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
     hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, dst, out, tot);
     return 0;
   };
+  auto apply_A = [&](const Z* z, Z* out, bool precond) -> int { return apply_A_from(z, out, precond); };
   auto norms = [&](const Z* vec, std::vector<double>& out) -> int {
     dots(0, 1, vec, n1, 1, nullptr);
     HIP_TRY(hipMemcpyAsync(hcol, n1, (size_t)R * sizeof(Z), hipMemcpyDeviceToHost, st));
@@ -2106,11 +2143,11 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
       if (!done[r]) cycles[r]++;
     }
     HIP_TRY(hipMemcpyAsync(scale, s0.data(), (size_t)R * sizeof(double), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_scale_real, gv, blk, 0, st, Nt, w, scale, V);
+    hipLaunchKernelGGL(k_scale_real<VB>, gv, blk, 0, st, Nt, (const Z*)w, (const double*)scale, V);
     int j = 0;
     std::vector<char> active(R);
     for (int r = 0; r < R; ++r) active[r] = !done[r];
-    if (int rc = apply_A(V, w, true)) return rc;
+    if (int rc = apply_A_from((const CV*)V, w, true)) return rc;
     for (; j < m && total_it < max_iter; ++j) {
       ++total_it;
       const int nv = j + 1;
@@ -2122,12 +2159,13 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
       dots(nv, 0, w, h2, ld, gate);
       subtract(nv, h2, w, n2, gate);
       hipLaunchKernelGGL(k_arnoldi_col, dim3(R), blk, 0, st, nv, ld, h1, n1, h2, n2, gate, col, scale);
-      hipLaunchKernelGGL(k_scale_real, gv, blk, 0, st, Nt, w, scale, V + (size_t)(j + 1) * vstride);
+      hipLaunchKernelGGL(k_scale_real<VB>, gv, blk, 0, st, Nt, (const Z*)w, (const double*)scale,
+                         V + (size_t)(j + 1) * vstride);
       HIP_TRY(hipMemcpyAsync(hcol, col, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipEventRecord(col_ev_, st));
       // queue the next product before the host looks at the column
       if (j + 1 < m && total_it < max_iter)
-        if (int rc = apply_A(V + (size_t)(j + 1) * vstride, w, true)) return rc;
+        if (int rc = apply_A_from((const CV*)(V + (size_t)(j + 1) * vstride), w, true)) return rc;
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipEventSynchronize(col_ev_));
       bool any_active = false;
@@ -2185,7 +2223,7 @@ int EngineT<T>::gmres(const void* bv, void* xv, int R, double rtol, int max_iter
       for (int i = 0; i < j; ++i) hy[(size_t)r * ld + i] = Z{yy[i].real(), yy[i].imag()};
     }
     HIP_TRY(hipMemcpyAsync(h1, hy, (size_t)R * ld * sizeof(Z), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_combine, gv, blk, 0, st, j, ld, Nt, vstride, V, h1, tmp, 0);
+    hipLaunchKernelGGL(k_combine<VB>, gv, blk, 0, st, j, ld, Nt, vstride, (const CV*)V, (const Z*)h1, tmp, 0);
     // x += P^-1 tmp (through the context precision)
     hipLaunchKernelGGL(k_from_z<T>, dim3(grid1d(tot)), blk, 0, st, tmp, tT, tot);
     if (int rc = precondition(tT, tT2, R, stream, err)) return rc;

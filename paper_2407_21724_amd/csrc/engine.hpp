@@ -64,7 +64,7 @@ class Engine {
   virtual int rhs(const std::vector<cd>& pat, const std::vector<V3>& khat, int R, void* b, void* stream,
                   std::string& err) = 0;
   virtual int gmres(const void* b, void* x, int R, double rtol, int max_iter, int restart, bool use_x0,
-                    bool always_reorth, std::vector<GmresResult>& res, void* stream, std::string& err) = 0;
+                    bool always_reorth, bool fp32_basis, std::vector<GmresResult>& res, void* stream, std::string& err) = 0;
   virtual long long device_bytes() const = 0;
   // interpolation strip heights per level (0 = default planner); agg_rows
   // indexed by the parent level, dis_rows by the child level

@@ -21,6 +21,7 @@ C64, C128 = 0, 1
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 SOLVE_USE_X0 = 1
 SOLVE_ALWAYS_REORTH = 2
+SOLVE_FP32_BASIS = 4
 
 
 class MlfmaError(RuntimeError):
@@ -327,7 +328,7 @@ class Context:
         return out
 
     def gmres_solve(self, b, x=None, rtol=1e-4, max_iter=1000, restart=100, use_x0=False, always_reorth=False,
-                    stream=None):
+                    fp32_basis=False, stream=None):
         import torch
         R = b.shape[0]
         if x is None:
@@ -335,7 +336,8 @@ class Context:
         stats = (SolveStats * R)()
         rc = self._check(lib().mlfma_gmres_solve(self._h, self._dev(b, R), self._dev(x, R), R, rtol, max_iter,
                                                  restart, (SOLVE_USE_X0 if use_x0 else 0)
-                                                 | (SOLVE_ALWAYS_REORTH if always_reorth else 0), stats,
+                                                 | (SOLVE_ALWAYS_REORTH if always_reorth else 0)
+                                                 | (SOLVE_FP32_BASIS if fp32_basis else 0), stats,
                                                  _stream_ptr(stream)), "gmres_solve")
         out = [dict(iterations=s.iterations, true_rel_res=s.true_rel_res, time_s=s.time_s,
                     converged=bool(s.converged), reorth=s.reorth, cycles=s.cycles) for s in stats]

@@ -150,3 +150,23 @@ def test_c3_batched_64_incidences():
         d = rel_err(x[r].cpu().numpy(), xs[0].cpu().numpy())
         note(f"  RHS {r}: batched vs single solve {d:.2e}")
         assert d < 1e-3
+
+
+def test_fp32_krylov_basis():
+    """GMRES with the Krylov basis stored in FP32 (FP64 arithmetic) reaches
+    the same true residual as with the FP64 basis, in about as many
+    iterations, on a 12 x 12 subarray of the cylinders."""
+    wl = w.workload("c2", 12, 12)
+    v, t, e = wl.meshes[0]
+    M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+    ctx = make_ctx(wl, M, mlfma.C64)
+    inc = wl.incidences[0]
+    b = ctx.plane_wave_rhs(inc.khat[None], inc.pol[None])
+    x64, s64, rc64 = ctx.gmres_solve(b, rtol=1e-4, max_iter=2000, restart=100)
+    x32, s32, rc32 = ctx.gmres_solve(b, rtol=1e-4, max_iter=2000, restart=100, fp32_basis=True)
+    note(f"FP64 basis {s64[0]['iterations']} it, FP32 basis {s32[0]['iterations']} it, "
+         f"solutions differ by {rel_err(x32.cpu().numpy(), x64.cpu().numpy()):.2e}")
+    assert rc64 == mlfma.OK and rc32 == mlfma.OK
+    assert s32[0]["true_rel_res"] <= 1e-4
+    assert abs(s32[0]["iterations"] - s64[0]["iterations"]) <= 0.1 * s64[0]["iterations"] + 2
+    assert rel_err(x32.cpu().numpy(), x64.cpu().numpy()) < 1e-3
