@@ -55,7 +55,12 @@ enum {
   MLFMA_NOT_CONVERGED = 1
 };
 
-enum { MLFMA_C64 = 0, MLFMA_C128 = 1 };
+/* MLFMA_C64: complex FP32 data and arithmetic (FP32 matrix-core products);
+ * MLFMA_C128: complex FP64; MLFMA_C64_BF16: complex FP32 data with the dense
+ * contractions (near field, projection, receive) as three BF16 matrix-core
+ * products per FP32 product (a_hi b_hi + a_hi b_lo + a_lo b_hi, each operand
+ * split into a BF16 head and a BF16 remainder), accumulated in FP32. */
+enum { MLFMA_C64 = 0, MLFMA_C128 = 1, MLFMA_C64_BF16 = 2 };
 
 /* Parts of the operator applied by mlfma_matvec_parts(). */
 enum { MLFMA_PART_NEAR = 1, MLFMA_PART_FAR = 2, MLFMA_PART_ALL = 3 };
@@ -86,7 +91,7 @@ typedef struct {
   double digits;         /* d0 of the excess-bandwidth rule (3)             */
   int32_t interp_order;  /* points per direction of the Lagrange stencil
                             (default 6; 4 = the paper's 4 x 4)              */
-  int32_t precision;     /* MLFMA_C64 or MLFMA_C128                         */
+  int32_t precision;     /* MLFMA_C64, MLFMA_C128 or MLFMA_C64_BF16          */
   int32_t outer_levels;  /* subdivision levels of the outer triangle in the
                             singular (touching-pair) quadrature (2)         */
 } mlfma_tree_params;

@@ -59,7 +59,7 @@ def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDA
     report = {}
     gemm = list(ctx.get_gemm_tiles())
     default_gemm = tuple(gemm)
-    if ctx.params.precision == mlfma.C64:
+    if ctx.params.precision in (mlfma.C64, mlfma.C64_BF16):
         for gi, names in ((0, ("near+project", "near", "project")), (1, ("receive",))):
             times = {}
             for rt in (1, 2, 4):

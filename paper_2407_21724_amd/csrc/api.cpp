@@ -325,7 +325,8 @@ int mlfma_build_tree(const mlfma_problem* pb, const mlfma_tree_params* tp, mlfma
   }
   if (!pb || !tp || !pb->centers || !pb->class_id || pb->n_particles < 1 || pb->n_classes < 1)
     return MLFMA_EINVAL;
-  if (tp->precision != MLFMA_C64 && tp->precision != MLFMA_C128) return MLFMA_EINVAL;
+  if (tp->precision != MLFMA_C64 && tp->precision != MLFMA_C128 && tp->precision != MLFMA_C64_BF16)
+    return MLFMA_EINVAL;
   if (tp->outer_levels < 0 || tp->outer_levels > 5 || !(tp->digits > 0) || (tp->L_rule != 0 && tp->L_rule != 1))
     return MLFMA_EINVAL;
   ctx->tp = *tp;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
@@ -197,6 +198,8 @@ struct GemmJob {
   size_t sB, sC;    // per right-hand side (blockIdx.z) strides of B and C
   int M, ncols, nseg, kseg, lda, ldb, ldc, acc, tiles_m, tiles;
   int xcd;          // (job 0 only) blocks in XCD-aware order over a grid of xcd_grid(tiles)
+  const unsigned short* Ah;  // BF16-split kernel: A as BF16 heads and remainders (same layout as A)
+  const unsigned short* Al;
 };
 
 template <int RT, int CT, int Tag>
@@ -300,6 +303,102 @@ __global__ __launch_bounds__(kBlock) void k_near_sum(int P, int nf, const float*
     for (int o = 0; o < 9; ++o)
       if (has[p * 9 + o]) acc += pr[((size_t)o * P + p) * nf + m];
     y[(size_t)r * cnt + i] = acc;
+  }
+}
+
+// BF16-split variant: the same jobs, tiles and reduction as k_gemm_stream,
+// with each FP32 product a b formed as a_h b_h + a_h b_l + a_l b_h from BF16
+// heads and remainders (A split once on the host, B split in registers)
+// on v_mfma_f32_16x16x16bf16_1k, accumulated in FP32.  Lane layout: A[i][k]
+// is element k % 4 of lane i + 16 (k / 4), B[k][j] element k % 4 of lane
+// j + 16 (k / 4); the result as for the FP32 instruction.  A lane loads the
+// 4 consecutive k = 16 s + 4 kq .. + 3 of its row and column.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {  // round to nearest, ties to even
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+template <int RT, int Tag>
+__global__ __launch_bounds__(kBlock) void k_gemm_bf16x3(GemmJob j0, GemmJob j1) {
+  __shared__ f32x4 red[3][RT][64];
+  const int bid = j0.xcd ? xcd_block(blockIdx.x, j0.tiles + j1.tiles) : (int)blockIdx.x;
+  if (bid >= j0.tiles + j1.tiles) return;
+  const bool second = bid >= j0.tiles;
+  const int t = second ? bid - j0.tiles : bid;
+  const int M = second ? j1.M : j0.M, ncols = second ? j1.ncols : j0.ncols;
+  const int nseg = second ? j1.nseg : j0.nseg, kseg = second ? j1.kseg : j0.kseg;
+  const int lda = second ? j1.lda : j0.lda, ldb = second ? j1.ldb : j0.ldb, ldc = second ? j1.ldc : j0.ldc;
+  const int accumulate = second ? j1.acc : j0.acc, tiles_m = second ? j1.tiles_m : j0.tiles_m;
+  const int* __restrict__ bcol = second ? j1.bcol : j0.bcol;
+  const int* __restrict__ ccol = second ? j1.ccol : j0.ccol;
+  const int* __restrict__ a_off = second ? j1.a_off : j0.a_off;
+  const int tm = t % tiles_m, tn = t / tiles_m;
+  const size_t aoff = a_off ? (size_t)a_off[tn] : 0;
+  const unsigned short* __restrict__ Ah = (second ? j1.Ah : j0.Ah) + aoff;
+  const unsigned short* __restrict__ Al = (second ? j1.Al : j0.Al) + aoff;
+  const int m0 = tm * 16 * RT, n0 = tn * 16, r = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  const float* __restrict__ Bb = (second ? j1.B : j0.B) + (size_t)r * (second ? j1.sB : j0.sB);
+  const int K = nseg * kseg;
+  const int nsup = (K + 15) / 16;
+  const int s0 = (wave * nsup) / 4, s1 = ((wave + 1) * nsup) / 4;
+  const int n = n0 + i;
+  f32x4 acc[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int sup = s0; sup < s1; ++sup) {
+    const int k = 16 * sup + 4 * kq;
+    s16x4 ah[RT], al[RT], bh, bl;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int m = m0 + 16 * rt + i;
+      const bool ok = m < M && k < K;
+      ah[rt] = ok ? *reinterpret_cast<const s16x4*>(Ah + (size_t)m * lda + k) : s16x4{0, 0, 0, 0};
+      al[rt] = ok ? *reinterpret_cast<const s16x4*>(Al + (size_t)m * lda + k) : s16x4{0, 0, 0, 0};
+    }
+    f32x4 b = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (n < ncols && k < K) {
+      const int sg = nseg == 1 ? 0 : k / kseg;
+      const int src = bcol[(size_t)n * nseg + sg];
+      if (src >= 0) b = *reinterpret_cast<const f32x4*>(Bb + (size_t)src * ldb + (k - sg * kseg));
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned short h = f32_to_bf16(b[e]);
+      bh[e] = (short)h;
+      bl[e] = (short)f32_to_bf16(b[e] - bf16_to_f32(h));
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[rt], bh, acc[rt], 0, 0, 0);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[rt], bl, acc[rt], 0, 0, 0);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[rt], bh, acc[rt], 0, 0, 0);
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) red[wave - 1][rt][lane] = acc[rt];
+  }
+  __syncthreads();
+  if (wave != 0 || n >= ncols) return;
+  const int dcol = ccol[n];
+  if (dcol < 0) return;
+  float* __restrict__ col = (second ? j1.C : j0.C) + (size_t)r * (second ? j1.sC : j0.sC) + (size_t)dcol * ldc;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    f32x4 v = acc[rt];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) v += red[w][rt][lane];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = m0 + 16 * rt + 4 * kq + e;
+      if (m < M) col[m] = accumulate ? col[m] + v[e] : v[e];
+    }
   }
 }
 
@@ -1166,10 +1265,31 @@ class EngineT final : public Engine {
   // block for a given neighbour offset.
   int upload_mfma(const Upload& u, std::string& err) {
     mfma_ = std::is_same<T, float>::value && std::getenv("MLFMA_NO_MFMA") == nullptr;
+    bf16_ = mfma_ && u.precision == 2;
     near_uniform_ = false;
     if (!mfma_) return 0;
     const int n = n_, nf = 2 * n_;
     auto put_f = [&](DevMem& d, const std::vector<float>& v) { return put_raw(d, v.data(), v.size(), err); };
+    // the BF16 heads and remainders of a matrix (round to nearest, ties to even)
+    auto put_split = [&](DevMem& dh, DevMem& dl, const std::vector<float>& v) -> int {
+      if (!bf16_) return 0;
+      auto tobf = [](float f) {
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+      };
+      std::vector<uint16_t> h(v.size()), l(v.size());
+      for (size_t i = 0; i < v.size(); ++i) {
+        h[i] = tobf(v[i]);
+        const uint32_t hb = (uint32_t)h[i] << 16;
+        float hf;
+        std::memcpy(&hf, &hb, 4);
+        l[i] = tobf(v[i] - hf);
+      }
+      if (int rc = put_raw(dh, h.data(), h.size(), err)) return rc;
+      return put_raw(dl, l.data(), l.size(), err);
+    };
     auto block2 = [](std::vector<float>& A, size_t lda, size_t row, size_t col, cd z) {
       A[row * lda + col] = (float)z.real();
       A[row * lda + col + 1] = (float)-z.imag();
@@ -1225,6 +1345,8 @@ class EngineT final : public Engine {
       }
       if (int rc = put_f(A_proj_, Ap)) return rc;
       if (int rc = put_f(A_recv_, Ar)) return rc;
+      if (int rc = put_split(A_proj_h_, A_proj_l_, Ap)) return rc;
+      if (int rc = put_split(A_recv_h_, A_recv_l_, Ar)) return rc;
     }
     // near blocks: one matrix per offset shared by all particles?
     std::vector<int> sl(9, -1);
@@ -1247,6 +1369,7 @@ class EngineT final : public Engine {
           for (int k = 0; k < n; ++k) block2(An, lda, 2 * j, (size_t)o * nf + 2 * k, Zt[(size_t)k * n + j]);
       }
       if (int rc = put_f(A_near_, An)) return rc;
+      if (int rc = put_split(A_near_h_, A_near_l_, An)) return rc;
       std::vector<int> iota(P_);
       for (int p = 0; p < P_; ++p) iota[p] = p;
       if (int rc = put_i(iota_, iota, err)) return rc;
@@ -1285,6 +1408,7 @@ class EngineT final : public Engine {
       }
       ngcols_ = (int)bq.size();
       if (int rc = put_f(A_near_, Aall)) return rc;
+      if (int rc = put_split(A_near_h_, A_near_l_, Aall)) return rc;
       if (int rc = put_i(ng_bcol_, bq, err)) return rc;
       if (int rc = put_i(ng_ccol_, cq, err)) return rc;
       if (int rc = put_i(ng_aoff_, aoff, err)) return rc;
@@ -1452,6 +1576,8 @@ class EngineT final : public Engine {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_near_.template as<float>();
+    j.Ah = A_near_h_.template as<unsigned short>();
+    j.Al = A_near_l_.template as<unsigned short>();
     j.a_off = ng_aoff_.template as<int>();
     j.B = reinterpret_cast<const float*>(x);
     j.bcol = ng_bcol_.template as<int>();
@@ -1550,6 +1676,8 @@ class EngineT final : public Engine {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_near_.template as<float>();
+    j.Ah = A_near_h_.template as<unsigned short>();
+    j.Al = A_near_l_.template as<unsigned short>();
     j.B = reinterpret_cast<const float*>(x);
     j.bcol = near_nbr_.template as<int>();
     j.C = reinterpret_cast<float*>(y);
@@ -1572,6 +1700,8 @@ class EngineT final : public Engine {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_proj_.template as<float>();
+    j.Ah = A_proj_h_.template as<unsigned short>();
+    j.Al = A_proj_l_.template as<unsigned short>();
     j.a_off = a_off_proj_.template as<int>();
     j.B = reinterpret_cast<const float*>(x);
     j.bcol = gcol_part_.template as<int>();
@@ -1596,6 +1726,8 @@ class EngineT final : public Engine {
     const int nf = 2 * n_;
     GemmJob j{};
     j.A = A_recv_.template as<float>();
+    j.Ah = A_recv_h_.template as<unsigned short>();
+    j.Al = A_recv_l_.template as<unsigned short>();
     j.a_off = a_off_recv_.template as<int>();
     j.B = reinterpret_cast<const float*>(lv_[0].G.template as<CT>());
     j.bcol = gcol_box_.template as<int>();
@@ -1621,6 +1753,15 @@ class EngineT final : public Engine {
   void launch_gemm(Pending& pr, int rt, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
     const int nt = j0.tiles + j1.tiles;
     const dim3 grid(j0.xcd ? xcd_grid(nt) : nt, 1, R);
+    if (bf16_) {
+      if (rt == 1)
+        launch(pr, k_gemm_bf16x3<1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+      else if (rt == 2)
+        launch(pr, k_gemm_bf16x3<2, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+      else
+        launch(pr, k_gemm_bf16x3<4, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+      return;
+    }
     if (rt == 1)
       launch(pr, k_gemm_stream<1, 1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
     else if (rt == 2)
@@ -1979,6 +2120,8 @@ class EngineT final : public Engine {
   // test switch: every disaggregation takes the two-pass path
   bool force_two_pass_ = std::getenv("MLFMA_DIS_TWO_PASS") != nullptr;
   DevMem A_proj_, A_recv_, A_near_, iota_;
+  DevMem A_proj_h_, A_proj_l_, A_recv_h_, A_recv_l_, A_near_h_, A_near_l_;  // BF16-split copies
+  bool bf16_ = false;  // dense contractions as BF16-split matrix-core products
   DevMem gcol_part_, gcol_box_, a_off_proj_, a_off_recv_;  // class-grouped GEMM columns
   DevMem ng_bcol_, ng_ccol_, ng_aoff_, ng_has_, near_part_;  // class-pair near GEMM
   DevMem dis_tmp_;                                            // two-pass disaggregation

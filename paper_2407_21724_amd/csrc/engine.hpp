@@ -12,7 +12,7 @@ namespace mlfma {
 
 // Everything the device path needs, assembled on the host in FP64.
 struct Upload {
-  int precision = 0;  // 0 = complex float, 1 = complex double
+  int precision = 0;  // 0 = complex float, 1 = complex double, 2 = complex float with BF16-split products
   int N = 0, n = 0;   // modes per current, unknowns per particle (2N)
   int P = 0;
   int n_classes = 0;

@@ -17,7 +17,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libmlfma.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTREADY, ENONFINITE, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
-C64, C128 = 0, 1
+C64, C128, C64_BF16 = 0, 1, 2
 PART_NEAR, PART_FAR, PART_ALL = 1, 2, 3
 SOLVE_USE_X0 = 1
 SOLVE_ALWAYS_REORTH = 2

@@ -123,15 +123,17 @@ def test_lens_subarray_fields_vs_oracle():
     assert en < 1e-2 and ef < 1e-2
 
 
-def test_c3_batched_64_incidences():
+@pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C64_BF16])
+def test_c3_batched_64_incidences(prec):
     """64 incidences (polar 5i deg x azimuth 45j deg, TE/TM alternating) on a
-    12 x 12 subarray of the cylinders, solved in one batched GMRES: every
-    RHS reaches its own true residual, the batched product equals the
-    single-RHS products bitwise, and two RHS agree with their single solves."""
+    12 x 12 subarray of the cylinders, solved in one batched GMRES with FP32
+    or BF16-split products: every RHS reaches its own true residual, the
+    batched product equals the single-RHS products bitwise, and two RHS
+    agree with their single solves."""
     wl = w.workload("c3", 12, 12)
     v, t, e = wl.meshes[0]
     M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
-    ctx = make_ctx(wl, M, mlfma.C64)
+    ctx = make_ctx(wl, M, prec)
     kh = np.array([i.khat for i in wl.incidences])
     pol = np.array([i.pol for i in wl.incidences])
     b = ctx.plane_wave_rhs(kh, pol)
@@ -142,7 +144,7 @@ def test_c3_batched_64_incidences():
     x, stats, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=2000, restart=200)
     res = [s["true_rel_res"] for s in stats]
     its = [s["iterations"] for s in stats]
-    note(f"c3 64 RHS: iterations {min(its)}..{max(its)}, true residual max {max(res):.2e}")
+    note(f"c3 64 RHS precision={prec}: iterations {min(its)}..{max(its)}, true residual max {max(res):.2e}")
     assert rc == mlfma.OK and max(res) <= 1e-4
     for r in (5, 40):
         xs, st, rc1 = ctx.gmres_solve(b[r:r + 1].contiguous(), rtol=1e-4, max_iter=2000, restart=200)
