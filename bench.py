@@ -36,6 +36,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_c2_40x40.json")
 KERNELS = [
     ("aggregate_l", "k_aggregate", "hbm"),
     ("translate_l", "k_translate", "hbm"),
+    ("translate_tiled_l", "k_translate_tiled", "hbm"),
     ("disaggregate_l", "k_disaggregate", "hbm"),
     ("disaggregate_phi_l", "k_dis_phi", "hbm"),
     ("disaggregate_theta_l", "k_dis_theta", "hbm"),

@@ -34,15 +34,22 @@ struct alignas(2 * sizeof(T)) C2 {
   T x, y;
 };
 
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc += a b as four chained fused multiply-adds (one rounding each)
 template <typename T>
 __device__ __forceinline__ void cfma(C2<T>& acc, C2<T> a, C2<T> b) {
-  acc.x += a.x * b.x - a.y * b.y;
-  acc.y += a.x * b.y + a.y * b.x;
+  acc.x = fmadd(a.x, b.x, acc.x);
+  acc.x = fmadd(-a.y, b.y, acc.x);
+  acc.y = fmadd(a.x, b.y, acc.y);
+  acc.y = fmadd(a.y, b.x, acc.y);
 }
 template <typename T>
-__device__ __forceinline__ void cfma_conj_a(C2<T>& acc, C2<T> a, C2<T> b) {  // conj(a) * b
-  acc.x += a.x * b.x + a.y * b.y;
-  acc.y += a.x * b.y - a.y * b.x;
+__device__ __forceinline__ void cfma_conj_a(C2<T>& acc, C2<T> a, C2<T> b) {  // acc += conj(a) b
+  acc.x = fmadd(a.x, b.x, acc.x);
+  acc.x = fmadd(a.y, b.y, acc.x);
+  acc.y = fmadd(a.x, b.y, acc.y);
+  acc.y = fmadd(-a.y, b.x, acc.y);
 }
 template <typename T>
 __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
@@ -516,6 +523,9 @@ __device__ __forceinline__ int fdiv(int i, float inv_d) { return (int)(((float)i
 // each thread owns up to kAggVPT outputs of the strip and sums the children
 // in registers.
 constexpr int kAggVPT = 4;
+// staged copies into LDS keep this many loads of each kind in flight per
+// thread (a plain copy loop waits for every load before its LDS store)
+constexpr int kStageU = 2;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_aggregate(
     int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int crows_max,
@@ -642,19 +652,59 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
   const int half = npc / 2;
   const int plo = strip_prow[2 * strip], prows = strip_prow[2 * strip + 1] - plo + 1;
   const float inv_npc = 1.0f / npc;
-  for (int i = threadIdx.x; i < nrow * tmax; i += kBlock) {
-    const int e = c0 * tmax + i;
-    ttw[i] = tth_w[e];
-    ttr[i] = tth_flip[e] ? -1 - (tth_row[e] - plo) : tth_row[e] - plo;
-  }
-  for (int i = threadIdx.x; i < npc * pmax; i += kBlock) {
-    tpw[i] = tph_w[i];
-    tpc[i] = tph_col[i];
-  }
   const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)plo * npp;
   const C2<T>* __restrict__ src = Gp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)plo * npp;
-  if (stage_par)
-    for (int i = threadIdx.x; i < prows * npp; i += kBlock) par[i] = cmul_conj_a(ph[i], src[i]);
+  // the child's translated pattern (first two outputs per thread), loaded
+  // first so its latency overlaps the staging
+  const int nout = nrow * npc;
+  C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc + (size_t)c0 * npc;
+  C2<T> gpre[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    gpre[u] = i < nout ? dst[i] : C2<T>{0, 0};
+  }
+  // tables and phase-weighted parent rows, kStageU loads of each kind in flight
+  {
+    const int n1 = nrow * tmax, n2 = npc * pmax, n3 = stage_par ? prows * npp : 0;
+    const int nmax = max(n3, max(n1, n2));
+    for (int b = threadIdx.x; b < nmax; b += kStageU * kBlock) {
+      T w1[kStageU], w2[kStageU];
+      int r1[kStageU], f1[kStageU], c2[kStageU];
+      C2<T> g3[kStageU], p3[kStageU];
+#pragma unroll
+      for (int u = 0; u < kStageU; ++u) {
+        const int i = b + u * kBlock;
+        if (i < n1) {
+          const int e = c0 * tmax + i;
+          w1[u] = tth_w[e];
+          r1[u] = tth_row[e];
+          f1[u] = tth_flip[e];
+        }
+        if (i < n2) {
+          w2[u] = tph_w[i];
+          c2[u] = tph_col[i];
+        }
+        if (i < n3) {
+          g3[u] = src[i];
+          p3[u] = ph[i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageU; ++u) {
+        const int i = b + u * kBlock;
+        if (i < n1) {
+          ttw[i] = w1[u];
+          ttr[i] = f1[u] ? -1 - (r1[u] - plo) : r1[u] - plo;
+        }
+        if (i < n2) {
+          tpw[i] = w2[u];
+          tpc[i] = c2[u];
+        }
+        if (i < n3) par[i] = cmul_conj_a(p3[u], g3[u]);
+      }
+    }
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < prows * npc; i += kBlock) {
     const int row = fdiv(i, inv_npc), col = i - row * npc;
@@ -669,20 +719,29 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
     tmp[i] = v;
   }
   __syncthreads();
-  C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc + (size_t)c0 * npc;
-  for (int i = threadIdx.x; i < nrow * npc; i += kBlock) {
-    const int row = fdiv(i, inv_npc), col = i - row * npc;
-    const int colf = col + half < npc ? col + half : col + half - npc;
-    C2<T> v{0, 0};
-    for (int e = 0; e < tmax; ++e) {
-      const int rr = ttr[row * tmax + e];
-      const T w = ttw[row * tmax + e];
-      const C2<T> sv = rr >= 0 ? tmp[rr * npc + col] : tmp[(-1 - rr) * npc + colf];
-      v.x += w * sv.x;
-      v.y += w * sv.y;
+  for (int b = threadIdx.x; b < nout; b += 2 * kBlock) {
+    C2<T> o[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = b + u * kBlock;
+      o[u] = b == (int)threadIdx.x ? gpre[u] : (i < nout ? dst[i] : C2<T>{0, 0});
     }
-    const C2<T> o = dst[i];
-    dst[i] = {o.x + v.x, o.y + v.y};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = b + u * kBlock;
+      if (i >= nout) break;
+      const int row = fdiv(i, inv_npc), col = i - row * npc;
+      const int colf = col + half < npc ? col + half : col + half - npc;
+      C2<T> v{0, 0};
+      for (int e = 0; e < tmax; ++e) {
+        const int rr = ttr[row * tmax + e];
+        const T w = ttw[row * tmax + e];
+        const C2<T> sv = rr >= 0 ? tmp[rr * npc + col] : tmp[(-1 - rr) * npc + colf];
+        v.x += w * sv.x;
+        v.y += w * sv.y;
+      }
+      dst[i] = {o[u].x + v.x, o[u].y + v.y};
+    }
   }
 }
 
@@ -791,6 +850,121 @@ __global__ __launch_bounds__(kBlock) void k_translate(int nb, int K, const C2<T>
   C2<T>* dst = G + ((size_t)r * nb + p) * 2 * K;
   dst[s] = g0;
   dst[K + s] = g1;
+}
+
+// The same sums with the partners staged in LDS.  The interaction list of a
+// box is the 6 x 6 window of offsets [-2, 3] (even index) or [-3, 2] (odd)
+// in x and y around it, without the 3 x 3 neighbourhood.  A block takes a
+// TX x TY tile of receiving boxes, both components and NS consecutive
+// samples: it stages the tile's (TX + 6) x (TY + 6) source boxes (zeros
+// outside the grid) and the 49 translation operators of those samples, so
+// each source sample is read from L2 once per tile instead of once per
+// receiver.  Wave w takes the boxes of parity (w & 1, w >> 1), which makes
+// its offset loop uniform.  The terms are added in the order of the
+// gathered lists (dy outer, dx inner); partners outside the grid add zeros.
+template <typename T>
+struct TrNS {
+  static constexpr int v = sizeof(T) == 4 ? 16 : 8;
+};
+// The sums of the boxes of parity (PX, PY) in the staged tile: all offsets
+// are compile-time, so the stencil is 27 pairs of LDS reads at immediate
+// offsets from one per-lane base.
+template <typename T, int TX, int TY, int PX, int PY>
+__device__ __forceinline__ void tr_tile_sums(const C2<T>* __restrict__ sS, const C2<T>* __restrict__ sT, int lane,
+                                             int bx0, int by0, int s0, int nx, int ny, int K, C2<T>* __restrict__ Gr) {
+  constexpr int NS = TrNS<T>::v, HX = TX + 6, BW = (TX / 2) * (TY / 2);
+  constexpr int DXLO = PX ? -3 : -2, DYLO = PY ? -3 : -2;
+  for (int it = lane; it < BW * NS; it += 64) {
+    const int k = it / NS, s = it % NS;
+    const int bx = 2 * (k % (TX / 2)) + PX, by = 2 * (k / (TX / 2)) + PY;
+    const int gx = bx0 + bx, gy = by0 + by;
+    if (gx >= nx || gy >= ny || s0 + s >= K) continue;
+    const C2<T>* __restrict__ src = sS + 2 * ((by + 3) * HX + bx + 3) * NS + s;
+    const C2<T>* __restrict__ tl = sT + s;
+    C2<T> g0{0, 0}, g1{0, 0};
+#pragma unroll
+    for (int iy = 0; iy < 6; ++iy) {
+#pragma unroll
+      for (int ix = 0; ix < 6; ++ix) {
+        const int dy = DYLO + iy, dx = DXLO + ix;
+        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+        const C2<T> t = tl[((dy + 3) * 7 + dx + 3) * NS];
+        const int h = dy * HX + dx;
+        cfma(g0, t, src[2 * h * NS]);
+        cfma(g1, t, src[(2 * h + 1) * NS]);
+      }
+    }
+    C2<T>* dst = Gr + (size_t)(gy * nx + gx) * 2 * K + s0 + s;
+    dst[0] = g0;
+    dst[K] = g1;
+  }
+}
+// 16 bytes of complex values: the unit of the staging loads
+template <typename T>
+struct alignas(16) Vec16 {
+  C2<T> c[16 / sizeof(C2<T>)];
+};
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(kBlock) void k_translate_tiled(int nx, int ny, int K, int R, const C2<T>* __restrict__ S,
+                                                             C2<T>* __restrict__ G, const C2<T>* __restrict__ TL) {
+  constexpr int NS = TrNS<T>::v, HX = TX + 6, HY = TY + 6;
+  constexpr int VPU = 16 / sizeof(C2<T>), NV = NS / VPU;  // complex values per load, loads per row
+  constexpr int NSL = HY * HX * 2 * NV, NTL = 49 * NV;    // loads of the halo and of the operators
+  constexpr int IS = (NSL + kBlock - 1) / kBlock, IT = (NTL + kBlock - 1) / kBlock;
+  static_assert(TX % 2 == 0 && TY % 2 == 0, "tiles start at even boxes");
+  __shared__ Vec16<T> sSv[NSL];  // [halo box][component][sample]
+  __shared__ Vec16<T> sTv[NTL];  // [offset][sample]
+  const int tx = (nx + TX - 1) / TX, ntile = tx * ((ny + TY - 1) / TY);
+  const int nch = (K + NS - 1) / NS;
+  const int total = ntile * nch * R;
+  const int lb = xcd_block(blockIdx.x, total);
+  if (lb >= total) return;
+  const int tile = lb % ntile, rest = lb / ntile;
+  const int ch = rest % nch, r = rest / nch;
+  const int bx0 = (tile % tx) * TX, by0 = (tile / tx) * TY, s0 = ch * NS;
+  const int nb = nx * ny;
+  const C2<T>* __restrict__ Sr = S + (size_t)r * nb * 2 * K;
+  // all loads of this thread in flight at once, then the LDS stores (K is
+  // even and chunks start at multiples of NS, so a 16-byte unit never
+  // straddles the end of a pattern)
+  Vec16<T> bs[IS], bt[IT];
+#pragma unroll
+  for (int u = 0; u < IS; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    bs[u] = Vec16<T>{};
+    if (i < NSL) {
+      const int s = (i % NV) * VPU, t = i / NV;
+      const int h = t >> 1, gx = bx0 - 3 + h % HX, gy = by0 - 3 + h / HX;
+      if (gx >= 0 && gy >= 0 && gx < nx && gy < ny && s0 + s < K)
+        bs[u] = *reinterpret_cast<const Vec16<T>*>(Sr + ((size_t)(gy * nx + gx) * 2 + (t & 1)) * K + s0 + s);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int i = threadIdx.x + u * kBlock;
+    bt[u] = Vec16<T>{};
+    if (i < NTL) {
+      const int s = (i % NV) * VPU, o = i / NV;
+      if (s0 + s < K) bt[u] = *reinterpret_cast<const Vec16<T>*>(TL + (size_t)o * K + s0 + s);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IS; ++u)
+    if (threadIdx.x + u * kBlock < NSL) sSv[threadIdx.x + u * kBlock] = bs[u];
+#pragma unroll
+  for (int u = 0; u < IT; ++u)
+    if (threadIdx.x + u * kBlock < NTL) sTv[threadIdx.x + u * kBlock] = bt[u];
+  __syncthreads();
+  const C2<T>* __restrict__ sS = sSv[0].c;
+  const C2<T>* __restrict__ sT = sTv[0].c;
+  const int lane = threadIdx.x & 63;
+  C2<T>* __restrict__ Gr = G + (size_t)r * nb * 2 * K;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // wave index = box parity
+    case 0: tr_tile_sums<T, TX, TY, 0, 0>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+    case 1: tr_tile_sums<T, TX, TY, 1, 0>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+    case 2: tr_tile_sums<T, TX, TY, 0, 1>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+    default: tr_tile_sums<T, TX, TY, 1, 1>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+  }
 }
 
 // -------------------------------------------------------------------- rhs --
@@ -1848,11 +2022,29 @@ class EngineT final : public Engine {
         const Lvl& L = lv_[l];
         {
           dim3 grid(xcd_grid(L.nx * L.ny * R * ((L.K + kBlock - 1) / kBlock)));
-          auto pr = begin("translate_l" + std::to_string(l), cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K),
-                          16.0 * R * (double)pairs_[l] * L.K);
-          launch(pr, k_translate<T>, grid, blk, 0, st, L.nx * L.ny, L.K, L.S.template as<CT>(),
-                 L.G.template as<CT>(), L.TL.template as<CT>(), L.il_cnt.template as<int>(),
-                 L.il_src.template as<int>(), L.il_off.template as<int>(), R);
+          // LDS tiles where the grid is at least 8 x 8 boxes (smaller grids waste
+          // most of a tile's halo and the gathered lists are shorter there);
+          // the 16-byte staging needs an even sample count (np = 2L always is)
+          const int trm = L.K % 2 != 0 ? 0 : tr_force_ >= 0 ? tr_force_ : (L.nx >= 8 && L.ny >= 8 ? 1 : 0);
+          auto pr = begin((trm ? "translate_tiled_l" : "translate_l") + std::to_string(l),
+                          cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K), 16.0 * R * (double)pairs_[l] * L.K);
+          if (trm == 0) {
+            launch(pr, k_translate<T>, grid, blk, 0, st, L.nx * L.ny, L.K, L.S.template as<CT>(),
+                   L.G.template as<CT>(), L.TL.template as<CT>(), L.il_cnt.template as<int>(),
+                   L.il_src.template as<int>(), L.il_off.template as<int>(), R);
+          } else {
+            const int TX = trm == 1 ? 4 : 8, TY = trm == 3 ? 8 : 4, NS = TrNS<T>::v;
+            const dim3 gt(xcd_grid(((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY) * ((L.K + NS - 1) / NS) * R));
+            const C2<T>* Sp = L.S.template as<CT>();
+            C2<T>* Gp = L.G.template as<CT>();
+            const C2<T>* TLp = L.TL.template as<CT>();
+            if (trm == 1)
+              launch(pr, k_translate_tiled<T, 4, 4>, gt, blk, 0u, st, L.nx, L.ny, L.K, R, Sp, Gp, TLp);
+            else if (trm == 2)
+              launch(pr, k_translate_tiled<T, 8, 4>, gt, blk, 0u, st, L.nx, L.ny, L.K, R, Sp, Gp, TLp);
+            else
+              launch(pr, k_translate_tiled<T, 8, 8>, gt, blk, 0u, st, L.nx, L.ny, L.K, R, Sp, Gp, TLp);
+          }
         }
         if (l + 1 < ntl_) {
           const Lvl& Pp = lv_[l + 1];
@@ -2119,6 +2311,14 @@ class EngineT final : public Engine {
   bool mfma_ = false, near_uniform_ = false;
   // test switch: every disaggregation takes the two-pass path
   bool force_two_pass_ = std::getenv("MLFMA_DIS_TWO_PASS") != nullptr;
+  // translation kernel forced on every level: 0 = gathered lists, 1/2/3 = LDS
+  // tiles of 4x4 / 8x4 / 8x8 boxes; -1 = per level (tiles of 4x4 on grids of
+  // at least 8 x 8 boxes)
+  int tr_force_ = [] {
+    const char* e = std::getenv("MLFMA_TRANSLATE");
+    const int m = e ? std::atoi(e) : -1;
+    return m >= 0 && m <= 3 ? m : -1;
+  }();
   DevMem A_proj_, A_recv_, A_near_, iota_;
   DevMem A_proj_h_, A_proj_l_, A_recv_h_, A_recv_l_, A_near_h_, A_near_l_;  // BF16-split copies
   bool bf16_ = false;  // dense contractions as BF16-split matrix-core products

@@ -158,6 +158,7 @@ def test_two_pass_disaggregation_matches_strip_path():
     os.environ["MLFMA_DIS_TWO_PASS"] = "1"
     try:
         ctx2 = make_ctx(wl, g["M"], mlfma.C64)
+        ctx2.prepare()
         y_two = ctx2.matvec(to_dev(x, ctx2)).cpu().numpy()[0]
     finally:
         del os.environ["MLFMA_DIS_TWO_PASS"]
@@ -165,6 +166,36 @@ def test_two_pass_disaggregation_matches_strip_path():
     err = rel_err(y_two[g["rows"]], g["y"])
     note(f"two-pass vs strip {d:.2e}; vs oracle {err:.3e}")
     assert d < 1e-6 and err < TOL
+
+
+@pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C128])
+def test_tiled_translation_matches_gathered_lists(prec):
+    """The LDS-tiled translation (4x4, 8x4 and 8x8 box tiles; the default is
+    4x4) adds the same terms in the same order as the kernel that gathers
+    each box's interaction list, on the 13 x 11 grid (ragged against every
+    tile size) with two RHS.  Only the compiler's choice of fused
+    multiply-adds inside a complex product may differ, so the products agree
+    to a few units in the last place."""
+    wl = w.workload("c2", 13, 11)
+    v, t, e = wl.meshes[0]
+    M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+    x = w.random_complex((2, wl.n_particles, 60), 5)
+    ys = {}
+    for mode in ("0", "1", "2", "3"):
+        os.environ["MLFMA_TRANSLATE"] = mode
+        try:
+            ctx = make_ctx(wl, M, prec)
+            ctx.prepare()                 # the engine reads the switch when it is built
+        finally:
+            del os.environ["MLFMA_TRANSLATE"]
+        ys[mode] = ctx.matvec(to_dev(x, ctx)).cpu().numpy()
+        del ctx
+    note(f"translation modes, levels of the 13x11 grid, precision={prec}")
+    bound = 1e-6 if prec == mlfma.C64 else 1e-14
+    for mode in ("1", "2", "3"):
+        d = rel_err(ys[mode], ys["0"])
+        note(f"  mode {mode}: rel. difference to the gathered lists {d:.1e}")
+        assert d < bound, mode
 
 
 @pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C128, mlfma.C64_BF16])
