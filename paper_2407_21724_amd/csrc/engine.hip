@@ -526,6 +526,13 @@ constexpr int kAggVPT = 4;
 // staged copies into LDS keep this many loads of each kind in flight per
 // thread (a plain copy loop waits for every load before its LDS store)
 constexpr int kStageU = 2;
+
+// A stencil tap staged in LDS: weight and element offset of its operand.
+template <typename T>
+struct Tap {
+  T w;
+  int off;
+};
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_aggregate(
     int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int crows_max,
@@ -619,23 +626,26 @@ __global__ __launch_bounds__(kBlock) void k_aggregate(
 // G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), the anterpolation written
 // as gathers over the transposed stencils, added to the child's translated
 // pattern.  Block = (child box, component) x strip of ts child rows x RHS,
-// in XCD-aware order over a 1-D grid (child box fastest).  LDS: the strip's transposed theta tables, the transposed phi
-// tables, the phase-weighted parent rows [plo, phi] ([rows][np_p]) and their
-// phi-transposed interpolation ([rows][np_c]).
+// in XCD-aware order over a 1-D grid (child box fastest).  LDS: the strip's
+// transposed theta taps and the transposed phi taps as (weight, offset)
+// pairs, the phase-weighted parent rows [plo, phi] ([rows][np_p]), and their
+// phi anterpolation ([rows][np_c + np_c/2], each row followed by its first
+// half again).  A theta tap that crosses a pole reads its row half a turn
+// further on in phi, i.e. np_c/2 elements later, so every tap is one offset
+// read, one add and two FMAs.
+constexpr int kDisRPT = 4;  // parent rows per thread in the phi pass
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_disaggregate(
     int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int tmax, int pmax,
     int prows_max, const C2<T>* __restrict__ Gp, C2<T>* __restrict__ Gc, const int* __restrict__ tth_row,
     const T* __restrict__ tth_w, const int* __restrict__ tth_flip, const int* __restrict__ strip_prow,
     const int* __restrict__ tph_col, const T* __restrict__ tph_w, const C2<T>* __restrict__ phase, int nstrips,
-    int R, int stage_par) {
+    int R) {
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* par = reinterpret_cast<C2<T>*>(smem_raw);                         // [prows_max][npp] if staged
-  C2<T>* tmp = par + (stage_par ? (size_t)prows_max * npp : (size_t)0);     // [prows_max][npc]
-  T* ttw = reinterpret_cast<T*>(tmp + (size_t)prows_max * npc);
-  T* tpw = ttw + ts * tmax;
-  int* ttr = reinterpret_cast<int*>(tpw + npc * pmax);  // parent row relative to plo; -1-row if flipped
-  int* tpc = ttr + ts * tmax;
+  Tap<T>* tt = reinterpret_cast<Tap<T>*>(smem_raw);  // [ts][tmax]: weight, element offset into tmp
+  Tap<T>* tp = tt + ts * tmax;                        // [np_c][pmax]: weight, parent column
+  C2<T>* par = reinterpret_cast<C2<T>*>(tp + npc * pmax);  // [prows_max][np_p]
+  C2<T>* tmp = par + (size_t)prows_max * npp;              // [prows_max][np_c + np_c / 2]
   const int total = nxc * nyc * 2 * nstrips * R;
   const int lb = xcd_block(blockIdx.x, total);
   if (lb >= total) return;
@@ -649,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
   const int q = (cj & 1) * 2 + (ci & 1);
   const int Kc = ntc * npc, Kp = ntp * npp;
   const int nbc = nxc * nyc, nbp = nxp * nyp;
-  const int half = npc / 2;
+  const int half = npc / 2, rw = npc + half;
   const int plo = strip_prow[2 * strip], prows = strip_prow[2 * strip + 1] - plo + 1;
   const float inv_npc = 1.0f / npc;
   const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)plo * npp;
@@ -664,9 +674,9 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
     const int i = threadIdx.x + u * kBlock;
     gpre[u] = i < nout ? dst[i] : C2<T>{0, 0};
   }
-  // tables and phase-weighted parent rows, kStageU loads of each kind in flight
+  // taps and phase-weighted parent rows, kStageU loads of each kind in flight
   {
-    const int n1 = nrow * tmax, n2 = npc * pmax, n3 = stage_par ? prows * npp : 0;
+    const int n1 = nrow * tmax, n2 = npc * pmax, n3 = prows * npp;
     const int nmax = max(n3, max(n1, n2));
     for (int b = threadIdx.x; b < nmax; b += kStageU * kBlock) {
       T w1[kStageU], w2[kStageU];
@@ -693,32 +703,46 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
 #pragma unroll
       for (int u = 0; u < kStageU; ++u) {
         const int i = b + u * kBlock;
-        if (i < n1) {
-          ttw[i] = w1[u];
-          ttr[i] = f1[u] ? -1 - (r1[u] - plo) : r1[u] - plo;
-        }
-        if (i < n2) {
-          tpw[i] = w2[u];
-          tpc[i] = c2[u];
-        }
+        if (i < n1) tt[i] = Tap<T>{w1[u], (r1[u] - plo) * rw + (f1[u] ? half : 0)};
+        if (i < n2) tp[i] = Tap<T>{w2[u], c2[u]};
         if (i < n3) par[i] = cmul_conj_a(p3[u], g3[u]);
       }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < prows * npc; i += kBlock) {
-    const int row = fdiv(i, inv_npc), col = i - row * npc;
-    C2<T> v{0, 0};
-    for (int e = 0; e < pmax; ++e) {
-      const T w = tpw[col * pmax + e];
-      const int c = row * npp + tpc[col * pmax + e];
-      const C2<T> t = stage_par ? par[c] : cmul_conj_a(ph[c], src[c]);  // largest boxes: parent from L2
-      v.x += w * t.x;
-      v.y += w * t.y;
+  // phi pass: item = (child column, kDisRPT consecutive parent rows); the
+  // last rows of a strip are clamped (computed twice, stored once)
+  {
+    const int rchunks = (prows + kDisRPT - 1) / kDisRPT;
+    for (int it = threadIdx.x; it < npc * rchunks; it += kBlock) {
+      const int c = it % npc, rr0 = (it / npc) * kDisRPT;
+      int ro[kDisRPT];
+      C2<T> acc[kDisRPT];
+#pragma unroll
+      for (int j = 0; j < kDisRPT; ++j) {
+        ro[j] = min(rr0 + j, prows - 1) * npp;
+        acc[j] = C2<T>{0, 0};
+      }
+      const Tap<T>* __restrict__ tc = tp + c * pmax;
+      for (int e = 0; e < pmax; ++e) {
+        const Tap<T> t = tc[e];
+#pragma unroll
+        for (int j = 0; j < kDisRPT; ++j) {
+          const C2<T> z = par[ro[j] + t.off];
+          acc[j].x = fmadd(t.w, z.x, acc[j].x);
+          acc[j].y = fmadd(t.w, z.y, acc[j].y);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kDisRPT; ++j)
+        if (rr0 + j < prows) {
+          tmp[(rr0 + j) * rw + c] = acc[j];
+          if (c < half) tmp[(rr0 + j) * rw + npc + c] = acc[j];
+        }
     }
-    tmp[i] = v;
   }
   __syncthreads();
+  // theta pass, added to the child's pattern
   for (int b = threadIdx.x; b < nout; b += 2 * kBlock) {
     C2<T> o[2];
 #pragma unroll
@@ -731,14 +755,13 @@ __global__ __launch_bounds__(kBlock) void k_disaggregate(
       const int i = b + u * kBlock;
       if (i >= nout) break;
       const int row = fdiv(i, inv_npc), col = i - row * npc;
-      const int colf = col + half < npc ? col + half : col + half - npc;
+      const Tap<T>* __restrict__ tr = tt + row * tmax;
       C2<T> v{0, 0};
       for (int e = 0; e < tmax; ++e) {
-        const int rr = ttr[row * tmax + e];
-        const T w = ttw[row * tmax + e];
-        const C2<T> sv = rr >= 0 ? tmp[rr * npc + col] : tmp[(-1 - rr) * npc + colf];
-        v.x += w * sv.x;
-        v.y += w * sv.y;
+        const Tap<T> t = tr[e];
+        const C2<T> z = tmp[t.off + col];
+        v.x = fmadd(t.w, z.x, v.x);
+        v.y = fmadd(t.w, z.y, v.y);
       }
       dst[i] = {o[u].x + v.x, o[u].y + v.y};
     }
@@ -1675,8 +1698,10 @@ class EngineT final : public Engine {
         prng.push_back(hi);
         pmax_rows = std::max(pmax_rows, hi - lo + 1);
       }
-      return (size_t)pmax_rows * ((stage_par ? Pp.np : 0) + C.np) * sizeof(CT) +
-             (size_t)tsd * T0.tmax * (sizeof(T) + 4) + (size_t)C.np * T0.pmax * (sizeof(T) + 4);
+      // k_disaggregate: parent rows, the wrapped phi pass, both tap tables
+      return stage_par ? (size_t)pmax_rows * (Pp.np + C.np + C.np / 2) * sizeof(CT) +
+                             ((size_t)tsd * T0.tmax + (size_t)C.np * T0.pmax) * sizeof(Tap<T>)
+                       : (size_t)4 * Pp.np * sizeof(CT);  // two-pass path: k_dis_phi's row buffer
     };
     int tsd = C.nt;
     while (tsd > 1 && (size_t)C.nx * C.ny * 2 * ((C.nt + tsd - 1) / tsd) < kMinBlocks) tsd = (tsd + 1) / 2;
@@ -2076,7 +2101,7 @@ class EngineT final : public Engine {
                              I.ts_dis, I.tmax, I.pmax, I.prows_max, Pp.G.template as<CT>(), L.G.template as<CT>(),
                              I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
                              I.strip_prow.template as<int>(), I.tph_col.template as<int>(),
-                             I.tph_w.template as<T>(), I.phase.template as<CT>(), nstrips, R, I.dis_stage);
+                             I.tph_w.template as<T>(), I.phase.template as<CT>(), nstrips, R);
         }
       }
       if (near && near_grouped) near_sum();
