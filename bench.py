@@ -44,12 +44,21 @@ KERNELS = [
 ]
 
 
+def gemm_waves(var):
+    """Waves per block of the GEMM launches: the engine's rule (4, 8 or 16
+    from the environment variable, default 8)."""
+    v = os.environ.get(var)
+    w = int(v) if v and v.lstrip("-").isdigit() else 8
+    return w if w in (4, 16) else 8
+
+
 def kernel_of(stage, gemm_rows=(4, 4)):
     """Kernel symbol and roofline bound of a product stage; the GEMM symbols
-    carry the row tiles per block the context runs with."""
+    carry the row tiles and the waves per block the context runs with."""
     rn, rr = gemm_rows
-    gemm = {"near+project": f"k_gemm_stream<{rn}, 1, 0>", "near": f"k_gemm_stream<{rn}, 1, 1>",
-            "project": f"k_gemm_stream<{rn}, 1, 2>", "receive": f"k_gemm_stream<{rr}, 1, 3>"}
+    wn, wr = gemm_waves("MLFMA_GEMM_WAVES_NP"), gemm_waves("MLFMA_GEMM_WAVES_RECV")
+    gemm = {"near+project": f"k_gemm_stream<{rn}, 1, 0, {wn}>", "near": f"k_gemm_stream<{rn}, 1, 1, {wn}>",
+            "project": f"k_gemm_stream<{rn}, 1, 2, {wn}>", "receive": f"k_gemm_stream<{rr}, 1, 3, {wr}>"}
     if stage in gemm:
         return gemm[stage], "mfma"
     for prefix, sym, bound in KERNELS:

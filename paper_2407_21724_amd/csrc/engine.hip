@@ -204,18 +204,28 @@ struct GemmJob {
   const int* ccol;  // C column n: floats C[ccol[n] * ldc + m] (< 0: not written)
   size_t sB, sC;    // per right-hand side (blockIdx.z) strides of B and C
   int M, ncols, nseg, kseg, lda, ldb, ldc, acc, tiles_m, tiles;
-  int xcd;          // (job 0 only) blocks in XCD-aware order over a grid of xcd_grid(tiles)
+  int xcd;          // (job 0 only) blocks in XCD-aware order over the launch grid
+  int wtile;        // 1: every wave of a block takes its own tile over all of K (short K); 0: the
+                    // block's waves split one tile's K and add their partial sums
   const unsigned short* Ah;  // BF16-split kernel: A as BF16 heads and remainders (same layout as A)
   const unsigned short* Al;
 };
 
-template <int RT, int CT, int Tag>
-__global__ __launch_bounds__(kBlock) void k_gemm_stream(GemmJob j0, GemmJob j1) {
-  __shared__ f32x4 red[3][RT * CT][64];
-  const int bid = j0.xcd ? xcd_block(blockIdx.x, j0.tiles + j1.tiles) : (int)blockIdx.x;
-  if (bid >= j0.tiles + j1.tiles) return;
-  const bool second = bid >= j0.tiles;
-  const int t = second ? bid - j0.tiles : bid;
+constexpr int kMaxSeg = 9;  // segments of a gathered B column (the 3 x 3 neighbourhood)
+// blocks of a job: one per tile, or one per W tiles when every wave takes its own
+__host__ __device__ inline int gemm_blocks(const GemmJob& j, int W) { return j.wtile ? (j.tiles + W - 1) / W : j.tiles; }
+template <int RT, int CT, int Tag, int W>
+__global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) {
+  __shared__ f32x4 red[W - 1][RT * CT][64];
+  __shared__ int sbc[16 * CT * kMaxSeg];  // the tile's source columns per segment (nseg > 1)
+  const int nb0 = gemm_blocks(j0, W), nb1 = gemm_blocks(j1, W);
+  const int bid = j0.xcd ? xcd_block(blockIdx.x, nb0 + nb1) : (int)blockIdx.x;
+  if (bid >= nb0 + nb1) return;
+  const bool second = bid >= nb0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wt = second ? j1.wtile : j0.wtile;
+  const int t = wt ? (bid - (second ? nb0 : 0)) * W + wave : bid - (second ? nb0 : 0);
+  if (wt && t >= (second ? j1.tiles : j0.tiles)) return;  // wave-tile blocks have no barrier
   const int M = second ? j1.M : j0.M, ncols = second ? j1.ncols : j0.ncols;
   const int nseg = second ? j1.nseg : j0.nseg, kseg = second ? j1.kseg : j0.kseg;
   const int lda = second ? j1.lda : j0.lda, ldb = second ? j1.ldb : j0.ldb, ldc = second ? j1.ldc : j0.ldc;
@@ -226,16 +236,26 @@ __global__ __launch_bounds__(kBlock) void k_gemm_stream(GemmJob j0, GemmJob j1) 
   const int tm = t % tiles_m, tn = t / tiles_m;
   const float* __restrict__ A = (second ? j1.A : j0.A) + (a_off ? a_off[tn] : 0);
   const int m0 = tm * 16 * RT, n0 = tn * 16 * CT, r = blockIdx.z;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = lane & 15, kq = lane >> 4;
   const float* __restrict__ Bb = (second ? j1.B : j0.B) + (size_t)r * (second ? j1.sB : j0.sB);
   const int K = nseg * kseg;
   const int nsup = (K + 15) / 16;
-  const int s0 = (wave * nsup) / 4, s1 = ((wave + 1) * nsup) / 4;
-  // per column tile: this lane's column and its source rows per segment
-  int ncol[CT];
+  const int s0 = wt ? 0 : (wave * nsup) / W, s1 = wt ? nsup : ((wave + 1) * nsup) / W;
+  // this lane's columns and their source columns: one per column, or per
+  // segment staged in LDS (split-K blocks only, so the barrier is uniform)
+  int ncol[CT], src1[CT];
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) ncol[ct] = n0 + 16 * ct + i;
+  for (int ct = 0; ct < CT; ++ct) {
+    ncol[ct] = n0 + 16 * ct + i;
+    src1[ct] = nseg == 1 && ncol[ct] < ncols ? bcol[ncol[ct]] : -1;
+  }
+  if (nseg > 1) {
+    for (int e = threadIdx.x; e < 16 * CT * nseg; e += 64 * W) {
+      const int c = n0 + e / nseg;
+      sbc[e] = c < ncols ? bcol[(size_t)n0 * nseg + e] : -1;
+    }
+    __syncthreads();
+  }
   f32x4 acc[RT][CT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -253,10 +273,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm_stream(GemmJob j0, GemmJob j1) 
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       b[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const int n = ncol[ct];
-      if (n < ncols && k < K) {
+      if (k < K) {
         const int sg = nseg == 1 ? 0 : k / kseg;
-        const int src = bcol[(size_t)n * nseg + sg];
+        const int src = nseg == 1 ? src1[ct] : sbc[(16 * ct + i) * nseg + sg];
         if (src >= 0) b[ct] = *reinterpret_cast<const f32x4*>(Bb + (size_t)src * ldb + (k - sg * kseg));
       }
     }
@@ -268,22 +287,28 @@ __global__ __launch_bounds__(kBlock) void k_gemm_stream(GemmJob j0, GemmJob j1) 
         for (int ct = 0; ct < CT; ++ct)
           acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][q], b[ct][q], acc[rt][ct], 0, 0, 0);
   }
-  if (wave > 0) {
+  if (!wt) {
+    if (wave > 0) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) red[wave - 1][rt * CT + ct][lane] = acc[rt][ct];
+    }
+    __syncthreads();
+    if (wave != 0) return;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) red[wave - 1][rt * CT + ct][lane] = acc[rt][ct];
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int w = 0; w < W - 1; ++w) acc[rt][ct] += red[w][rt * CT + ct][lane];
   }
-  __syncthreads();
-  if (wave != 0) return;
   float* __restrict__ Cb = (second ? j1.C : j0.C) + (size_t)r * (second ? j1.sC : j0.sC);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      f32x4 v = acc[rt][ct];
-#pragma unroll
-      for (int w = 0; w < 3; ++w) v += red[w][rt * CT + ct][lane];
+      const f32x4 v = acc[rt][ct];
       const int n = ncol[ct];
       if (n >= ncols) continue;
       const int dcol = ccol[n];
@@ -533,12 +558,13 @@ struct Tap {
   T w;
   int off;
 };
-template <typename T>
+template <typename T, int ORD>
 __global__ __launch_bounds__(kBlock) void k_aggregate(
-    int order, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int crows_max,
+    int order_rt, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int crows_max,
     const C2<T>* __restrict__ Sc, C2<T>* __restrict__ Sp, const int* __restrict__ th_row,
     const T* __restrict__ th_w, const int* __restrict__ th_flip, const int* __restrict__ ph_col,
     const T* __restrict__ ph_w, const C2<T>* __restrict__ phase, const int* __restrict__ strip_crow, int nstage) {
+  const int order = ORD > 0 ? ORD : order_rt;  // a compile-time order unrolls the stencil loops
   extern __shared__ unsigned char smem_raw[];
   C2<T>* cbuf = reinterpret_cast<C2<T>*>(smem_raw);        // [nstage][crows_max][npc]
   C2<T>* tmp = cbuf + (size_t)nstage * crows_max * npc;    // [nstage][ts][npc]
@@ -1795,6 +1821,7 @@ class EngineT final : public Engine {
     j.tiles_m = (nf + 16 * rt - 1) / (16 * rt);
     j.tiles = j.tiles_m * (ngcols_ / 16);
     j.xcd = 1;  // consecutive tiles share a block matrix: keep them in one L2
+    j.wtile = short_k(j);
     return j;
   }
 
@@ -1870,6 +1897,9 @@ class EngineT final : public Engine {
     return 0;
   }
 
+  // one wave per tile where K is short (at most 16 k-steps of 16) and B
+  // columns are not segmented; the BF16-split kernel always splits K
+  int short_k(const GemmJob& j) const { return !bf16_ && j.nseg == 1 && j.nseg * j.kseg <= 256 ? 1 : 0; }
   // GEMM job descriptors of the matrix-core stages (see k_gemm_stream).
   GemmJob near_job(const CT* x, CT* y, int R, int rt) const {
     const int nf = 2 * n_;
@@ -1918,6 +1948,7 @@ class EngineT final : public Engine {
     j.acc = 0;
     j.tiles_m = (j.M + 16 * rt - 1) / (16 * rt);
     j.tiles = j.tiles_m * (ncols_pad_ / 16);
+    j.wtile = short_k(j);
     return j;
   }
   // y += receiving matrix of each particle's class times G0 (eqs. Tmn_fmm, Kmn_fmm)
@@ -1950,7 +1981,8 @@ class EngineT final : public Engine {
   // rt: 16-row MFMA tiles per block (1, 2 or 4; the jobs' tiles_m must use it)
   template <int Tag>
   void launch_gemm(Pending& pr, int rt, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
-    const int nt = j0.tiles + j1.tiles;
+    const int w = bf16_ ? 4 : Tag == 3 ? gw_recv_ : gw_np_;  // waves per block
+    const int nt = gemm_blocks(j0, w) + gemm_blocks(j1, w);
     const dim3 grid(j0.xcd ? xcd_grid(nt) : nt, 1, R);
     if (bf16_) {
       if (rt == 1)
@@ -1961,12 +1993,28 @@ class EngineT final : public Engine {
         launch(pr, k_gemm_bf16x3<4, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
       return;
     }
-    if (rt == 1)
-      launch(pr, k_gemm_stream<1, 1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
-    else if (rt == 2)
-      launch(pr, k_gemm_stream<2, 1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
-    else
-      launch(pr, k_gemm_stream<4, 1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+    if (w == 16) {
+      if (rt == 1)
+        launch(pr, k_gemm_stream<1, 1, Tag, 16>, grid, dim3(1024), 0u, st, j0, j1);
+      else if (rt == 2)
+        launch(pr, k_gemm_stream<2, 1, Tag, 16>, grid, dim3(1024), 0u, st, j0, j1);
+      else
+        launch(pr, k_gemm_stream<4, 1, Tag, 16>, grid, dim3(1024), 0u, st, j0, j1);
+    } else if (w == 8) {
+      if (rt == 1)
+        launch(pr, k_gemm_stream<1, 1, Tag, 8>, grid, dim3(512), 0u, st, j0, j1);
+      else if (rt == 2)
+        launch(pr, k_gemm_stream<2, 1, Tag, 8>, grid, dim3(512), 0u, st, j0, j1);
+      else
+        launch(pr, k_gemm_stream<4, 1, Tag, 8>, grid, dim3(512), 0u, st, j0, j1);
+    } else {
+      if (rt == 1)
+        launch(pr, k_gemm_stream<1, 1, Tag, 4>, grid, dim3(kBlock), 0u, st, j0, j1);
+      else if (rt == 2)
+        launch(pr, k_gemm_stream<2, 1, Tag, 4>, grid, dim3(kBlock), 0u, st, j0, j1);
+      else
+        launch(pr, k_gemm_stream<4, 1, Tag, 4>, grid, dim3(kBlock), 0u, st, j0, j1);
+    }
   }
 
   // One product y = Z x: near-field apply and leaf projection (one launch on
@@ -2037,7 +2085,7 @@ class EngineT final : public Engine {
                         cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
                         2.0 * R * (double)C.nx * C.ny * 2 *
                             (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K));
-        launch(pr, k_aggregate<T>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
+        launch(pr, I.order == 6 ? k_aggregate<T, 6> : k_aggregate<T, 0>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
                            Pp.np, I.ts_agg, I.crows_max, C.S.template as<CT>(), Pp.S.template as<CT>(),
                            I.th_row.template as<int>(), I.th_w.template as<T>(), I.th_flip.template as<int>(),
                            I.ph_col.template as<int>(), I.ph_w.template as<T>(), I.phase.template as<CT>(),
@@ -2336,6 +2384,14 @@ class EngineT final : public Engine {
   bool mfma_ = false, near_uniform_ = false;
   // test switch: every disaggregation takes the two-pass path
   bool force_two_pass_ = std::getenv("MLFMA_DIS_TWO_PASS") != nullptr;
+  // waves per block of the near/projection and of the receive GEMM launches
+  static int gemm_waves(const char* var) {  // 4, 8 or 16 (default 8)
+    const char* e = std::getenv(var);
+    const int w = e ? std::atoi(e) : 8;
+    return w == 4 || w == 16 ? w : 8;
+  }
+  int gw_np_ = gemm_waves("MLFMA_GEMM_WAVES_NP");
+  int gw_recv_ = gemm_waves("MLFMA_GEMM_WAVES_RECV");
   // translation kernel forced on every level: 0 = gathered lists, 1/2/3 = LDS
   // tiles of 4x4 / 8x4 / 8x8 boxes; -1 = per level (tiles of 4x4 on grids of
   // at least 8 x 8 boxes)
