@@ -210,7 +210,9 @@ int mlfma_precondition(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R
  * in the context precision.
  *  b_dev, x_dev: device [R][P][2][N] in the context precision.  x_dev holds
  *  the initial guess if flags & MLFMA_SOLVE_USE_X0 (else zero is used) and
- *  the best iterate on return.  rtol: relative tolerance on the true
+ *  the best iterate on return.  A guess x0 is first scaled by the complex
+ *  factor a = (Z x0)^H b / |Z x0|^2 that minimises |b - a Z x0|, so it never
+ *  starts worse than zero (a = 0 for a guess orthogonal to b).  rtol: relative tolerance on the true
  *  residual; max_iter: total matrix-vector products per RHS; restart: Krylov
  *  dimension m.  stats [R] (may be NULL).  Synchronous: returns after the
  *  solution is in x_dev.  Returns MLFMA_NOT_CONVERGED (1) if some RHS did
@@ -281,8 +283,9 @@ int mlfma_debug_translation(mlfma_ctx* ctx, int32_t level, int32_t dx, int32_t d
  * A fully connected ReLU network, trained on solutions the method itself
  * produces on small arrays, maps each particle's class, its eight
  * neighbours' geometry parameters and the incidence direction to its
- * static-mode coefficients; the prediction is the GMRES initial guess (with
- * the zero start as fallback, mlfma_gmres_solve with MLFMA_SOLVE_USE_X0).
+ * static-mode coefficients; the prediction is the GMRES initial guess
+ * (mlfma_gmres_solve with MLFMA_SOLVE_USE_X0, which scales it to its least
+ * residual; the zero start is the limit of that scaling).
  * The paper has no such network: this is an addition around its solver (the
  * solution vector of Sec. V stage v).  All network arithmetic is FP32 on
  * the GPU.  A network is not tied to a context. */

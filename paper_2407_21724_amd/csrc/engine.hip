@@ -1099,6 +1099,55 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
 
 // out[r * ldo + s] = sum over b < nblk of partial[((r * ldp) + s) * nblk + b]
 // (grid: slots x R), in a fixed order.
+// Per-RHS block partials of y^H b (slot 0) and |y|^2 (slot 1), reduced by
+// k_reduce: the minimal-residual scaling of an initial guess.
+__global__ __launch_bounds__(kBlock) void k_guess_dots(size_t Nt, const Z* __restrict__ y, const Z* __restrict__ b,
+                                                        Z* __restrict__ partial) {
+  const int r = blockIdx.y, nblk = gridDim.x, blk = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double red[3][kBlock / 64];
+  const Z* yr = y + (size_t)r * Nt;
+  const Z* br = b + (size_t)r * Nt;
+  double px = 0, py = 0, nn = 0;
+  for (size_t k = (size_t)blk * kBlock + threadIdx.x; k < Nt; k += (size_t)nblk * kBlock) {
+    const Z a = yr[k], c = br[k];
+    px += a.x * c.x + a.y * c.y;
+    py += a.x * c.y - a.y * c.x;
+    nn += a.x * a.x + a.y * a.y;
+  }
+  px = wave_sum(px);
+  py = wave_sum(py);
+  nn = wave_sum(nn);
+  if (lane == 0) {
+    red[0][wave] = px;
+    red[1][wave] = py;
+    red[2][wave] = nn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sx = 0, sy = 0, sn = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      sx += red[0][q];
+      sy += red[1][q];
+      sn += red[2][q];
+    }
+    partial[((size_t)r * 2 + 0) * nblk + blk] = Z{sx, sy};
+    partial[((size_t)r * 2 + 1) * nblk + blk] = Z{sn, 0.0};
+  }
+}
+// x_r = a_r x_r and w_r = b_r - a_r y_r (y = A x before scaling)
+__global__ __launch_bounds__(kBlock) void k_guess_apply(size_t Nt, const Z* __restrict__ alpha, Z* __restrict__ x,
+                                                         const Z* __restrict__ y, const Z* __restrict__ b,
+                                                         Z* __restrict__ w) {
+  const int r = blockIdx.y;
+  const Z a = alpha[r];
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
+    const size_t i = (size_t)r * Nt + k;
+    const Z xv = x[i], yv = y[i], bv = b[i];
+    x[i] = Z{a.x * xv.x - a.y * xv.y, a.x * xv.y + a.y * xv.x};
+    w[i] = Z{bv.x - (a.x * yv.x - a.y * yv.y), bv.y - (a.x * yv.y + a.y * yv.x)};
+  }
+}
 __global__ __launch_bounds__(kBlock) void k_reduce(int nblk, const Z* __restrict__ partial, int ldp,
                                                     Z* __restrict__ out, int ldo, const int* __restrict__ gate) {
   const int s = blockIdx.x, r = blockIdx.y;
@@ -2535,14 +2584,22 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   if (int rc = residual(w)) return rc;
   if (int rc = norms(w, rnorm)) return rc;
   if (use_x0) {
-    // fall back to a zero start where the guess is worse than zero
-    bool any = false;
-    for (int r = 0; r < R; ++r) any |= rnorm[r] > bnorm[r];
-    if (any) {
-      HIP_TRY(hipMemsetAsync(x, 0, tot * sizeof(Z), st));
-      if (int rc = residual(w)) return rc;
-      if (int rc = norms(w, rnorm)) return rc;
+    // scale each guess by the complex factor a = (A x0)^H b / |A x0|^2 that
+    // minimises |b - a A x0|: never worse than a zero start (a = 0), which is
+    // what a guess uncorrelated with the solution falls back to
+    hipLaunchKernelGGL(k_guess_dots, dim3(nblk_d, R), blk, 0, st, Nt, (const Z*)tmp, (const Z*)b, part);
+    hipLaunchKernelGGL(k_reduce, dim3(2, R), blk, 0, st, nblk_d, (const Z*)part, 2, n1, 2, nullptr);
+    HIP_TRY(hipMemcpyAsync(hcol, n1, (size_t)2 * R * sizeof(Z), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int r = 0; r < R; ++r) {
+      const double yy = hcol[2 * r + 1].x;
+      cd a = yy > 0.0 ? cd(hcol[2 * r].x, hcol[2 * r].y) / yy : cd(0.0);
+      if (!std::isfinite(a.real()) || !std::isfinite(a.imag())) a = 0.0;
+      hy[r] = Z{a.real(), a.imag()};
     }
+    HIP_TRY(hipMemcpyAsync(h1, hy, (size_t)R * sizeof(Z), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_guess_apply, gv, blk, 0, st, Nt, (const Z*)h1, x, (const Z*)tmp, (const Z*)b, w);
+    if (int rc = norms(w, rnorm)) return rc;
   }
   std::vector<char> done(R, 0);
   std::vector<int> iters(R, 0), reorth(R, 0), cycles(R, 0);

@@ -77,7 +77,12 @@ def test_gmres_initial_guess_and_zero_rhs(c1_solution):
     x0 = to_dev(J[None], ctx)
     x, stats, rc = ctx.gmres_solve(b, x=x0.clone(), rtol=1e-6, max_iter=50, restart=20, use_x0=True)
     assert rc == mlfma.OK and stats[0]["iterations"] == 0
-    # a guess worse than zero falls back to the zero start
+    # the guess is scaled by the complex factor that minimises its residual:
+    # a multiple of the solution needs no iteration ...
+    x, stats, rc = ctx.gmres_solve(b, x=((1.5 - 2.0j) * x0).contiguous(), rtol=1e-6, max_iter=50, restart=20,
+                                   use_x0=True)
+    assert rc == mlfma.OK and stats[0]["iterations"] == 0
+    # ... and a guess unrelated to it is scaled towards zero
     bad = to_dev(1e3 * w.random_complex(J[None].shape, 4), ctx)
     x, stats, rc = ctx.gmres_solve(b, x=bad, rtol=1e-6, max_iter=200, restart=50, use_x0=True)
     assert rc == mlfma.OK and stats[0]["true_rel_res"] <= 1e-6
