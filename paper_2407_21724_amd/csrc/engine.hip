@@ -261,10 +261,9 @@ __global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) 
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int sup = s0; sup < s1; ++sup) {
+  // operands of k-step sup (16 k): A rows of this lane, B column of this lane
+  auto load = [&](int sup, f32x4(&a)[RT], f32x4(&b)[CT]) {
     const int k = 16 * sup + 4 * kq;
-    f32x4 a[RT], b[CT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       const int m = m0 + 16 * rt + i;
@@ -279,13 +278,25 @@ __global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) 
         if (src >= 0) b[ct] = *reinterpret_cast<const f32x4*>(Bb + (size_t)src * ldb + (k - sg * kseg));
       }
     }
+  };
+  // two-stage pipeline: the next step's loads are in flight during this
+  // step's matrix-core products
+  f32x4 a0[RT], b0[CT], a1[RT], b1[CT];
+  if (s0 < s1) load(s0, a0, b0);
+#pragma unroll 2
+  for (int sup = s0; sup < s1; ++sup) {
+    if (sup + 1 < s1) load(sup + 1, a1, b1);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][q], b[ct][q], acc[rt][ct], 0, 0, 0);
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[rt][q], b0[ct][q], acc[rt][ct], 0, 0, 0);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) a0[rt] = a1[rt];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) b0[ct] = b1[ct];
   }
   if (!wt) {
     if (wave > 0) {
