@@ -883,31 +883,54 @@ __global__ __launch_bounds__(kBlock) void k_dis_theta(int nxc, int nyc, int ntc,
 // host) is uniform over the block, so all partner loads are independent.
 // Blocks (box fastest, then RHS, then 256-sample chunk) in XCD-aware order.
 constexpr int kMaxIL = 27;
+// One translation level of a multi-level launch: its grid, sample count,
+// patterns, operators and interaction lists, and its first block.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_translate(int nb, int K, const C2<T>* __restrict__ S,
-                                                       C2<T>* __restrict__ G, const C2<T>* __restrict__ TL,
-                                                       const int* __restrict__ il_cnt, const int* __restrict__ il_src,
-                                                       const int* __restrict__ il_off, int R) {
-  const int nz = (K + kBlock - 1) / kBlock;
-  const int total = nb * R * nz;
-  const int lb = xcd_block(blockIdx.x, total);
-  if (lb >= total) return;
+struct TrLevel {
+  const C2<T>* S;
+  C2<T>* G;
+  const C2<T>* TL;
+  const int *il_cnt, *il_src, *il_off;
+  int nx, ny, K, start;
+};
+constexpr int kMaxTrLv = 12;
+template <typename T>
+struct TrLevels {
+  TrLevel<T> lv[kMaxTrLv];
+  int n, total;  // levels, blocks over all of them
+};
+// the level of block b (levels in order of their first block)
+template <typename T>
+__device__ __forceinline__ int tr_level(const TrLevels<T>& L, int b) {
+  int l = 0;
+  while (l + 1 < L.n && b >= L.lv[l + 1].start) ++l;
+  return l;
+}
+// All levels in one launch: the translations of different levels are
+// independent (each reads its own aggregated patterns).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_translate(TrLevels<T> L, int R) {
+  const int gb = xcd_block(blockIdx.x, L.total);
+  if (gb >= L.total) return;
+  const TrLevel<T>& V = L.lv[tr_level(L, gb)];
+  const int nb = V.nx * V.ny, K = V.K, lb = gb - V.start;
   const int p = lb % nb, rest = lb / nb;
   const int r = rest % R;
   const int s = (rest / R) * kBlock + threadIdx.x;
   if (s >= K) return;
-  const int cnt = il_cnt[p];
-  const C2<T>* __restrict__ Sr = S + (size_t)r * nb * 2 * K;
+  const int cnt = V.il_cnt[p];
+  const C2<T>* __restrict__ Sr = V.S + (size_t)r * nb * 2 * K;
+  const C2<T>* __restrict__ TL = V.TL;
   C2<T> g0{0, 0}, g1{0, 0};
 #pragma unroll 4
   for (int e = 0; e < cnt; ++e) {
-    const int q = il_src[p * kMaxIL + e], o = il_off[p * kMaxIL + e];
+    const int q = V.il_src[p * kMaxIL + e], o = V.il_off[p * kMaxIL + e];
     const C2<T> t = TL[(size_t)o * K + s];
     const C2<T>* src = Sr + (size_t)q * 2 * K;
     cfma(g0, t, src[s]);
     cfma(g1, t, src[K + s]);
   }
-  C2<T>* dst = G + ((size_t)r * nb + p) * 2 * K;
+  C2<T>* dst = V.G + ((size_t)r * nb + p) * 2 * K;
   dst[s] = g0;
   dst[K + s] = g1;
 }
@@ -965,8 +988,7 @@ struct alignas(16) Vec16 {
   C2<T> c[16 / sizeof(C2<T>)];
 };
 template <typename T, int TX, int TY>
-__global__ __launch_bounds__(kBlock) void k_translate_tiled(int nx, int ny, int K, int R, const C2<T>* __restrict__ S,
-                                                             C2<T>* __restrict__ G, const C2<T>* __restrict__ TL) {
+__global__ __launch_bounds__(kBlock) void k_translate_tiled(TrLevels<T> L, int R) {
   constexpr int NS = TrNS<T>::v, HX = TX + 6, HY = TY + 6;
   constexpr int VPU = 16 / sizeof(C2<T>), NV = NS / VPU;  // complex values per load, loads per row
   constexpr int NSL = HY * HX * 2 * NV, NTL = 49 * NV;    // loads of the halo and of the operators
@@ -974,11 +996,15 @@ __global__ __launch_bounds__(kBlock) void k_translate_tiled(int nx, int ny, int 
   static_assert(TX % 2 == 0 && TY % 2 == 0, "tiles start at even boxes");
   __shared__ Vec16<T> sSv[NSL];  // [halo box][component][sample]
   __shared__ Vec16<T> sTv[NTL];  // [offset][sample]
+  const int gb = xcd_block(blockIdx.x, L.total);
+  if (gb >= L.total) return;
+  const TrLevel<T>& V = L.lv[tr_level(L, gb)];
+  const int nx = V.nx, ny = V.ny, K = V.K, lb = gb - V.start;
+  const C2<T>* __restrict__ S = V.S;
+  C2<T>* __restrict__ G = V.G;
+  const C2<T>* __restrict__ TL = V.TL;
   const int tx = (nx + TX - 1) / TX, ntile = tx * ((ny + TY - 1) / TY);
   const int nch = (K + NS - 1) / NS;
-  const int total = ntile * nch * R;
-  const int lb = xcd_block(blockIdx.x, total);
-  if (lb >= total) return;
   const int tile = lb % ntile, rest = lb / ntile;
   const int ch = rest % nch, r = rest / nch;
   const int bx0 = (tile % tx) * TX, by0 = (tile / tx) * TY, s0 = ch * NS;
@@ -1403,6 +1429,10 @@ class EngineT final : public Engine {
     const Tree& tr = *u.tree;
     tree_ = u.tree;
     ntl_ = tr.ntl;
+    if (ntl_ > kMaxTrLv) {
+      err = "more than " + std::to_string(kMaxTrLv) + " tree levels";
+      return -1;
+    }
     lv_.clear();
     lv_.resize(ntl_);
     it_.clear();
@@ -2038,6 +2068,52 @@ class EngineT final : public Engine {
     j.xcd = 1;  // the row tiles of one column tile read the same G0 columns
     return j;
   }
+  // All translation levels, in two launches: LDS tiles on grids of at least
+  // 8 x 8 boxes (smaller grids waste most of a tile's halo and their gathered
+  // lists are shorter), gathered lists on the others; largest level first so
+  // the small ones fill the tail.  The 16-byte tile staging needs an even
+  // sample count (np = 2L always is).
+  void launch_translations(int R, hipStream_t st, double cb) {
+    TrLevels<T> tiled{}, gath{};
+    double tb = 0, tf = 0, gbytes = 0, gf = 0;
+    int trm_all = 0;
+    for (int l = 0; l < ntl_; ++l) {
+      const Lvl& L = lv_[l];
+      const int trm = L.K % 2 != 0 ? 0 : tr_force_ >= 0 ? tr_force_ : (L.nx >= 8 && L.ny >= 8 ? 1 : 0);
+      TrLevels<T>& D = trm ? tiled : gath;
+      TrLevel<T>& V = D.lv[D.n++];
+      V = TrLevel<T>{L.S.template as<CT>(), L.G.template as<CT>(), L.TL.template as<CT>(),
+                     L.il_cnt.template as<int>(), L.il_src.template as<int>(), L.il_off.template as<int>(),
+                     L.nx, L.ny, L.K, D.total};
+      const double bytes = cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K), flops = 16.0 * R * (double)pairs_[l] * L.K;
+      if (trm) {
+        trm_all = trm;
+        const int TX = trm == 1 ? 4 : 8, TY = trm == 3 ? 8 : 4, NS = TrNS<T>::v;
+        D.total += ((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY) * ((L.K + NS - 1) / NS) * R;
+        tb += bytes;
+        tf += flops;
+      } else {
+        D.total += L.nx * L.ny * R * ((L.K + kBlock - 1) / kBlock);
+        gbytes += bytes;
+        gf += flops;
+      }
+    }
+    const dim3 blk(kBlock);
+    if (tiled.n) {
+      auto pr = begin("translate_tiled", tb, tf);
+      const dim3 g(xcd_grid(tiled.total));
+      if (trm_all == 1)
+        launch(pr, k_translate_tiled<T, 4, 4>, g, blk, 0u, st, tiled, R);
+      else if (trm_all == 2)
+        launch(pr, k_translate_tiled<T, 8, 4>, g, blk, 0u, st, tiled, R);
+      else
+        launch(pr, k_translate_tiled<T, 8, 8>, g, blk, 0u, st, tiled, R);
+    }
+    if (gath.n) {
+      auto pr = begin("translate", gbytes, gf);
+      launch(pr, k_translate<T>, dim3(xcd_grid(gath.total)), blk, 0u, st, gath, R);
+    }
+  }
   // rt: 16-row MFMA tiles per block (1, 2 or 4; the jobs' tiles_m must use it)
   template <int Tag>
   void launch_gemm(Pending& pr, int rt, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
@@ -2151,34 +2227,9 @@ class EngineT final : public Engine {
                            I.ph_col.template as<int>(), I.ph_w.template as<T>(), I.phase.template as<CT>(),
                            I.strip_crow.template as<int>(), I.agg_stage);
       }
+      launch_translations(R, st, cb);
       for (int l = ntl_ - 1; l >= 0; --l) {
         const Lvl& L = lv_[l];
-        {
-          dim3 grid(xcd_grid(L.nx * L.ny * R * ((L.K + kBlock - 1) / kBlock)));
-          // LDS tiles where the grid is at least 8 x 8 boxes (smaller grids waste
-          // most of a tile's halo and the gathered lists are shorter there);
-          // the 16-byte staging needs an even sample count (np = 2L always is)
-          const int trm = L.K % 2 != 0 ? 0 : tr_force_ >= 0 ? tr_force_ : (L.nx >= 8 && L.ny >= 8 ? 1 : 0);
-          auto pr = begin((trm ? "translate_tiled_l" : "translate_l") + std::to_string(l),
-                          cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K), 16.0 * R * (double)pairs_[l] * L.K);
-          if (trm == 0) {
-            launch(pr, k_translate<T>, grid, blk, 0, st, L.nx * L.ny, L.K, L.S.template as<CT>(),
-                   L.G.template as<CT>(), L.TL.template as<CT>(), L.il_cnt.template as<int>(),
-                   L.il_src.template as<int>(), L.il_off.template as<int>(), R);
-          } else {
-            const int TX = trm == 1 ? 4 : 8, TY = trm == 3 ? 8 : 4, NS = TrNS<T>::v;
-            const dim3 gt(xcd_grid(((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY) * ((L.K + NS - 1) / NS) * R));
-            const C2<T>* Sp = L.S.template as<CT>();
-            C2<T>* Gp = L.G.template as<CT>();
-            const C2<T>* TLp = L.TL.template as<CT>();
-            if (trm == 1)
-              launch(pr, k_translate_tiled<T, 4, 4>, gt, blk, 0u, st, L.nx, L.ny, L.K, R, Sp, Gp, TLp);
-            else if (trm == 2)
-              launch(pr, k_translate_tiled<T, 8, 4>, gt, blk, 0u, st, L.nx, L.ny, L.K, R, Sp, Gp, TLp);
-            else
-              launch(pr, k_translate_tiled<T, 8, 8>, gt, blk, 0u, st, L.nx, L.ny, L.K, R, Sp, Gp, TLp);
-          }
-        }
         if (l + 1 < ntl_) {
           const Lvl& Pp = lv_[l + 1];
           const Itp& I = it_[l + 1];
