@@ -1093,7 +1093,7 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-constexpr int kDotChunk = 512;      // vector elements per block and sweep (8 per lane)
+constexpr int kDotE = 4;             // vector elements per lane and sweep of k_dots
 constexpr int kDotMaxBlocks = 512;
 
 // Block partial sums of the inner products conj(V_i) . w (slots i < nv) and,
@@ -1108,29 +1108,70 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
                                                   Z* __restrict__ partial, int ldp, const int* __restrict__ gate) {
   const int r = blockIdx.y;
   if (gate && !gate[r]) return;
-  const int nblk = gridDim.x, blk = blockIdx.x;
+  // per wave: kDotE elements per lane of w held in registers while every
+  // basis vector streams past them once; per-vector wave sums accumulate in
+  // LDS red[vector][wave] (dynamic, (nv + want_norm) * kBlock / 64 entries)
+  extern __shared__ unsigned char smem_raw[];
+  Z* red = reinterpret_cast<Z*>(smem_raw);
+  constexpr int NW = kBlock / 64;
+  const int ns = nv + want_norm, nblk = gridDim.x, blk = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < ns * NW; i += kBlock) red[i] = Z{0, 0};
+  __syncthreads();
   const Z* wr = w + (size_t)r * Nt;
-  for (int s = wave; s < nv + want_norm; s += kBlock / 64) {
-    const bool norm = s == nv;
-    const C2<VB>* vr = V + (size_t)(norm ? 0 : s) * vstride + (size_t)r * Nt;
-    double ax = 0, ay = 0;
-    for (size_t c0 = (size_t)blk * kDotChunk; c0 < Nt; c0 += (size_t)nblk * kDotChunk) {
+  const C2<VB>* Vr = V + (size_t)r * Nt;
+  const size_t sweep = (size_t)nblk * NW * 64 * kDotE;
+  for (size_t base = ((size_t)blk * NW + wave) * 64 * kDotE; base < Nt; base += sweep) {
+    Z wv[kDotE];
 #pragma unroll
-      for (int e = 0; e < kDotChunk / 64; ++e) {
-        const size_t k = c0 + (size_t)e * 64 + lane;
-        if (k < Nt) {
-          const Z b = wr[k];
-          Z a = b;
-          if (!norm) a = Z{(double)vr[k].x, (double)vr[k].y};
-          ax += a.x * b.x + a.y * b.y;
-          ay += a.x * b.y - a.y * b.x;
+    for (int e = 0; e < kDotE; ++e) {
+      const size_t k = base + (size_t)e * 64 + lane;
+      wv[e] = k < Nt ? wr[k] : Z{0, 0};
+    }
+    for (int i0 = 0; i0 < nv; i0 += 4) {
+      C2<VB> v[4][kDotE];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {
+          const size_t k = base + (size_t)e * 64 + lane;
+          v[u][e] = (i0 + u < nv && k < Nt) ? Vr[(size_t)(i0 + u) * vstride + k] : C2<VB>{0, 0};
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double ax = 0, ay = 0;
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {  // conj(v) w
+          const double a = (double)v[u][e].x, b = (double)v[u][e].y;
+          ax += a * wv[e].x + b * wv[e].y;
+          ay += a * wv[e].y - b * wv[e].x;
+        }
+        ax = wave_sum(ax);
+        ay = wave_sum(ay);
+        if (lane == 0 && i0 + u < nv) {
+          Z& o = red[(i0 + u) * NW + wave];
+          o.x += ax;
+          o.y += ay;
         }
       }
     }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    if (lane == 0) partial[((size_t)r * ldp + s) * nblk + blk] = Z{ax, ay};
+    if (want_norm) {
+      double nn = 0;
+#pragma unroll
+      for (int e = 0; e < kDotE; ++e) nn += wv[e].x * wv[e].x + wv[e].y * wv[e].y;
+      nn = wave_sum(nn);
+      if (lane == 0) red[nv * NW + wave].x += nn;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += kBlock) {
+    Z o{0, 0};
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      o.x += red[i * NW + q].x;
+      o.y += red[i * NW + q].y;
+    }
+    partial[((size_t)r * ldp + i) * nblk + blk] = o;
   }
 }
 
@@ -2555,7 +2596,7 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   const size_t tot = (size_t)R * Nt;
   const size_t vstride = tot;  // V[i] is [R][Nt]
   const int ld = m + 2;        // per-RHS coefficient slots: m + 1 dots/norm + gate
-  const int nblk_d = (int)std::min<size_t>(kDotMaxBlocks, (Nt + kDotChunk - 1) / kDotChunk);
+  const int nblk_d = (int)std::min<size_t>(kDotMaxBlocks, (Nt + kBlock * kDotE - 1) / (kBlock * kDotE));
   const int nblk_s = (int)std::min<size_t>(1024, (Nt + kBlock - 1) / kBlock);
   HIP_TRY(gV_.alloc((size_t)(m + 1) * tot * sizeof(CV)));
   HIP_TRY(gw_.alloc(tot * sizeof(Z)));
@@ -2595,8 +2636,8 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   const dim3 gv(grid1d(Nt) > 1024 ? 1024 : grid1d(Nt), R);
   // h[r][0..nv) = V_i^H w_r, and h[r][nv] = |w_r|^2 when want_norm
   auto dots = [&](int nv, int want_norm, const Z* ww, Z* out, int ldo, const int* g) {
-    hipLaunchKernelGGL(k_dots<VB>, dim3(nblk_d, R), blk, 0, st, nv, want_norm, Nt, vstride, (const CV*)V, ww, part,
-                       ld, g);
+    hipLaunchKernelGGL(k_dots<VB>, dim3(nblk_d, R), blk, (uint32_t)((nv + want_norm) * (kBlock / 64) * sizeof(Z)), st,
+                       nv, want_norm, Nt, vstride, (const CV*)V, ww, part, ld, g);
     hipLaunchKernelGGL(k_reduce, dim3(nv + want_norm, R), blk, 0, st, nblk_d, part, ld, out, ldo, g);
   };
   // ww -= sum_i V_i c_i; nout[r] = |ww_r|^2
