@@ -1093,7 +1093,7 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-constexpr int kDotE = 4;             // vector elements per lane and sweep of k_dots
+constexpr int kDotE = 4;  // vector elements per lane and sweep of k_dots
 constexpr int kDotMaxBlocks = 512;
 
 // Block partial sums of the inner products conj(V_i) . w (slots i < nv) and,
@@ -1108,40 +1108,41 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
                                                   Z* __restrict__ partial, int ldp, const int* __restrict__ gate) {
   const int r = blockIdx.y;
   if (gate && !gate[r]) return;
-  // per wave: kDotE elements per lane of w held in registers while every
+  // per wave: E elements per lane of w held in registers while every
   // basis vector streams past them once; per-vector wave sums accumulate in
   // LDS red[vector][wave] (dynamic, (nv + want_norm) * kBlock / 64 entries)
   extern __shared__ unsigned char smem_raw[];
   Z* red = reinterpret_cast<Z*>(smem_raw);
   constexpr int NW = kBlock / 64;
+  constexpr int VU = sizeof(VB) == 4 ? 8 : 4, E = kDotE;  // basis vectors per group, elements per lane
   const int ns = nv + want_norm, nblk = gridDim.x, blk = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < ns * NW; i += kBlock) red[i] = Z{0, 0};
   __syncthreads();
   const Z* wr = w + (size_t)r * Nt;
   const C2<VB>* Vr = V + (size_t)r * Nt;
-  const size_t sweep = (size_t)nblk * NW * 64 * kDotE;
-  for (size_t base = ((size_t)blk * NW + wave) * 64 * kDotE; base < Nt; base += sweep) {
-    Z wv[kDotE];
+  const size_t sweep = (size_t)nblk * NW * 64 * E;
+  for (size_t base = ((size_t)blk * NW + wave) * 64 * E; base < Nt; base += sweep) {
+    Z wv[E];
 #pragma unroll
-    for (int e = 0; e < kDotE; ++e) {
+    for (int e = 0; e < E; ++e) {
       const size_t k = base + (size_t)e * 64 + lane;
       wv[e] = k < Nt ? wr[k] : Z{0, 0};
     }
-    for (int i0 = 0; i0 < nv; i0 += 4) {
-      C2<VB> v[4][kDotE];
+    for (int i0 = 0; i0 < nv; i0 += VU) {
+      C2<VB> v[VU][E];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < VU; ++u)
 #pragma unroll
-        for (int e = 0; e < kDotE; ++e) {
+        for (int e = 0; e < E; ++e) {
           const size_t k = base + (size_t)e * 64 + lane;
           v[u][e] = (i0 + u < nv && k < Nt) ? Vr[(size_t)(i0 + u) * vstride + k] : C2<VB>{0, 0};
         }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < VU; ++u) {
         double ax = 0, ay = 0;
 #pragma unroll
-        for (int e = 0; e < kDotE; ++e) {  // conj(v) w
+        for (int e = 0; e < E; ++e) {  // conj(v) w
           const double a = (double)v[u][e].x, b = (double)v[u][e].y;
           ax += a * wv[e].x + b * wv[e].y;
           ay += a * wv[e].y - b * wv[e].x;
@@ -1158,7 +1159,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
     if (want_norm) {
       double nn = 0;
 #pragma unroll
-      for (int e = 0; e < kDotE; ++e) nn += wv[e].x * wv[e].x + wv[e].y * wv[e].y;
+      for (int e = 0; e < E; ++e) nn += wv[e].x * wv[e].x + wv[e].y * wv[e].y;
       nn = wave_sum(nn);
       if (lane == 0) red[nv * NW + wave].x += nn;
     }
@@ -1264,6 +1265,7 @@ __global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, siz
   const int r = blockIdx.y;
   if (gate && !gate[r]) return;
   __shared__ double red[kBlock / 64];
+  constexpr int VU = sizeof(VB) == 4 ? 8 : 4;  // basis vectors loaded together
   const Z* cr = c + (size_t)r * ldc;
   Z* wr = w + (size_t)r * Nt;
   const C2<VB>* Vr = V + (size_t)r * Nt;
@@ -1271,15 +1273,15 @@ __global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, siz
   for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
     Z acc = wr[k];
     int i = 0;
-    for (; i + 4 <= nv; i += 4) {
-      Z v[4];
+    for (; i + VU <= nv; i += VU) {
+      Z v[VU];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < VU; ++u) {
         const C2<VB> t = Vr[(size_t)(i + u) * vstride + k];
         v[u] = Z{(double)t.x, (double)t.y};
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < VU; ++u) {
         const Z q = cr[i + u];
         acc.x -= v[u].x * q.x - v[u].y * q.y;
         acc.y -= v[u].x * q.y + v[u].y * q.x;
