@@ -209,10 +209,15 @@ def lens_gmres(torch, w, mlfma):
         ctx.set_static_modes(c, v, t, e, wl.n_perp, wl.n_par, M, wl.eps_r)
     ctx.prepare()
     setup_s = time.perf_counter() - t0
+    from paper_2407_21724_amd import autotune
+    tfile = autotune.tuning_file("c4", 1)
+    if os.path.exists(tfile):
+        autotune.apply(tfile, ctx)
     inc = wl.incidences[0]
     b = ctx.plane_wave_rhs(inc.khat[None], inc.pol[None])
     res = {"workload": "80x80 metalens, 32 classes, 384000 unknowns, normal incidence, FP32 product",
-           "restart": 300, "setup_s": setup_s}
+           "restart": 300, "setup_s": setup_s,
+           "tuning": os.path.relpath(tfile, ROOT) if os.path.exists(tfile) else "default tile shapes"}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, st, _ = ctx.gmres_solve(b, rtol=1e-4, max_iter=4000, restart=300)
