@@ -192,6 +192,34 @@ def cpu_baseline(wl, M):
                        f"{P * P} block products = {T:.0f} s per product")}
 
 
+def focal_field(ctx, wl, x, inc, focal, torch, n=200, half=10.0):
+    """Field of the lens solution x on an n x n grid in the focal plane
+    (z = focal length above the array, +-half wavelengths about the axis),
+    by mlfma_fields; the focal spot's peak and its width along x."""
+    import numpy as np
+    c = wl.centers.mean(0)
+    g = np.linspace(-half, half, n)
+    X, Y = np.meshgrid(g, g)
+    pts = np.stack([c[0] + X.ravel(), c[1] + Y.ravel(), np.full(X.size, c[2] + focal)], -1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E = ctx.fields(x, pts)[0].cpu().numpy()
+    dt = time.perf_counter() - t0
+    k = 2 * np.pi
+    Einc = np.asarray(inc.pol)[None, :] * np.exp(-1j * k * (pts @ np.asarray(inc.khat)))[:, None]
+    I_s = np.sum(np.abs(E) ** 2, 1).reshape(n, n)
+    I_t = np.sum(np.abs(E + Einc) ** 2, 1).reshape(n, n)
+    iy, ix = np.unravel_index(np.argmax(I_t), I_t.shape)
+    row = I_t[iy]
+    above = np.nonzero(row >= 0.5 * row[ix])[0]
+    return {"grid": f"{n}x{n} points, plane z = {focal:g} above the array, +-{half:g} wavelengths about the axis",
+            "time_s": dt, "pairs": int(len(pts) * wl.n_particles),
+            "peak_total_intensity": float(I_t[iy, ix]), "incident_intensity": 1.0,
+            "peak_at_wavelengths": [float(g[ix]), float(g[iy])],
+            "fwhm_x_wavelengths": float((above.max() - above.min() + 1) * (g[1] - g[0])),
+            "peak_scattered_intensity": float(I_s.max())}
+
+
 def lens_gmres(torch, w, mlfma):
     """80 x 80 metalens (32 diameter classes, 384,000 unknowns, FP32 product):
     GMRES(300) time to a 1e-4 true residual from zero and from the learned
@@ -274,7 +302,8 @@ def main():
                     help="c2: 40x40 cylinders (the headline workload); c4 / c5: 80x80 / 200x200 metalens "
                          "(32 classes; extra figures, not the headline line)")
     ap.add_argument("--restart", type=int, default=0, help="GMRES restart (default 100 for c2, 300 otherwise)")
-    ap.add_argument("--max-iter", type=int, default=4000)
+    ap.add_argument("--max-iter", type=int, default=None,
+                    help="GMRES iteration cap (default 4000; 10000 for the 200 x 200 lens)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the tuning file: default tile shapes")
@@ -433,7 +462,8 @@ def main():
         b = ctx.plane_wave_rhs(np.array([i.khat for i in incs]), np.array([i.pol for i in incs]))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xs, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=args.max_iter, restart=restart)
+        max_iter = args.max_iter or (10000 if args.workload == "c5" else 4000)
+        xs, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=max_iter, restart=restart)
         torch.cuda.synchronize()
         out["gmres"] = {"time_to_1e-4_s": time.perf_counter() - t0,
                         "iterations": max(s_["iterations"] for s_ in st),
@@ -443,12 +473,15 @@ def main():
                         "reorth": st[0]["reorth"], "cycles": st[0]["cycles"], "krylov_basis": "fp64"}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xs, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=args.max_iter, restart=restart, fp32_basis=True)
+        xs, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=max_iter, restart=restart, fp32_basis=True)
         torch.cuda.synchronize()
         out["gmres_fp32_basis"] = {"time_to_1e-4_s": time.perf_counter() - t0,
                                    "iterations": max(s_["iterations"] for s_ in st),
                                    "true_rel_res": max(s_["true_rel_res"] for s_ in st),
                                    "converged": all(s_["converged"] for s_ in st), "restart": restart}
+        if args.workload in ("c4", "c5"):
+            out["focal_field"] = focal_field(ctx, wl, xs[:1].contiguous(), incs[0], 20.0 if args.workload == "c4" else 50.0,
+                                             torch)
     if not args.no_gmres and not args.no_lens and headline:
         out["gmres_lens"] = lens_gmres(torch, w, mlfma)
     if cpu is not None:

@@ -240,6 +240,23 @@ typedef struct {
 int mlfma_set_tuning(mlfma_ctx* ctx, const mlfma_tuning* t);
 int mlfma_get_tuning(mlfma_ctx* ctx, mlfma_tuning* t);
 
+/* Scattered electric field of the currents x at observation points (the
+ * near/focal fields of Sec. V): E(r) = sum_p E_p(r) with each particle's
+ * field expanded about its centre c_p, from its leaf radiation pattern U_p
+ * (eq. kspace_Rap, the product's projection stage) and the translation
+ * operator of eq. translation_fun taken to the point itself:
+ *   E(r) = -jk sum_p sum_s w_s T_L(khat_s, r - c_p) (U_th,p(s) th_s + U_ph,p(s) ph_s)
+ * over the leaf sphere samples s.  Exact to the leaf level's truncation for
+ * any point outside the particle's circumscribing sphere.
+ *  x_dev: device [R][P][2][N] currents in the context precision;
+ *  points: host FP64 [n_points][3]; each must lie farther than half a leaf-
+ *  box diagonal from every particle centre (EINVAL otherwise);
+ *  E_dev: device [R][n_points][3] complex in the context precision.
+ *  Needs at least one far level and a leaf sphere of at most 256 samples
+ *  (L_leaf <= 11).  Returns after E_dev is written (synchronises stream). */
+int mlfma_fields(mlfma_ctx* ctx, const void* x_dev, int32_t R, int32_t n_points, const double* points, void* E_dev,
+                 void* stream);
+
 /* Per-kernel timing: while enabled, every kernel launch of mlfma_matvec is
  * bracketed by HIP events recorded on the launch stream.  Enabling clears
  * the accumulated table. */

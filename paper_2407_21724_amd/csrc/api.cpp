@@ -163,6 +163,7 @@ int do_prepare(mlfma_ctx* ctx) {
   }
   Upload u;
   u.precision = ctx->tp.precision;
+  u.k = kK0;
   u.N = N;
   u.n = n;
   u.P = ctx->P;
@@ -592,6 +593,39 @@ int mlfma_matvec_parts(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R
 
 int mlfma_matvec(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream) {
   return mlfma_matvec_parts(ctx, x_dev, y_dev, R, MLFMA_PART_ALL, stream);
+}
+
+int mlfma_fields(mlfma_ctx* ctx, const void* x_dev, int32_t R, int32_t n_points, const double* points, void* E_dev,
+                 void* stream) {
+  if (!ctx) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    if (!x_dev || !E_dev || R < 1 || n_points < 0 || (n_points > 0 && !points) || x_dev == E_dev)
+      return fail(ctx, MLFMA_EINVAL, "fields arguments");
+    if ((uintptr_t)x_dev & 15) return fail(ctx, MLFMA_EINVAL, "x must be 16-byte aligned");
+    for (int i = 0; i < 3 * n_points; ++i)
+      if (!std::isfinite(points[i])) return fail(ctx, MLFMA_EINVAL, "non-finite observation point");
+    if (int rc = do_prepare(ctx)) return rc;
+    // every point farther from every centre than half a leaf-box diagonal
+    // (the expansion of a particle's field about its centre holds outside
+    // the sphere that circumscribes it): only the sites next to a point in
+    // the array plane can be that close
+    const double s = ctx->tp.leaf_size, rmin = 0.5 * std::sqrt(2.0) * s;
+    for (int i = 0; i < n_points; ++i) {
+      const V3 q{points[3 * i], points[3 * i + 1], points[3 * i + 2]};
+      if (std::fabs(q.z - ctx->origin.z) > rmin) continue;
+      const long cx = std::lround((q.x - ctx->origin.x) / s), cy = std::lround((q.y - ctx->origin.y) / s);
+      for (long jy = cy - 1; jy <= cy + 1; ++jy)
+        for (long jx = cx - 1; jx <= cx + 1; ++jx) {
+          if (jx < 0 || jy < 0 || jx >= ctx->nx || jy >= ctx->ny) continue;
+          const int p = ctx->part_of_box[(size_t)jy * ctx->nx + jx];
+          if (p >= 0 && norm(q - ctx->centers[p]) <= rmin)
+            return fail(ctx, MLFMA_EINVAL, "observation point within half a leaf-box diagonal of a particle");
+        }
+    }
+    std::string err;
+    int rc = ctx->eng->fields(x_dev, R, n_points, points, E_dev, stream, err);
+    return rc ? fail(ctx, rc, err) : MLFMA_OK;
+  });
 }
 
 int mlfma_precondition(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream) {

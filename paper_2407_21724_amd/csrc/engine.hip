@@ -1053,6 +1053,153 @@ __global__ __launch_bounds__(kBlock) void k_translate_tiled(TrLevels<T> L, int R
   }
 }
 
+// ----------------------------------------------------------------- fields --
+// Scattered E at observation points from the leaf patterns U_p (the
+// projection of x): the far interaction of the product with the observation
+// point as a receiving box of zero size,
+//   E(r) = -jk sum_p sum_s w_s T_L(khat_s, r - c_p) (U_th,p(s) th_s + U_ph,p(s) ph_s),
+// valid where r is farther from c_p than the particle's circumscribed
+// radius.  Block = kFldPts points x one RHS; thread = one sample s of the
+// leaf sphere (K <= kBlock).  Per chunk of kFldPar particles the block
+// stages, for every (point, particle) pair, the unit vector and the Hankel
+// coefficients -jk/(16 pi^2) (-j)^l (2l+1) h_l^(2)(k|D|) (FP64 recurrence,
+// stored FP32); each thread then sums its sample's Legendre series.
+constexpr int kFldPts = 8, kFldPar = 32, kFldMaxL = 16;
+static_assert(kFldPts * kFldPar == kBlock, "one (point, particle) pair per thread in the staging");
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fields(int P, int K, int L, double k, const double* __restrict__ centers,
+                                                    const int* __restrict__ box_of, int nb0,
+                                                    const C2<T>* __restrict__ S0, const float* __restrict__ tab,
+                                                    int npts, const double* __restrict__ pts, C2<T>* __restrict__ E) {
+  __shared__ float2 cl[kFldPts * kFldPar][kFldMaxL + 1];
+  __shared__ float dh[kFldPts * kFldPar][3];
+  __shared__ float2 red[kBlock / 64][kFldPts * 3];
+  const int r = blockIdx.y, pt0 = blockIdx.x * kFldPts;
+  const int s = threadIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool live = s < K;
+  float ks[3] = {0, 0, 0};
+  if (live)
+    for (int c = 0; c < 3; ++c) ks[c] = tab[s * 10 + c];
+  C2<float> acc[kFldPts][2];  // per point: sums of T U_th and T U_ph
+#pragma unroll
+  for (int q = 0; q < kFldPts; ++q) acc[q][0] = acc[q][1] = C2<float>{0.f, 0.f};
+  const C2<T>* __restrict__ Sr = S0 + (size_t)r * nb0 * 2 * K;
+  for (int pc = 0; pc < P; pc += kFldPar) {
+    __syncthreads();  // the previous chunk's coefficients are consumed
+    {
+      const int q = threadIdx.x / kFldPar, j = threadIdx.x % kFldPar;  // kBlock = kFldPts * kFldPar
+      const int p = pc + j, pt = pt0 + q;
+      if (p < P && pt < npts) {
+        const double dx = pts[3 * pt] - centers[3 * p], dy = pts[3 * pt + 1] - centers[3 * p + 1],
+                     dz = pts[3 * pt + 2] - centers[3 * p + 2];
+        const double D = sqrt(dx * dx + dy * dy + dz * dz), x = k * D;
+        dh[threadIdx.x][0] = (float)(dx / D);
+        dh[threadIdx.x][1] = (float)(dy / D);
+        dh[threadIdx.x][2] = (float)(dz / D);
+        // h_0 = j e^{-jx}/x, h_1 = e^{-jx}(j/x^2 - 1/x), h_{l+1} = (2l+1)/x h_l - h_{l-1}
+        const double cx = cos(x), sx = sin(x);  // e^{-jx} = cx - j sx
+        double h0r = sx / x, h0i = cx / x;
+        double h1r = sx / (x * x) - cx / x, h1i = cx / (x * x) + sx / x;
+        const double pr = 0.0, pi = -k / (16.0 * 3.14159265358979323846 * 3.14159265358979323846);  // -jk/(16 pi^2)
+        for (int l = 0; l <= L; ++l) {
+          double hr, hi;
+          if (l == 0) {
+            hr = h0r;
+            hi = h0i;
+          } else if (l == 1) {
+            hr = h1r;
+            hi = h1i;
+          } else {
+            hr = (2.0 * l - 1.0) / x * h1r - h0r;
+            hi = (2.0 * l - 1.0) / x * h1i - h0i;
+            h0r = h1r;
+            h0i = h1i;
+            h1r = hr;
+            h1i = hi;
+          }
+          // (-j)^l (2l+1) h_l, times the prefactor
+          double ar = (2.0 * l + 1.0) * hr, ai = (2.0 * l + 1.0) * hi, t;
+          switch (l & 3) {
+            case 1: t = ar; ar = ai; ai = -t; break;   // times -j
+            case 2: ar = -ar; ai = -ai; break;
+            case 3: t = ar; ar = -ai; ai = t; break;   // times +j
+            default: break;
+          }
+          cl[threadIdx.x][l] = make_float2((float)(pr * ar - pi * ai), (float)(pr * ai + pi * ar));
+        }
+      } else {
+        dh[threadIdx.x][0] = dh[threadIdx.x][1] = dh[threadIdx.x][2] = 0.f;
+        for (int l = 0; l <= L; ++l) cl[threadIdx.x][l] = make_float2(0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    if (!live) continue;
+    const int nj = min(kFldPar, P - pc);
+    for (int j = 0; j < nj; ++j) {
+      const int p = pc + j;
+      const C2<T>* Up = Sr + (size_t)box_of[p] * 2 * K;
+      const C2<float> ut{(float)Up[s].x, (float)Up[s].y}, up{(float)Up[K + s].x, (float)Up[K + s].y};
+#pragma unroll
+      for (int q = 0; q < kFldPts; ++q) {
+        const int e = q * kFldPar + j;
+        const float mu = ks[0] * dh[e][0] + ks[1] * dh[e][1] + ks[2] * dh[e][2];
+        // T = sum_l c_l P_l(mu) by the Legendre recurrence
+        float p0 = 1.f, p1 = mu;
+        float2 c = cl[e][0];
+        C2<float> tt{c.x, c.y};
+        c = cl[e][1];
+        tt.x = fmadd(c.x, p1, tt.x);
+        tt.y = fmadd(c.y, p1, tt.y);
+        for (int l = 1; l < L; ++l) {
+          const float p2 = ((2.f * l + 1.f) * mu * p1 - (float)l * p0) / (float)(l + 1);
+          c = cl[e][l + 1];
+          tt.x = fmadd(c.x, p2, tt.x);
+          tt.y = fmadd(c.y, p2, tt.y);
+          p0 = p1;
+          p1 = p2;
+        }
+        cfma(acc[q][0], tt, ut);
+        cfma(acc[q][1], tt, up);
+      }
+    }
+  }
+  // E += -jk w_s (A th_s + B ph_s), summed over the samples (threads)
+  float th[3] = {0, 0, 0}, ph[3] = {0, 0, 0}, ws = 0;
+  if (live) {
+    for (int c = 0; c < 3; ++c) {
+      th[c] = tab[s * 10 + 3 + c];
+      ph[c] = tab[s * 10 + 6 + c];
+    }
+    ws = tab[s * 10 + 9];
+  }
+  const float kf = (float)k;
+#pragma unroll
+  for (int q = 0; q < kFldPts; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // v = A th_c + B ph_c, times -jk w_s
+      const float vx = acc[q][0].x * th[c] + acc[q][1].x * ph[c], vy = acc[q][0].y * th[c] + acc[q][1].y * ph[c];
+      float ox = kf * ws * vy, oy = -kf * ws * vx;
+      for (int o = 32; o > 0; o >>= 1) {
+        ox += __shfl_xor(ox, o);
+        oy += __shfl_xor(oy, o);
+      }
+      if (lane == 0) red[wave][q * 3 + c] = make_float2(ox, oy);
+    }
+  __syncthreads();
+  if (threadIdx.x < kFldPts * 3) {
+    const int q = threadIdx.x / 3, c = threadIdx.x % 3, pt = pt0 + q;
+    if (pt < npts) {
+      float2 o = make_float2(0.f, 0.f);
+      for (int w = 0; w < kBlock / 64; ++w) {
+        o.x += red[w][threadIdx.x].x;
+        o.y += red[w][threadIdx.x].y;
+      }
+      E[((size_t)r * npts + pt) * 3 + c] = C2<T>{(T)o.x, (T)o.y};
+    }
+  }
+}
+
 // -------------------------------------------------------------------- rhs --
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rhs(int n, int P, int R, const C2<T>* __restrict__ pat,
@@ -1535,6 +1682,33 @@ class EngineT final : public Engine {
     nx0_ = u.nx0;
     ny0_ = u.ny0;
     if (int rc = put_i(box_of_, u.box_of, err)) return rc;
+    // field evaluation: particle centres, and the leaf sphere's directions,
+    // unit vectors and weights [K0][khat, th_hat, ph_hat, w]
+    fld_k_ = u.k;
+    fld_L_ = ntl_ > 0 ? tr.lv[0].L : 0;
+    {
+      std::vector<double> cen((size_t)P_ * 3);
+      for (int p = 0; p < P_; ++p) {
+        cen[3 * p] = u.centers[p].x;
+        cen[3 * p + 1] = u.centers[p].y;
+        cen[3 * p + 2] = u.centers[p].z;
+      }
+      if (int rc = put_raw(fld_cen_, cen.data(), cen.size(), err)) return rc;
+      if (ntl_ > 0) {
+        const LevelGrid& g = tr.lv[0];
+        std::vector<float> tab((size_t)g.K * 10);
+        for (int s = 0; s < g.K; ++s) {
+          const V3 v[3] = {g.khat[s], g.th_hat[s], g.ph_hat[s]};
+          for (int c = 0; c < 3; ++c) {
+            tab[(size_t)s * 10 + 3 * c] = (float)v[c].x;
+            tab[(size_t)s * 10 + 3 * c + 1] = (float)v[c].y;
+            tab[(size_t)s * 10 + 3 * c + 2] = (float)v[c].z;
+          }
+          tab[(size_t)s * 10 + 9] = (float)g.w[s];
+        }
+        if (int rc = put_raw(fld_tab_, tab.data(), tab.size(), err)) return rc;
+      }
+    }
     if (int rc = put_i(class_of_, u.class_of, err)) return rc;
     if (int rc = put_i(order_, u.order, err)) return rc;
     if (int rc = put_i(tile_start_, u.tile_start, err)) return rc;
@@ -2325,6 +2499,44 @@ class EngineT final : public Engine {
     return 0;
   }
 
+  int fields(const void* xv, int R, int npts, const double* points, void* Ev, void* stream,
+             std::string& err) override {
+    if (ntl_ == 0) {
+      err = "fields: the tree has no far level (the leaf patterns are not formed)";
+      return -1;
+    }
+    const Lvl& L0 = lv_[0];
+    if (L0.K > kBlock || fld_L_ > kFldMaxL) {
+      err = "fields: the leaf sphere has more than " + std::to_string(kBlock) + " samples";
+      return -1;
+    }
+    if (npts <= 0) return 0;
+    if (int rc = ensure(R, err)) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const CT* x = reinterpret_cast<const CT*>(xv);
+    // leaf patterns of x, as the projection stage of the product forms them
+    Pending none;
+    if (mfma_) {
+      launch_gemm<2>(none, rt_np_, project_job(x, rt_np_), GemmJob{}, R, st);
+    } else {
+      dim3 grid(ntiles_, (M2_ + kProjBlock - 1) / kProjBlock, R);
+      size_t sh = (size_t)kTP * n_ * sizeof(CT);
+      launch(none, k_project<T, kTP>, grid, dim3(kProjBlock), sh, st, n_, P_, M2_, L0.nx * L0.ny, x,
+             L0.S.template as<CT>(), Rm_.template as<CT>(), rm_off_.template as<int>(), order_.template as<int>(),
+             tile_start_.template as<int>(), tile_count_.template as<int>(), tile_class_.template as<int>(),
+             box_of_.template as<int>());
+    }
+    if ((size_t)npts * 3 * sizeof(double) > fld_pts_.bytes) HIP_TRY(fld_pts_.alloc((size_t)npts * 3 * sizeof(double)));
+    HIP_TRY(hipMemcpyAsync(fld_pts_.p, points, (size_t)npts * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    launch(none, k_fields<T>, dim3((npts + kFldPts - 1) / kFldPts, R), dim3(kBlock), 0u, st, P_, L0.K, fld_L_,
+           fld_k_, fld_cen_.template as<double>(), box_of_.template as<int>(), L0.nx * L0.ny,
+           (const CT*)L0.S.template as<CT>(), fld_tab_.template as<float>(), npts,
+           (const double*)fld_pts_.template as<double>(), reinterpret_cast<CT*>(Ev));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));  // the host point array may be released on return
+    return 0;
+  }
+
   int precondition(const void* xv, void* yv, int R, void* stream, std::string& err) override {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     Pending none;
@@ -2533,6 +2745,9 @@ class EngineT final : public Engine {
   std::vector<Itp> it_;
   const Tree* tree_ = nullptr;
   DevMem box_of_, class_of_, order_, tile_start_, tile_count_, tile_class_;
+  DevMem fld_cen_, fld_tab_, fld_pts_;  // field evaluation: centres, leaf sample table, points
+  double fld_k_ = 0;
+  int fld_L_ = 0;
   DevMem Rm_, Qm_, rm_off_, qm_off_;
   DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;
   bool mfma_ = false, near_uniform_ = false;

@@ -13,6 +13,7 @@ namespace mlfma {
 // Everything the device path needs, assembled on the host in FP64.
 struct Upload {
   int precision = 0;  // 0 = complex float, 1 = complex double, 2 = complex float with BF16-split products
+  double k = 0;       // background wavenumber
   int N = 0, n = 0;   // modes per current, unknowns per particle (2N)
   int P = 0;
   int n_classes = 0;
@@ -65,6 +66,10 @@ class Engine {
                   std::string& err) = 0;
   virtual int gmres(const void* b, void* x, int R, double rtol, int max_iter, int restart, bool use_x0,
                     bool always_reorth, bool fp32_basis, std::vector<GmresResult>& res, void* stream, std::string& err) = 0;
+  // scattered E at n_points observation points (host FP64 [n][3]) from the
+  // leaf patterns of x: E[r][i][3] in the context precision (device)
+  virtual int fields(const void* x, int R, int n_points, const double* points, void* E, void* stream,
+                     std::string& err) = 0;
   virtual long long device_bytes() const = 0;
   // interpolation strip heights per level (0 = default planner); agg_rows
   // indexed by the parent level, dis_rows by the child level

@@ -65,7 +65,7 @@ class SolveStats(C.Structure):
 EXPORTS = [
     "mlfma_default_params", "mlfma_build_tree", "mlfma_static_modes", "mlfma_set_static_modes",
     "mlfma_prepare", "mlfma_plane_wave_rhs", "mlfma_matvec", "mlfma_matvec_parts",
-    "mlfma_precondition", "mlfma_gmres_solve", "mlfma_info", "mlfma_destroy", "mlfma_last_error",
+    "mlfma_precondition", "mlfma_gmres_solve", "mlfma_fields", "mlfma_info", "mlfma_destroy", "mlfma_last_error",
     "mlfma_debug_near_block", "mlfma_debug_pair_block_device", "mlfma_debug_leaf_pattern", "mlfma_debug_level_grid",
     "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read", "mlfma_share_setup",
     "mlfma_mlp_create", "mlfma_mlp_destroy", "mlfma_mlp_last_error", "mlfma_mlp_num_params",
@@ -92,6 +92,7 @@ def load_library(path: str = _LIB_PATH):
         "mlfma_matvec": (C.c_int, [ctxp, vp, vp, C.c_int32, vp]),
         "mlfma_matvec_parts": (C.c_int, [ctxp, vp, vp, C.c_int32, C.c_int32, vp]),
         "mlfma_precondition": (C.c_int, [ctxp, vp, vp, C.c_int32, vp]),
+        "mlfma_fields": (C.c_int, [ctxp, vp, C.c_int32, C.c_int32, dp, vp, vp]),
         "mlfma_gmres_solve": (C.c_int, [ctxp, vp, vp, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(SolveStats), vp]),
         "mlfma_info": (C.c_int, [ctxp, C.POINTER(Info)]),
@@ -325,6 +326,19 @@ class Context:
             out = torch.empty_like(x)
         self._check(lib().mlfma_precondition(self._h, self._dev(x, R), self._dev(out, R), R, _stream_ptr(stream)),
                     "precondition")
+        return out
+
+    def fields(self, x, points, stream=None):
+        """Scattered E at host points [n][3] from currents x [R][P][2N]
+        (mlfma_fields): device tensor [R][n][3] in the context dtype."""
+        import torch
+        R = x.shape[0]
+        pts = np.ascontiguousarray(np.atleast_2d(points), np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be [n][3]")
+        out = torch.empty((R, len(pts), 3), dtype=self.dtype, device=x.device)
+        self._check(lib().mlfma_fields(self._h, self._dev(x, R), R, len(pts), _dptr(pts), out.data_ptr(),
+                                       _stream_ptr(stream)), "fields")
         return out
 
     def gmres_solve(self, b, x=None, rtol=1e-4, max_iter=1000, restart=100, use_x0=False, always_reorth=False,
