@@ -44,21 +44,12 @@ KERNELS = [
 ]
 
 
-def gemm_waves(var):
-    """Waves per block of the GEMM launches: the engine's rule (4, 8 or 16
-    from the environment variable, default 8)."""
-    v = os.environ.get(var)
-    w = int(v) if v and v.lstrip("-").isdigit() else 8
-    return w if w in (4, 16) else 8
-
-
 def kernel_of(stage, gemm_rows=(4, 4)):
     """Kernel symbol and roofline bound of a product stage; the GEMM symbols
-    carry the row tiles and the waves per block the context runs with."""
+    carry the row tiles the context runs with (8 waves per block)."""
     rn, rr = gemm_rows
-    wn, wr = gemm_waves("MLFMA_GEMM_WAVES_NP"), gemm_waves("MLFMA_GEMM_WAVES_RECV")
-    gemm = {"near+project": f"k_gemm_stream<{rn}, 1, 0, {wn}>", "near": f"k_gemm_stream<{rn}, 1, 1, {wn}>",
-            "project": f"k_gemm_stream<{rn}, 1, 2, {wn}>", "receive": f"k_gemm_stream<{rr}, 1, 3, {wr}>"}
+    gemm = {"near+project": f"k_gemm_stream<{rn}, 1, 0, 8>", "near": f"k_gemm_stream<{rn}, 1, 1, 8>",
+            "project": f"k_gemm_stream<{rn}, 1, 2, 8>", "receive": f"k_gemm_stream<{rr}, 1, 3, 8>"}
     if stage in gemm:
         return gemm[stage], "mfma"
     for prefix, sym, bound in KERNELS:

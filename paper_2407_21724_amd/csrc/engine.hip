@@ -212,6 +212,7 @@ struct GemmJob {
 };
 
 constexpr int kMaxSeg = 9;  // segments of a gathered B column (the 3 x 3 neighbourhood)
+constexpr int kGemmW = 8;   // waves per block of the FP32 GEMM launches
 // blocks of a job: one per tile, or one per W tiles when every wave takes its own
 __host__ __device__ inline int gemm_blocks(const GemmJob& j, int W) { return j.wtile ? (j.tiles + W - 1) / W : j.tiles; }
 template <int RT, int CT, int Tag, int W>
@@ -234,7 +235,8 @@ __global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) 
   const int* __restrict__ ccol = second ? j1.ccol : j0.ccol;
   const int* __restrict__ a_off = second ? j1.a_off : j0.a_off;
   const int tm = t % tiles_m, tn = t / tiles_m;
-  const float* __restrict__ A = (second ? j1.A : j0.A) + (a_off ? a_off[tn] : 0);
+  // a_off has one entry per 16-column tile; the CT tiles of a block share it
+  const float* __restrict__ A = (second ? j1.A : j0.A) + (a_off ? a_off[tn * CT] : 0);
   const int m0 = tm * 16 * RT, n0 = tn * 16 * CT, r = blockIdx.z;
   const int i = lane & 15, kq = lane >> 4;
   const float* __restrict__ Bb = (second ? j1.B : j0.B) + (size_t)r * (second ? j1.sB : j0.sB);
@@ -2334,7 +2336,7 @@ class EngineT final : public Engine {
   // rt: 16-row MFMA tiles per block (1, 2 or 4; the jobs' tiles_m must use it)
   template <int Tag>
   void launch_gemm(Pending& pr, int rt, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
-    const int w = bf16_ ? 4 : Tag == 3 ? gw_recv_ : gw_np_;  // waves per block
+    const int w = bf16_ ? 4 : kGemmW;  // waves per block
     const int nt = gemm_blocks(j0, w) + gemm_blocks(j1, w);
     const dim3 grid(j0.xcd ? xcd_grid(nt) : nt, 1, R);
     if (bf16_) {
@@ -2346,28 +2348,13 @@ class EngineT final : public Engine {
         launch(pr, k_gemm_bf16x3<4, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
       return;
     }
-    if (w == 16) {
-      if (rt == 1)
-        launch(pr, k_gemm_stream<1, 1, Tag, 16>, grid, dim3(1024), 0u, st, j0, j1);
-      else if (rt == 2)
-        launch(pr, k_gemm_stream<2, 1, Tag, 16>, grid, dim3(1024), 0u, st, j0, j1);
-      else
-        launch(pr, k_gemm_stream<4, 1, Tag, 16>, grid, dim3(1024), 0u, st, j0, j1);
-    } else if (w == 8) {
-      if (rt == 1)
-        launch(pr, k_gemm_stream<1, 1, Tag, 8>, grid, dim3(512), 0u, st, j0, j1);
-      else if (rt == 2)
-        launch(pr, k_gemm_stream<2, 1, Tag, 8>, grid, dim3(512), 0u, st, j0, j1);
-      else
-        launch(pr, k_gemm_stream<4, 1, Tag, 8>, grid, dim3(512), 0u, st, j0, j1);
-    } else {
-      if (rt == 1)
-        launch(pr, k_gemm_stream<1, 1, Tag, 4>, grid, dim3(kBlock), 0u, st, j0, j1);
-      else if (rt == 2)
-        launch(pr, k_gemm_stream<2, 1, Tag, 4>, grid, dim3(kBlock), 0u, st, j0, j1);
-      else
-        launch(pr, k_gemm_stream<4, 1, Tag, 4>, grid, dim3(kBlock), 0u, st, j0, j1);
-    }
+    const dim3 blk(64 * kGemmW);
+    if (rt == 1)
+      launch(pr, k_gemm_stream<1, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+    else if (rt == 2)
+      launch(pr, k_gemm_stream<2, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+    else
+      launch(pr, k_gemm_stream<4, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
   }
 
   // One product y = Z x: near-field apply and leaf projection (one launch on
@@ -2753,14 +2740,6 @@ class EngineT final : public Engine {
   bool mfma_ = false, near_uniform_ = false;
   // test switch: every disaggregation takes the two-pass path
   bool force_two_pass_ = std::getenv("MLFMA_DIS_TWO_PASS") != nullptr;
-  // waves per block of the near/projection and of the receive GEMM launches
-  static int gemm_waves(const char* var) {  // 4, 8 or 16 (default 8)
-    const char* e = std::getenv(var);
-    const int w = e ? std::atoi(e) : 8;
-    return w == 4 || w == 16 ? w : 8;
-  }
-  int gw_np_ = gemm_waves("MLFMA_GEMM_WAVES_NP");
-  int gw_recv_ = gemm_waves("MLFMA_GEMM_WAVES_RECV");
   // translation kernel forced on every level: 0 = gathered lists, 1/2/3 = LDS
   // tiles of 4x4 / 8x4 / 8x8 boxes; -1 = per level (tiles of 4x4 on grids of
   // at least 8 x 8 boxes)
