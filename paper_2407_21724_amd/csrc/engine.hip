@@ -1244,32 +1244,38 @@ __device__ inline double wave_sum(double v) {
 
 constexpr int kDotE = 4;  // vector elements per lane and sweep of k_dots
 constexpr int kDotMaxBlocks = 512;
+constexpr int kDotMinBlocks = 2048;  // blocks k_dots aims for, over stretches and vector groups
 
 // Block partial sums of the inner products conj(V_i) . w (slots i < nv) and,
 // when want_norm, of |w|^2 (slot nv), in one sweep over the basis (stored
-// in VB precision, products accumulated in FP64).  The four
-// waves of a block share one stretch of w and take the slots round-robin;
-// partial[((r * ldp) + slot) * gridDim.x + blockIdx.x].  RHS r is skipped
-// where gate[r] == 0.
+// in VB precision, products accumulated in FP64).  Grid: stretches of w x
+// groups of gsz basis vectors x RHS (the norm goes with group 0), so that a
+// short basis still fills the chip.  The four waves of a block share one
+// stretch of w; partial[((r * ldp) + slot) * gridDim.x + blockIdx.x].  RHS r
+// is skipped where gate[r] == 0.
 template <typename VB>
-__global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t Nt, size_t vstride,
+constexpr int dot_vu() { return sizeof(VB) == 4 ? 8 : 4; }  // basis vectors loaded per step
+template <typename VB>
+__global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, int gsz, size_t Nt, size_t vstride,
                                                   const C2<VB>* __restrict__ V, const Z* __restrict__ w,
                                                   Z* __restrict__ partial, int ldp, const int* __restrict__ gate) {
-  const int r = blockIdx.y;
+  const int r = blockIdx.z;
   if (gate && !gate[r]) return;
-  // per wave: E elements per lane of w held in registers while every
-  // basis vector streams past them once; per-vector wave sums accumulate in
-  // LDS red[vector][wave] (dynamic, (nv + want_norm) * kBlock / 64 entries)
+  // per wave: E elements per lane of w held in registers while the group's
+  // basis vectors stream past them once; per-vector wave sums accumulate in
+  // LDS red[vector][wave] (dynamic, (gsz + want_norm) * kBlock / 64 entries)
   extern __shared__ unsigned char smem_raw[];
   Z* red = reinterpret_cast<Z*>(smem_raw);
   constexpr int NW = kBlock / 64;
-  constexpr int VU = sizeof(VB) == 4 ? 8 : 4, E = kDotE;  // basis vectors per group, elements per lane
-  const int ns = nv + want_norm, nblk = gridDim.x, blk = blockIdx.x;
+  constexpr int VU = dot_vu<VB>(), E = kDotE;  // basis vectors per step, elements per lane
+  const int v0 = blockIdx.y * gsz;
+  const int cnt = min(gsz, nv - v0), norm = want_norm && blockIdx.y == 0;
+  const int ns = cnt + norm, nblk = gridDim.x, blk = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < ns * NW; i += kBlock) red[i] = Z{0, 0};
   __syncthreads();
   const Z* wr = w + (size_t)r * Nt;
-  const C2<VB>* Vr = V + (size_t)r * Nt;
+  const C2<VB>* Vr = V + (size_t)r * Nt + (size_t)v0 * vstride;
   const size_t sweep = (size_t)nblk * NW * 64 * E;
   for (size_t base = ((size_t)blk * NW + wave) * 64 * E; base < Nt; base += sweep) {
     Z wv[E];
@@ -1278,14 +1284,14 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
       const size_t k = base + (size_t)e * 64 + lane;
       wv[e] = k < Nt ? wr[k] : Z{0, 0};
     }
-    for (int i0 = 0; i0 < nv; i0 += VU) {
+    for (int i0 = 0; i0 < cnt; i0 += VU) {
       C2<VB> v[VU][E];
 #pragma unroll
       for (int u = 0; u < VU; ++u)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const size_t k = base + (size_t)e * 64 + lane;
-          v[u][e] = (i0 + u < nv && k < Nt) ? Vr[(size_t)(i0 + u) * vstride + k] : C2<VB>{0, 0};
+          v[u][e] = (i0 + u < cnt && k < Nt) ? Vr[(size_t)(i0 + u) * vstride + k] : C2<VB>{0, 0};
         }
 #pragma unroll
       for (int u = 0; u < VU; ++u) {
@@ -1298,19 +1304,19 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
         }
         ax = wave_sum(ax);
         ay = wave_sum(ay);
-        if (lane == 0 && i0 + u < nv) {
+        if (lane == 0 && i0 + u < cnt) {
           Z& o = red[(i0 + u) * NW + wave];
           o.x += ax;
           o.y += ay;
         }
       }
     }
-    if (want_norm) {
+    if (norm) {
       double nn = 0;
 #pragma unroll
       for (int e = 0; e < E; ++e) nn += wv[e].x * wv[e].x + wv[e].y * wv[e].y;
       nn = wave_sum(nn);
-      if (lane == 0) red[nv * NW + wave].x += nn;
+      if (lane == 0) red[cnt * NW + wave].x += nn;
     }
   }
   __syncthreads();
@@ -1321,7 +1327,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, size_t N
       o.x += red[i * NW + q].x;
       o.y += red[i * NW + q].y;
     }
-    partial[((size_t)r * ldp + i) * nblk + blk] = o;
+    partial[((size_t)r * ldp + (i < cnt ? v0 + i : nv)) * nblk + blk] = o;
   }
 }
 
@@ -2831,9 +2837,16 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   const dim3 blk(kBlock);
   const dim3 gv(grid1d(Nt) > 1024 ? 1024 : grid1d(Nt), R);
   // h[r][0..nv) = V_i^H w_r, and h[r][nv] = |w_r|^2 when want_norm
+  // groups of basis vectors: enough blocks for kDotMinBlocks, each group a
+  // multiple of the vectors one step loads
   auto dots = [&](int nv, int want_norm, const Z* ww, Z* out, int ldo, const int* g) {
-    hipLaunchKernelGGL(k_dots<VB>, dim3(nblk_d, R), blk, (uint32_t)((nv + want_norm) * (kBlock / 64) * sizeof(Z)), st,
-                       nv, want_norm, Nt, vstride, (const CV*)V, ww, part, ld, g);
+    constexpr int VU = dot_vu<VB>();
+    const int steps = (nv + VU - 1) / VU;
+    const int want_g = std::max(1, std::min(steps, (kDotMinBlocks + nblk_d - 1) / nblk_d));
+    const int gsz = VU * ((steps + want_g - 1) / want_g);
+    const int ng = nv > 0 ? (nv + gsz - 1) / gsz : 1;
+    hipLaunchKernelGGL(k_dots<VB>, dim3(nblk_d, ng, R), blk, (uint32_t)((gsz + want_norm) * (kBlock / 64) * sizeof(Z)),
+                       st, nv, want_norm, gsz, Nt, vstride, (const CV*)V, ww, part, ld, g);
     hipLaunchKernelGGL(k_reduce, dim3(nv + want_norm, R), blk, 0, st, nblk_d, part, ld, out, ldo, g);
   };
   // ww -= sum_i V_i c_i; nout[r] = |ww_r|^2
