@@ -216,7 +216,12 @@ int mlfma_precondition(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R
  *  residual; max_iter: total matrix-vector products per RHS; restart: Krylov
  *  dimension m.  stats [R] (may be NULL).  Synchronous: returns after the
  *  solution is in x_dev.  Returns MLFMA_NOT_CONVERGED (1) if some RHS did
- *  not reach rtol within max_iter. */
+ *  not reach rtol within max_iter.
+ *  Kernels are launched one by one; with the environment variable
+ *  MLFMA_GMRES_GRAPHS set when the context is prepared, each product and
+ *  each Arnoldi step is instead one replayed HIP graph (the same results
+ *  bit for bit; slower on ROCm 7, where each graph boundary idles the GPU
+ *  for a few microseconds). */
 int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R, double rtol,
                       int32_t max_iter, int32_t restart, int32_t flags, mlfma_solve_stats* stats,
                       void* stream);

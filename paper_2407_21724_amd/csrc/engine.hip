@@ -1252,15 +1252,29 @@ constexpr int kDotMinBlocks = 2048;  // blocks k_dots aims for, over stretches a
 // groups of gsz basis vectors x RHS (the norm goes with group 0), so that a
 // short basis still fills the chip.  The four waves of a block share one
 // stretch of w; partial[((r * ldp) + slot) * gridDim.x + blockIdx.x].  RHS r
-// is skipped where gate[r] == 0.
+// is skipped where gate[r] == 0.  With jd, the basis has *jd + 1 vectors
+// (the Arnoldi step index on the device) and the group size is derived
+// from it as the host derives it (dot_group); groups past the basis exit.
 template <typename VB>
 constexpr int dot_vu() { return sizeof(VB) == 4 ? 8 : 4; }  // basis vectors loaded per step
+// vectors per group for nv basis vectors: at most gcap groups (the number
+// of w stretches that makes kDotMinBlocks blocks), each a multiple of VU
+__host__ __device__ inline int dot_group(int nv, int VU, int gcap) {
+  const int steps = (nv + VU - 1) / VU;
+  const int want = steps < gcap ? (steps > 1 ? steps : 1) : (gcap > 1 ? gcap : 1);
+  return VU * ((steps + want - 1) / want);
+}
 template <typename VB>
-__global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, int gsz, size_t Nt, size_t vstride,
+__global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, int gsz, int gcap, size_t Nt, size_t vstride,
                                                   const C2<VB>* __restrict__ V, const Z* __restrict__ w,
-                                                  Z* __restrict__ partial, int ldp, const int* __restrict__ gate) {
+                                                  Z* __restrict__ partial, int ldp, const int* __restrict__ gate,
+                                                  const int* __restrict__ jd) {
   const int r = blockIdx.z;
   if (gate && !gate[r]) return;
+  if (jd) {
+    nv = *jd + 1;
+    gsz = dot_group(nv, dot_vu<VB>(), gcap);
+  }
   // per wave: E elements per lane of w held in registers while the group's
   // basis vectors stream past them once; per-vector wave sums accumulate in
   // LDS red[vector][wave] (dynamic, (gsz + want_norm) * kBlock / 64 entries)
@@ -1270,6 +1284,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, int gsz,
   constexpr int VU = dot_vu<VB>(), E = kDotE;  // basis vectors per step, elements per lane
   const int v0 = blockIdx.y * gsz;
   const int cnt = min(gsz, nv - v0), norm = want_norm && blockIdx.y == 0;
+  if (cnt <= 0 && !norm) return;
   const int ns = cnt + norm, nblk = gridDim.x, blk = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < ns * NW; i += kBlock) red[i] = Z{0, 0};
@@ -1383,9 +1398,11 @@ __global__ __launch_bounds__(kBlock) void k_guess_apply(size_t Nt, const Z* __re
   }
 }
 __global__ __launch_bounds__(kBlock) void k_reduce(int nblk, const Z* __restrict__ partial, int ldp,
-                                                    Z* __restrict__ out, int ldo, const int* __restrict__ gate) {
+                                                    Z* __restrict__ out, int ldo, const int* __restrict__ gate,
+                                                    const int* __restrict__ jd, int extra) {
   const int s = blockIdx.x, r = blockIdx.y;
   if (gate && !gate[r]) return;
+  if (jd && s >= *jd + 1 + extra) return;  // slots: *jd + 1 dots, then `extra` more
   __shared__ double red[2][kBlock / 64];
   const Z* p = partial + ((size_t)r * ldp + s) * nblk;
   double ax = 0, ay = 0;
@@ -1416,9 +1433,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int nblk, const Z* __restrict
 template <typename VB>
 __global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, size_t vstride, const C2<VB>* __restrict__ V,
                                                            const Z* __restrict__ c, int ldc, Z* __restrict__ w,
-                                                           Z* __restrict__ partial, const int* __restrict__ gate) {
+                                                           Z* __restrict__ partial, const int* __restrict__ gate,
+                                                           const int* __restrict__ jd) {
   const int r = blockIdx.y;
   if (gate && !gate[r]) return;
+  if (jd) nv = *jd + 1;
   __shared__ double red[kBlock / 64];
   constexpr int VU = sizeof(VB) == 4 ? 8 : 4;  // basis vectors loaded together
   const Z* cr = c + (size_t)r * ldc;
@@ -1465,9 +1484,10 @@ __global__ __launch_bounds__(kBlock) void k_subtract_norm(int nv, size_t Nt, siz
 // Gram-Schmidt pass is taken where the first removed more than half of
 // |w|^2, i.e. |w'| < |w| / sqrt(2); always when `always`.
 __global__ void k_dgks_gate(int R, const Z* __restrict__ h1, int ld, int nv, const Z* __restrict__ n1,
-                            int* __restrict__ gate, int always) {
+                            int* __restrict__ gate, int always, const int* __restrict__ jd) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
+  if (jd) nv = *jd + 1;
   gate[r] = (always || n1[r].x < 0.5 * h1[(size_t)r * ld + nv].x) ? 1 : 0;
 }
 
@@ -1476,9 +1496,11 @@ __global__ void k_dgks_gate(int R, const Z* __restrict__ h1, int ld, int nv, con
 __global__ __launch_bounds__(kBlock) void k_arnoldi_col(int nv, int ld, const Z* __restrict__ h1,
                                                          const Z* __restrict__ n1, const Z* __restrict__ h2,
                                                          const Z* __restrict__ n2, const int* __restrict__ gate,
-                                                         Z* __restrict__ col, double* __restrict__ scale) {
+                                                         Z* __restrict__ col, double* __restrict__ scale,
+                                                         const int* __restrict__ jd) {
   const int r = blockIdx.x;
   const int g = gate[r];
+  if (jd) nv = *jd + 1;
   for (int i = threadIdx.x; i < nv; i += kBlock) {
     const Z a = h1[(size_t)r * ld + i];
     const Z b = g ? h2[(size_t)r * ld + i] : Z{0, 0};
@@ -1502,6 +1524,32 @@ __global__ __launch_bounds__(kBlock) void k_scale_real(size_t Nt, const Z* __res
     const Z v = a[(size_t)r * Nt + k];
     out[(size_t)r * Nt + k] = C2<VB>{(VB)(v.x * c), (VB)(v.y * c)};
   }
+}
+
+// The Arnoldi step on the device (*jd = j): V_{j+1} = a * s (as k_scale_real),
+// and its conversion to the product's precision.
+template <typename VB>
+__global__ __launch_bounds__(kBlock) void k_scale_next(size_t Nt, const Z* __restrict__ a, const double* __restrict__ s,
+                                                        C2<VB>* __restrict__ V, size_t vstride,
+                                                        const int* __restrict__ jd) {
+  const int r = blockIdx.y;
+  const double c = s[r];
+  C2<VB>* __restrict__ out = V + (size_t)(*jd + 1) * vstride;
+  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
+    const Z v = a[(size_t)r * Nt + k];
+    out[(size_t)r * Nt + k] = C2<VB>{(VB)(v.x * c), (VB)(v.y * c)};
+  }
+}
+template <typename VB, typename D>
+__global__ __launch_bounds__(kBlock) void k_convert_next(const C2<VB>* __restrict__ V, size_t vstride,
+                                                          const int* __restrict__ jd, C2<D>* __restrict__ b,
+                                                          size_t cnt) {
+  const C2<VB>* __restrict__ a = V + (size_t)(*jd + 1) * vstride;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
+    b[i] = {(D)a[i].x, (D)a[i].y};
+}
+__global__ void k_set_step(int* __restrict__ jd, int v, int add) {
+  if (threadIdx.x == 0) jd[0] = add ? jd[0] + v : v;
 }
 
 // out += a
@@ -2679,6 +2727,12 @@ class EngineT final : public Engine {
   hipStream_t cap_stream_ = nullptr;
   unsigned long long use_clock_ = 0;
   bool use_graphs_ = std::getenv("MLFMA_NO_GRAPH") == nullptr;
+  // GMRES launches its kernels directly unless MLFMA_GMRES_GRAPHS is set:
+  // then the product and the Arnoldi step are replayed graphs.  Each graph
+  // boundary costs about 8 us of idle GPU on ROCm 7 (the next dispatch
+  // waits for the graph's completion signal), more than the host's launch
+  // time it saves.
+  bool gmres_graphs_ = std::getenv("MLFMA_GMRES_GRAPHS") != nullptr;
 
   static void destroy_entry(GraphEntry& e) {
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
@@ -2767,7 +2821,7 @@ class EngineT final : public Engine {
   long long nnear_ = 0;
   std::vector<long long> pairs_;
   // GMRES workspace
-  DevMem gV_, gw_, gx_, gb_, gtmp_, gtmpT_, gtmpT2_, gpart_, gh_, gh2_, gcol_, gn_, ggate_, gscale_;
+  DevMem gV_, gw_, gx_, gb_, gtmp_, gtmpT_, gtmpT2_, gpart_, gh_, gh2_, gcol_, gn_, ggate_, gscale_, gstep_;
   HostMem hcol_, hy_;
   hipEvent_t col_ev_ = nullptr;
 };
@@ -2813,6 +2867,7 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   HIP_TRY(gcol_.alloc((size_t)R * ld * sizeof(Z)));
   HIP_TRY(gn_.alloc((size_t)2 * R * sizeof(Z)));
   HIP_TRY(ggate_.alloc((size_t)R * sizeof(int)));
+  HIP_TRY(gstep_.alloc(sizeof(int)));
   HIP_TRY(gscale_.alloc((size_t)R * sizeof(double)));
   HIP_TRY(hcol_.alloc((size_t)R * ld * sizeof(Z)));
   HIP_TRY(hy_.alloc((size_t)R * ld * sizeof(Z)));
@@ -2837,38 +2892,87 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   const dim3 blk(kBlock);
   const dim3 gv(grid1d(Nt) > 1024 ? 1024 : grid1d(Nt), R);
   // h[r][0..nv) = V_i^H w_r, and h[r][nv] = |w_r|^2 when want_norm
+  int* jd_dev = gstep_.as<int>();
   // groups of basis vectors: enough blocks for kDotMinBlocks, each group a
-  // multiple of the vectors one step loads
-  auto dots = [&](int nv, int want_norm, const Z* ww, Z* out, int ldo, const int* g) {
+  // multiple of the vectors one step loads.  With jd (graph replay) the
+  // launch is shaped for the longest basis, m vectors, and the kernels read
+  // the basis length from the device.
+  const int gcap = (kDotMinBlocks + nblk_d - 1) / nblk_d;
+  auto dots_on = [&](hipStream_t s, int nv, int want_norm, const Z* ww, Z* out, int ldo, const int* g,
+                     const int* jd) {
     constexpr int VU = dot_vu<VB>();
-    const int steps = (nv + VU - 1) / VU;
-    const int want_g = std::max(1, std::min(steps, (kDotMinBlocks + nblk_d - 1) / nblk_d));
-    const int gsz = VU * ((steps + want_g - 1) / want_g);
-    const int ng = nv > 0 ? (nv + gsz - 1) / gsz : 1;
+    const int nl = jd ? m : nv;
+    int gsz = dot_group(nl, VU, gcap), ng = nl > 0 ? (nl + gsz - 1) / gsz : 1;
+    if (jd)  // every basis length up to m: the largest group and group count
+      for (int n = 1; n <= m; ++n) {
+        const int gn = dot_group(n, VU, gcap);
+        gsz = std::max(gsz, gn);
+        ng = std::max(ng, (n + gn - 1) / gn);
+      }
     hipLaunchKernelGGL(k_dots<VB>, dim3(nblk_d, ng, R), blk, (uint32_t)((gsz + want_norm) * (kBlock / 64) * sizeof(Z)),
-                       st, nv, want_norm, gsz, Nt, vstride, (const CV*)V, ww, part, ld, g);
-    hipLaunchKernelGGL(k_reduce, dim3(nv + want_norm, R), blk, 0, st, nblk_d, part, ld, out, ldo, g);
+                       s, nv, want_norm, gsz, gcap, Nt, vstride, (const CV*)V, ww, part, ld, g, jd);
+    hipLaunchKernelGGL(k_reduce, dim3(nl + want_norm, R), blk, 0, s, nblk_d, part, ld, out, ldo, g, jd, want_norm);
+  };
+  auto dots = [&](int nv, int want_norm, const Z* ww, Z* out, int ldo, const int* g) {
+    dots_on(st, nv, want_norm, ww, out, ldo, g, nullptr);
   };
   // ww -= sum_i V_i c_i; nout[r] = |ww_r|^2
-  auto subtract = [&](int nv, const Z* c, Z* ww, Z* nout, const int* g) {
-    hipLaunchKernelGGL(k_subtract_norm<VB>, dim3(nblk_s, R), blk, 0, st, nv, Nt, vstride, (const CV*)V, c, ld, ww,
-                       part, g);
-    hipLaunchKernelGGL(k_reduce, dim3(1, R), blk, 0, st, nblk_s, part, 1, nout, 1, g);
+  auto subtract_on = [&](hipStream_t s, int nv, const Z* c, Z* ww, Z* nout, const int* g, const int* jd) {
+    hipLaunchKernelGGL(k_subtract_norm<VB>, dim3(nblk_s, R), blk, 0, s, nv, Nt, vstride, (const CV*)V, c, ld, ww,
+                       part, g, jd);
+    hipLaunchKernelGGL(k_reduce, dim3(1, R), blk, 0, s, nblk_s, part, 1, nout, 1, g, nullptr, 0);
+  };
+  // Arnoldi step j on w = A v_j: two Gram-Schmidt passes, the second where
+  // DGKS asks for it; the Hessenberg column to col (and to the host), v_{j+1}
+  // = w / |w|.  With jd: j is read from the device, v_{j+1} is also
+  // converted for the next product into tT, and *jd advances, so that the
+  // same launches (one captured graph) serve every step.
+  auto arnoldi_step = [&](hipStream_t s, int j, const int* jd) -> int {
+    const int nv = j + 1;
+    dots_on(s, nv, 1, w, h1, ld, nullptr, jd);
+    subtract_on(s, nv, h1, w, n1, nullptr, jd);
+    hipLaunchKernelGGL(k_dgks_gate, dim3((R + 63) / 64), dim3(64), 0, s, R, h1, ld, nv, n1, gate,
+                       always_reorth ? 1 : 0, jd);
+    dots_on(s, nv, 0, w, h2, ld, gate, jd);
+    subtract_on(s, nv, h2, w, n2, gate, jd);
+    hipLaunchKernelGGL(k_arnoldi_col, dim3(R), blk, 0, s, nv, ld, h1, n1, h2, n2, gate, col, scale, jd);
+    if (jd)
+      hipLaunchKernelGGL(k_scale_next<VB>, gv, blk, 0, s, Nt, (const Z*)w, (const double*)scale, V, vstride, jd);
+    else
+      hipLaunchKernelGGL(k_scale_real<VB>, gv, blk, 0, s, Nt, (const Z*)w, (const double*)scale,
+                         V + (size_t)(j + 1) * vstride);
+    HIP_TRY(hipMemcpyAsync(hcol, col, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, s));
+    if (jd) {
+      hipLaunchKernelGGL((k_convert_next<VB, T>), dim3(grid1d(tot)), blk, 0, s, (const CV*)V, vstride, jd, tT, tot);
+      hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, jd_dev, 1, 1);
+    }
+    return 0;
   };
   // operator A z = Z (P^-1 z) -> result FP64 in `out`; z is a basis vector
   // (precond) or an FP64 iterate
-  auto apply_A_from = [&](auto* z, Z* out, bool precond) -> int {
-    using S = typename std::remove_const<typename std::remove_pointer<decltype(z)>::type>::type;
-    hipLaunchKernelGGL((k_convert<decltype(S{}.x), T>), dim3(grid1d(tot)), blk, 0, st, (const S*)z, tT, tot);
+  // (A_converted: z already converted into tT)
+  auto apply_A_converted = [&](Z* out, bool precond) -> int {
     const CT* src = tT;
     if (precond) {
       if (int rc = precondition(tT, tT2, R, stream, err)) return rc;
       src = tT2;
     }
     CT* dst = precond ? tT : tT2;
-    if (int rc = matvec(src, dst, R, 3, stream, err)) return rc;
+    if (gmres_graphs_) {
+      if (int rc = matvec(src, dst, R, 3, stream, err)) return rc;
+    } else {
+      const int old_alloc = R_alloc_;
+      if (int rc = ensure(R, err)) return rc;
+      if (R_alloc_ != old_alloc) clear_graphs();
+      if (int rc = enqueue(src, dst, R, 3, st, err)) return rc;
+    }
     hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, dst, out, tot);
     return 0;
+  };
+  auto apply_A_from = [&](auto* z, Z* out, bool precond) -> int {
+    using S = typename std::remove_const<typename std::remove_pointer<decltype(z)>::type>::type;
+    hipLaunchKernelGGL((k_convert<decltype(S{}.x), T>), dim3(grid1d(tot)), blk, 0, st, (const S*)z, tT, tot);
+    return apply_A_converted(out, precond);
   };
   auto apply_A = [&](const Z* z, Z* out, bool precond) -> int { return apply_A_from(z, out, precond); };
   auto norms = [&](const Z* vec, std::vector<double>& out) -> int {
@@ -2900,7 +3004,7 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
     // minimises |b - a A x0|: never worse than a zero start (a = 0), which is
     // what a guess uncorrelated with the solution falls back to
     hipLaunchKernelGGL(k_guess_dots, dim3(nblk_d, R), blk, 0, st, Nt, (const Z*)tmp, (const Z*)b, part);
-    hipLaunchKernelGGL(k_reduce, dim3(2, R), blk, 0, st, nblk_d, (const Z*)part, 2, n1, 2, nullptr);
+    hipLaunchKernelGGL(k_reduce, dim3(2, R), blk, 0, st, nblk_d, (const Z*)part, 2, n1, 2, nullptr, nullptr, 0);
     HIP_TRY(hipMemcpyAsync(hcol, n1, (size_t)2 * R * sizeof(Z), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int r = 0; r < R; ++r) {
@@ -2918,6 +3022,31 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   for (int r = 0; r < R; ++r) {
     if (bnorm[r] == 0.0 || rnorm[r] <= rtol * bnorm[r]) done[r] = 1;
   }
+  // the Arnoldi step as one graph, captured on first use (not while
+  // profiling, nor with graphs switched off)
+  struct ExecGuard {
+    hipGraphExec_t e = nullptr;
+    ~ExecGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+    }
+  } step_graph;
+  const bool graph_steps = use_graphs_ && gmres_graphs_ && !prof_on_;
+  auto capture_step = [&]() -> int {
+    if (!cap_stream_) HIP_TRY(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
+    const int rc = arnoldi_step(cap_stream_, 0, jd_dev);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cap_stream_, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HIP_TRY(ce);
+    const hipError_t ie = hipGraphInstantiate(&step_graph.e, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(ie);
+    return 0;
+  };
   int total_it = 0;
   std::vector<std::vector<cd>> H(R), cs(R), sn(R), g(R);
   std::vector<double> s0(R);
@@ -2941,24 +3070,26 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
     std::vector<char> active(R);
     for (int r = 0; r < R; ++r) active[r] = !done[r];
     if (int rc = apply_A_from((const CV*)V, w, true)) return rc;
+    if (graph_steps) {
+      if (!step_graph.e)
+        if (int rc = capture_step()) return rc;
+      hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, st, jd_dev, 0, 0);
+    }
     for (; j < m && total_it < max_iter; ++j) {
       ++total_it;
       const int nv = j + 1;
-      // w = A v_j: two Gram-Schmidt passes, the second where DGKS asks for it
-      dots(nv, 1, w, h1, ld, nullptr);
-      subtract(nv, h1, w, n1, nullptr);
-      hipLaunchKernelGGL(k_dgks_gate, dim3((R + 63) / 64), dim3(64), 0, st, R, h1, ld, nv, n1, gate,
-                         always_reorth ? 1 : 0);
-      dots(nv, 0, w, h2, ld, gate);
-      subtract(nv, h2, w, n2, gate);
-      hipLaunchKernelGGL(k_arnoldi_col, dim3(R), blk, 0, st, nv, ld, h1, n1, h2, n2, gate, col, scale);
-      hipLaunchKernelGGL(k_scale_real<VB>, gv, blk, 0, st, Nt, (const Z*)w, (const double*)scale,
-                         V + (size_t)(j + 1) * vstride);
-      HIP_TRY(hipMemcpyAsync(hcol, col, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, st));
+      if (graph_steps) {
+        HIP_TRY(hipGraphLaunch(step_graph.e, st));
+      } else if (int rc = arnoldi_step(st, j, nullptr)) {
+        return rc;
+      }
       HIP_TRY(hipEventRecord(col_ev_, st));
       // queue the next product before the host looks at the column
-      if (j + 1 < m && total_it < max_iter)
-        if (int rc = apply_A_from((const CV*)(V + (size_t)(j + 1) * vstride), w, true)) return rc;
+      if (j + 1 < m && total_it < max_iter) {
+        const int rc = graph_steps ? apply_A_converted(w, true)
+                                   : apply_A_from((const CV*)(V + (size_t)(j + 1) * vstride), w, true);
+        if (rc) return rc;
+      }
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipEventSynchronize(col_ev_));
       bool any_active = false;

@@ -177,3 +177,39 @@ def test_fp32_krylov_basis():
     assert s32[0]["true_rel_res"] <= 1e-4
     assert abs(s32[0]["iterations"] - s64[0]["iterations"]) <= 0.1 * s64[0]["iterations"] + 2
     assert rel_err(x32.cpu().numpy(), x64.cpu().numpy()) < 1e-3
+
+
+@pytest.mark.parametrize("fp32_basis", [False, True])
+def test_graph_replayed_arnoldi_steps_match_direct_launches(monkeypatch, fp32_basis):
+    """With MLFMA_GMRES_GRAPHS, the product and the Arnoldi step are replayed
+    captured graphs (the step index read from the device); they give the
+    same iterates, bit for bit, as the default direct launches: several restart cycles, one and then two
+    right-hand sides, with the host's own work and synchronisations between
+    the replays."""
+    wl = w.workload("c2", 12, 12)
+    v, t, e = wl.meshes[0]
+    M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+    res = {}
+    rhs = None
+    for mode in ("graph", "direct"):
+        if mode == "graph":
+            monkeypatch.setenv("MLFMA_GMRES_GRAPHS", "1")
+        else:
+            monkeypatch.delenv("MLFMA_GMRES_GRAPHS", raising=False)
+        ctx = make_ctx(wl, M, mlfma.C64)
+        ctx.prepare()
+        if rhs is None:
+            kh = np.array([i.khat for i in wl.incidences[:2]])
+            pol = np.array([i.pol for i in wl.incidences[:2]])
+            b2 = ctx.plane_wave_rhs(kh, pol)
+            rhs = (b2[:1].contiguous(), b2)
+        out = []
+        for b in rhs:
+            x, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=600, restart=30, fp32_basis=fp32_basis)
+            out.append((x.cpu(), [s["iterations"] for s in st], [s["true_rel_res"] for s in st], rc))
+        res[mode] = out
+    for (xg, ig, rg, cg), (xd, idd, rd, cd) in zip(res["graph"], res["direct"]):
+        note(f"graph-replayed steps (fp32 basis {fp32_basis}): iterations {ig}, true residual {rg}")
+        assert min(ig) > 60  # at least three restart cycles
+        assert ig == idd and rg == rd and cg == cd
+        assert torch.equal(xg, xd)
