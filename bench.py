@@ -451,12 +451,15 @@ def main():
         restart = args.restart or (100 if headline else 300)
         incs = wl.incidences[:R]
         b = ctx.plane_wave_rhs(np.array([i.khat for i in incs]), np.array([i.pol for i in incs]))
+        # a 20-iteration solve first: it allocates the Krylov basis and loads
+        # the GMRES kernels, one-off costs that the timed solve leaves out
+        ctx.gmres_solve(b, rtol=1e-4, max_iter=20, restart=restart)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         max_iter = args.max_iter or (10000 if args.workload == "c5" else 4000)
         xs, st, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=max_iter, restart=restart)
         torch.cuda.synchronize()
-        out["gmres"] = {"time_to_1e-4_s": time.perf_counter() - t0,
+        out["gmres"] = {"time_to_1e-4_s": time.perf_counter() - t0, "after": "a 20-iteration warm-up solve",
                         "iterations": max(s_["iterations"] for s_ in st),
                         "true_rel_res": max(s_["true_rel_res"] for s_ in st),
                         "converged": all(s_["converged"] for s_ in st),
