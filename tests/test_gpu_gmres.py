@@ -213,3 +213,29 @@ def test_graph_replayed_arnoldi_steps_match_direct_launches(monkeypatch, fp32_ba
         assert min(ig) > 60  # at least three restart cycles
         assert ig == idd and rg == rd and cg == cd
         assert torch.equal(xg, xd)
+
+
+def test_c5_full_scale_batched_restarted_gmres():
+    """The full-scale lens (200 x 200 cylinders, 32 classes, 2.4 M unknowns):
+    two incidences in one restarted GMRES (restart 100, 150 steps, so one
+    restart with its true-residual product) take the same steps as each
+    incidence alone, bit for bit, since the batched product and Arnoldi keep
+    every right-hand side separate."""
+    wl = w.workload("c5")
+    M = {}
+    for c in sorted(set(wl.class_id.tolist())):
+        v, t, e = wl.meshes[c]
+        M[c], _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
+    ctx = make_ctx(wl, M, mlfma.C64)
+    kh = np.array([i.khat for i in wl.incidences[:2]])
+    pol = np.array([i.pol for i in wl.incidences[:2]])
+    b = ctx.plane_wave_rhs(kh, pol)
+    x2, st2, _ = ctx.gmres_solve(b, rtol=1e-8, max_iter=150, restart=100)
+    assert [s["iterations"] for s in st2] == [150, 150]
+    for r in range(2):
+        x1, st1, _ = ctx.gmres_solve(b[r:r + 1].contiguous(), rtol=1e-8, max_iter=150, restart=100)
+        note(f"C5 RHS {r}: 150 steps, true residual {st1[0]['true_rel_res']:.3e} alone, "
+             f"{st2[r]['true_rel_res']:.3e} batched")
+        assert st1[0]["iterations"] == 150 and st1[0]["cycles"] == st2[r]["cycles"] == 2
+        assert st1[0]["true_rel_res"] == st2[r]["true_rel_res"]
+        assert torch.equal(x1[0], x2[r])
