@@ -1514,39 +1514,24 @@ __global__ __launch_bounds__(kBlock) void k_arnoldi_col(int nv, int ld, const Z*
   }
 }
 
-// out[r] = a[r] * s[r] with a real per-RHS factor (rounded to the basis precision)
-template <typename VB>
+// out[r] = a[r] * s[r] with a real per-RHS factor (rounded to the basis
+// precision); conv (if not null) receives the same rounded values in the
+// product's precision D, the input of the next product.  With jd (the
+// Arnoldi step index on the device), out is V_{*jd + 1} of the basis at out.
+template <typename VB, typename D>
 __global__ __launch_bounds__(kBlock) void k_scale_real(size_t Nt, const Z* __restrict__ a,
-                                                        const double* __restrict__ s, C2<VB>* __restrict__ out) {
-  const int r = blockIdx.y;
-  const double c = s[r];
-  for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
-    const Z v = a[(size_t)r * Nt + k];
-    out[(size_t)r * Nt + k] = C2<VB>{(VB)(v.x * c), (VB)(v.y * c)};
-  }
-}
-
-// The Arnoldi step on the device (*jd = j): V_{j+1} = a * s (as k_scale_real),
-// and its conversion to the product's precision.
-template <typename VB>
-__global__ __launch_bounds__(kBlock) void k_scale_next(size_t Nt, const Z* __restrict__ a, const double* __restrict__ s,
-                                                        C2<VB>* __restrict__ V, size_t vstride,
+                                                        const double* __restrict__ s, C2<VB>* __restrict__ out,
+                                                        C2<D>* __restrict__ conv, size_t vstride,
                                                         const int* __restrict__ jd) {
   const int r = blockIdx.y;
   const double c = s[r];
-  C2<VB>* __restrict__ out = V + (size_t)(*jd + 1) * vstride;
+  if (jd) out += (size_t)(*jd + 1) * vstride;
   for (size_t k = (size_t)blockIdx.x * kBlock + threadIdx.x; k < Nt; k += (size_t)gridDim.x * kBlock) {
     const Z v = a[(size_t)r * Nt + k];
-    out[(size_t)r * Nt + k] = C2<VB>{(VB)(v.x * c), (VB)(v.y * c)};
+    const C2<VB> q{(VB)(v.x * c), (VB)(v.y * c)};
+    out[(size_t)r * Nt + k] = q;
+    if (conv) conv[(size_t)r * Nt + k] = C2<D>{(D)q.x, (D)q.y};
   }
-}
-template <typename VB, typename D>
-__global__ __launch_bounds__(kBlock) void k_convert_next(const C2<VB>* __restrict__ V, size_t vstride,
-                                                          const int* __restrict__ jd, C2<D>* __restrict__ b,
-                                                          size_t cnt) {
-  const C2<VB>* __restrict__ a = V + (size_t)(*jd + 1) * vstride;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock)
-    b[i] = {(D)a[i].x, (D)a[i].y};
 }
 __global__ void k_set_step(int* __restrict__ jd, int v, int add) {
   if (threadIdx.x == 0) jd[0] = add ? jd[0] + v : v;
@@ -2924,10 +2909,11 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   };
   // Arnoldi step j on w = A v_j: two Gram-Schmidt passes, the second where
   // DGKS asks for it; the Hessenberg column to col (and to the host), v_{j+1}
-  // = w / |w|.  With jd: j is read from the device, v_{j+1} is also
-  // converted for the next product into tT, and *jd advances, so that the
-  // same launches (one captured graph) serve every step.
-  auto arnoldi_step = [&](hipStream_t s, int j, const int* jd) -> int {
+  // = w / |w|, also written to tT for the next product when conv_next.  With
+  // jd: j is read from the device, v_{j+1} always goes to tT, and *jd
+  // advances, so that the same launches (one captured graph) serve every
+  // step.
+  auto arnoldi_step = [&](hipStream_t s, int j, const int* jd, bool conv_next) -> int {
     const int nv = j + 1;
     dots_on(s, nv, 1, w, h1, ld, nullptr, jd);
     subtract_on(s, nv, h1, w, n1, nullptr, jd);
@@ -2936,16 +2922,10 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
     dots_on(s, nv, 0, w, h2, ld, gate, jd);
     subtract_on(s, nv, h2, w, n2, gate, jd);
     hipLaunchKernelGGL(k_arnoldi_col, dim3(R), blk, 0, s, nv, ld, h1, n1, h2, n2, gate, col, scale, jd);
-    if (jd)
-      hipLaunchKernelGGL(k_scale_next<VB>, gv, blk, 0, s, Nt, (const Z*)w, (const double*)scale, V, vstride, jd);
-    else
-      hipLaunchKernelGGL(k_scale_real<VB>, gv, blk, 0, s, Nt, (const Z*)w, (const double*)scale,
-                         V + (size_t)(j + 1) * vstride);
+    hipLaunchKernelGGL((k_scale_real<VB, T>), gv, blk, 0, s, Nt, (const Z*)w, (const double*)scale,
+                       jd ? V : V + (size_t)(j + 1) * vstride, (jd || conv_next) ? tT : (CT*)nullptr, vstride, jd);
     HIP_TRY(hipMemcpyAsync(hcol, col, (size_t)R * ld * sizeof(Z), hipMemcpyDeviceToHost, s));
-    if (jd) {
-      hipLaunchKernelGGL((k_convert_next<VB, T>), dim3(grid1d(tot)), blk, 0, s, (const CV*)V, vstride, jd, tT, tot);
-      hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, jd_dev, 1, 1);
-    }
+    if (jd) hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, jd_dev, 1, 1);
     return 0;
   };
   // operator A z = Z (P^-1 z) -> result FP64 in `out`; z is a basis vector
@@ -3034,7 +3014,7 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
   auto capture_step = [&]() -> int {
     if (!cap_stream_) HIP_TRY(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal));
-    const int rc = arnoldi_step(cap_stream_, 0, jd_dev);
+    const int rc = arnoldi_step(cap_stream_, 0, jd_dev, true);
     hipGraph_t graph = nullptr;
     const hipError_t ce = hipStreamEndCapture(cap_stream_, &graph);
     if (rc) {
@@ -3065,11 +3045,12 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
       if (!done[r]) cycles[r]++;
     }
     HIP_TRY(hipMemcpyAsync(scale, s0.data(), (size_t)R * sizeof(double), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_scale_real<VB>, gv, blk, 0, st, Nt, (const Z*)w, (const double*)scale, V);
+    hipLaunchKernelGGL((k_scale_real<VB, T>), gv, blk, 0, st, Nt, (const Z*)w, (const double*)scale, V, tT, vstride,
+                       (const int*)nullptr);
     int j = 0;
     std::vector<char> active(R);
     for (int r = 0; r < R; ++r) active[r] = !done[r];
-    if (int rc = apply_A_from((const CV*)V, w, true)) return rc;
+    if (int rc = apply_A_converted(w, true)) return rc;  // v_0 is in tT
     if (graph_steps) {
       if (!step_graph.e)
         if (int rc = capture_step()) return rc;
@@ -3078,18 +3059,17 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
     for (; j < m && total_it < max_iter; ++j) {
       ++total_it;
       const int nv = j + 1;
+      const bool next = j + 1 < m && total_it < max_iter;
       if (graph_steps) {
         HIP_TRY(hipGraphLaunch(step_graph.e, st));
-      } else if (int rc = arnoldi_step(st, j, nullptr)) {
+      } else if (int rc = arnoldi_step(st, j, nullptr, next)) {
         return rc;
       }
       HIP_TRY(hipEventRecord(col_ev_, st));
-      // queue the next product before the host looks at the column
-      if (j + 1 < m && total_it < max_iter) {
-        const int rc = graph_steps ? apply_A_converted(w, true)
-                                   : apply_A_from((const CV*)(V + (size_t)(j + 1) * vstride), w, true);
-        if (rc) return rc;
-      }
+      // queue the next product (its input v_{j+1} is in tT) before the host
+      // looks at the column
+      if (next)
+        if (int rc = apply_A_converted(w, true)) return rc;
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipEventSynchronize(col_ev_));
       bool any_active = false;
