@@ -71,3 +71,60 @@ def mie_s1_s2(radius: float, k: float, m: complex, theta, n_max=None):
         s1 += c * (a[n - 1] * pi_n[n] + b[n - 1] * tau_n[n])
         s2 += c * (a[n - 1] * tau_n[n] + b[n - 1] * pi_n[n])
     return s1, s2
+
+
+def mie_near_field(radius: float, k: float, m: complex, pts, n_max=None):
+    """Scattered E at exterior points of a sphere centred at the origin, lit
+    by E_inc = x exp(-j k z) (unit amplitude, exp(+jwt)), from the vector
+    spherical wave expansion (Bohren & Huffman sec. 4.4, written there for
+    exp(-iwt) and E_inc = x exp(ikz)):
+      E_s = sum_n E_n (i a_n N_e1n - b_n M_o1n),  E_n = i^n (2n+1)/(n(n+1)),
+      M_o1n = cos(phi) pi_n h_n th_hat - sin(phi) tau_n h_n ph_hat,
+      N_e1n = cos(phi) n(n+1) sin(th) pi_n h_n/rho r_hat
+              + cos(phi) tau_n (rho h_n)'/rho th_hat - sin(phi) pi_n (rho h_n)'/rho ph_hat,
+    with h_n the outgoing spherical Hankel function h_n^(1)(rho), rho = k r,
+    and pi_n, tau_n the angular functions of mie_s1_s2.  For a real index m
+    the exp(+jwt) field of E_inc = x exp(-jkz) is the complex conjugate of
+    that one.  pts [D][3] -> E [D][3] (Cartesian)."""
+    from scipy.special import spherical_jn, spherical_yn
+    m = complex(m)
+    if abs(m.imag) > 0:
+        raise ValueError("mie_near_field: the conjugation argument needs a real index")
+    x = k * radius
+    a, b = mie_coefficients(x, m, n_max)
+    N = len(a)
+    pts = np.atleast_2d(np.asarray(pts, float))
+    r = np.linalg.norm(pts, axis=1)
+    th = np.arccos(np.clip(pts[:, 2] / r, -1.0, 1.0))
+    ph = np.arctan2(pts[:, 1], pts[:, 0])
+    mu = np.cos(th)
+    rho = k * r
+    pi_n = np.zeros((N + 1, len(mu)))
+    tau_n = np.zeros((N + 1, len(mu)))
+    pi_n[1] = 1.0
+    if N >= 2:
+        pi_n[2] = 3 * mu
+    for n in range(3, N + 1):
+        pi_n[n] = ((2 * n - 1) / (n - 1)) * mu * pi_n[n - 1] - (n / (n - 1)) * pi_n[n - 2]
+    for n in range(1, N + 1):
+        tau_n[n] = n * mu * pi_n[n] - (n + 1) * pi_n[n - 1]
+    Er = np.zeros(len(r), complex)
+    Et = np.zeros(len(r), complex)
+    Ep = np.zeros(len(r), complex)
+    cp, sp_, st = np.cos(ph), np.sin(ph), np.sin(th)
+    for n in range(1, N + 1):
+        h = spherical_jn(n, rho) + 1j * spherical_yn(n, rho)
+        dh = spherical_jn(n, rho, derivative=True) + 1j * spherical_yn(n, rho, derivative=True)
+        drh = (h + rho * dh) / rho                          # (rho h)'/rho
+        En = (1j ** n) * (2 * n + 1) / (n * (n + 1))
+        M_t, M_p = cp * pi_n[n] * h, -sp_ * tau_n[n] * h
+        N_r = cp * n * (n + 1) * st * pi_n[n] * h / rho
+        N_t, N_p = cp * tau_n[n] * drh, -sp_ * pi_n[n] * drh
+        Er += En * (1j * a[n - 1] * N_r)
+        Et += En * (1j * a[n - 1] * N_t - b[n - 1] * M_t)
+        Ep += En * (1j * a[n - 1] * N_p - b[n - 1] * M_p)
+    rh = np.stack([st * cp, st * sp_, mu], -1)
+    thh = np.stack([mu * cp, mu * sp_, -st], -1)
+    phh = np.stack([-sp_, cp, 0 * cp], -1)
+    E = Er[:, None] * rh + Et[:, None] * thh + Ep[:, None] * phh
+    return np.conj(E)

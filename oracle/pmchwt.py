@@ -13,6 +13,12 @@ k+ = k- sqrt(eps_r), z+ = z- / sqrt(eps_r).
 
 Right-hand side (Sec. II): V = -[<psi, E_inc>; <psi, H_inc>] for
 E_inc = pol exp(-j k khat . r), H_inc = khat x E_inc / z-.
+
+Background medium (Sec. II: particles (eps+, mu+) in (eps-, mu-), mu = 1):
+with eps_bg = eps- and every eps_r relative to vacuum, k- = k0 sqrt(eps-),
+z- = 1 / sqrt(eps-), k+ = k0 sqrt(eps+), z+ = 1 / sqrt(eps+) (vacuum
+wavelengths and the vacuum impedance as units).  eps_bg = 1 is the vacuum
+case above.
 """
 from __future__ import annotations
 
@@ -47,31 +53,36 @@ def assemble_block(T, K, zeta):
     return np.block([[zeta * T, K], [-K, T / zeta]])
 
 
-def self_block(pc: ParticleClass, k0: float = K0):
-    """Z_s of eq. Zpq_delta with delta = 1."""
+def self_block(pc: ParticleClass, k0: float = K0, eps_bg: complex = 1.0):
+    """Z_s of eq. Zpq_delta with delta = 1 (exterior: the background)."""
+    k_out, z_out = k0 * np.sqrt(eps_bg), 1.0 / np.sqrt(eps_bg)
     k_in = k0 * np.sqrt(pc.eps_r)
     z_in = 1.0 / np.sqrt(pc.eps_r)
-    To, Ko = self_TK(pc.bs, pc.sing, k0)
+    To, Ko = self_TK(pc.bs, pc.sing, k_out)
     Ti, Ki = self_TK(pc.bs, pc.sing, k_in)
     Kt = Ko + Ki
-    return np.block([[To + z_in * Ti, Kt], [-Kt, To + Ti / z_in]])
+    return np.block([[z_out * To + z_in * Ti, Kt], [-Kt, To / z_out + Ti / z_in]])
 
 
-def pair_block(pp: ParticleClass, pq: ParticleClass, offset, k0: float = K0):
+def pair_block(pp: ParticleClass, pq: ParticleClass, offset, k0: float = K0, eps_bg: complex = 1.0):
     """Z^{mu nu} for distinct particles, offset = r_nu - r_mu."""
-    T, K = direct_TK(pp.bs, pq.bs, offset, k0)
-    return assemble_block(T, K, 1.0)
+    T, K = direct_TK(pp.bs, pq.bs, offset, k0 * np.sqrt(eps_bg))
+    return assemble_block(T, K, 1.0 / np.sqrt(eps_bg))
 
 
 class DenseProblem:
     """Particles at ``centers`` with class ids into ``classes``; blocks are
     memoised by (class_mu, class_nu, centre offset)."""
 
-    def __init__(self, classes, centers, class_id, k0: float = K0):
+    def __init__(self, classes, centers, class_id, k0: float = K0, eps_bg: complex = 1.0):
         self.classes = classes
         self.centers = np.asarray(centers, float)
         self.class_id = np.asarray(class_id, int)
-        self.k0 = k0
+        self.k0 = k0                                    # vacuum wavenumber
+        self.eps_bg = complex(eps_bg)
+        kb = k0 * np.sqrt(self.eps_bg)
+        self.k = kb.real if kb.imag == 0 else kb        # background wavenumber
+        self.zeta = 1.0 / np.sqrt(self.eps_bg)          # background impedance / vacuum impedance
         self._cache = {}
 
     @property
@@ -84,9 +95,9 @@ class DenseProblem:
         key = self._key(mu, nu)
         if key not in self._cache:
             if mu == nu:
-                self._cache[key] = self_block(self.classes[cm], self.k0)
+                self._cache[key] = self_block(self.classes[cm], self.k0, self.eps_bg)
             else:
-                self._cache[key] = pair_block(self.classes[cm], self.classes[cn], off, self.k0)
+                self._cache[key] = pair_block(self.classes[cm], self.classes[cn], off, self.k0, self.eps_bg)
         return self._cache[key]
 
     def _key(self, mu, nu):
@@ -143,12 +154,12 @@ class DenseProblem:
         """V for a plane wave exp(-j k khat . r) pol; returns [P][n]."""
         khat = np.asarray(khat, float)
         pol = np.asarray(pol, complex)
-        hpol = np.cross(khat, pol)                       # H_inc / E amplitude, z- = 1
+        hpol = np.cross(khat, pol) / self.zeta           # H_inc / E amplitude
         out = []
         for mu in range(self.n_particles):
             pc = self.classes[self.class_id[mu]]
             X = pc.bs.X + self.centers[mu][None, :]
-            ph = np.exp(-1j * self.k0 * (X @ khat)) * pc.bs.W
+            ph = np.exp(-1j * self.k * (X @ khat)) * pc.bs.W
             Ev = sum(pc.bs.Psi[c] @ (ph * pol[c]) for c in range(3))
             Hv = sum(pc.bs.Psi[c] @ (ph * hpol[c]) for c in range(3))
             out.append(-np.concatenate([Ev, Hv]))

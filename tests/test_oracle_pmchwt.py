@@ -1,5 +1,7 @@
 """Pins of the dense PMCHWT oracle: brute force on a tiny mesh, the Mie
-series, power balance, reciprocity and mirror symmetry."""
+series (cross-section, far amplitudes and the near field), power balance,
+reciprocity, mirror symmetry, and Love's equivalence theorem for the
+near-field quadrature."""
 import math
 
 import numpy as np
@@ -7,9 +9,9 @@ import pytest
 
 import workloads as w
 from oracle.basis import MeshBasis
-from oracle.fields import (extinction_cross_section, far_amplitude,
+from oracle.fields import (extinction_cross_section, far_amplitude, near_field,
                            scattering_cross_section)
-from oracle.mie import mie_cross_sections, mie_s1_s2
+from oracle.mie import mie_cross_sections, mie_near_field, mie_s1_s2
 from oracle.operators import SampledBasis, direct_TK
 from oracle.pmchwt import DenseProblem, ParticleClass, solve_dense
 from oracle.quadrature import triangle_rule
@@ -168,3 +170,135 @@ def test_array_mirror_symmetry(array2x2):
     # components map to +- themselves under the mirrors; compare magnitudes
     assert np.abs(F0 - F1).max() < 1e-9 * F0.max()
     assert np.abs(F0 - F2).max() < 1e-9 * F0.max()
+
+
+# ---------------------------------------------------------------- near field
+
+
+def test_mie_near_field_far_limit_is_s1_s2():
+    """The VSWF near-field sum of the Mie series, taken far out, is the
+    textbook far amplitude: r exp(jkr) E_theta -> conj(j S2 / k) at phi = 0
+    and |E_phi| -> |S1| / k at phi = 90 deg (exp(+jwt) is the complex
+    conjugate of the exp(-iwt) series for a real index)."""
+    a, m, R = 0.15, 2.0, 400.0
+    th = np.array([0.4, 1.1, 2.3])
+    s1, s2 = mie_s1_s2(a, K0, m, th)
+    p0 = R * np.stack([np.sin(th), 0 * th, np.cos(th)], -1)
+    E0 = mie_near_field(a, K0, m, p0) * R * np.exp(1j * K0 * R)
+    thh = np.stack([np.cos(th), 0 * th, -np.sin(th)], -1)
+    Et = np.einsum("dc,dc->d", E0, thh)
+    assert np.abs(Et - np.conj(1j * s2 / K0)).max() < 5e-3 * np.abs(s2 / K0).max()
+    p1 = R * np.stack([0 * th, np.sin(th), np.cos(th)], -1)
+    E1 = mie_near_field(a, K0, m, p1) * R * np.exp(1j * K0 * R)
+    assert np.abs(np.abs(E1[:, 0]) - np.abs(s1) / K0).max() < 5e-3 * np.abs(s1 / K0).max()
+
+
+def test_near_field_far_zone_limit(single_sphere):
+    """r exp(jkr) E_s(r rhat) of the oracle's near-field quadrature tends to
+    its far amplitude (itself pinned by Mie above), with the error falling
+    like 1/r."""
+    prob, x, _ = single_sphere
+    rh = np.array([[0.3, 0.2, 0.93], [-0.5, 0.6, -0.2]])
+    rh /= np.linalg.norm(rh, axis=1)[:, None]
+    F = far_amplitude(prob, x, rh)
+    errs = []
+    for R in (100.0, 200.0, 400.0):
+        E = near_field(prob, x, R * rh) * R * np.exp(1j * K0 * R)
+        errs.append(np.linalg.norm(E - F) / np.linalg.norm(F))
+    assert errs[0] < 5e-3
+    assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2
+
+
+def test_near_field_vs_mie_series(single_sphere):
+    """Scattered near field of the single-sphere solution at points 0.1 to 1
+    wavelength outside the surface against the Mie VSWF sum (Sec. V.A's
+    check, here in the near zone), at the volume-equivalent radius."""
+    prob, x, req = single_sphere
+    rng = np.random.default_rng(3)
+    for rr in (0.25, 0.4, 0.7, 1.15):
+        d = rng.normal(size=(16, 3))
+        pts = rr * d / np.linalg.norm(d, axis=1)[:, None]
+        E = near_field(prob, x, pts)
+        Em = mie_near_field(req, K0, 2.0, pts)
+        assert np.linalg.norm(E - Em) / np.linalg.norm(Em) < 5e-3, rr
+
+
+def _dipole_fields(pts, p, k=K0):
+    """Closed-form fields of a point current element p at the origin
+    (exp(+jwt), zeta = 1): E = -jk (I + grad grad / k^2) g p, written with
+    the textbook dyadic coefficients; H = grad g x p."""
+    R = np.linalg.norm(pts, axis=1)
+    rh = pts / R[:, None]
+    kr = k * R
+    g = np.exp(-1j * kr) / (4 * np.pi * R)
+    rp = rh @ p
+    trans = p[None, :] - rh * rp[:, None]
+    a = 1 - 1 / kr ** 2 - 1j / kr
+    b = 2 / kr ** 2 + 2j / kr
+    E = -1j * k * g[:, None] * (a[:, None] * trans + b[:, None] * rh * rp[:, None])
+    H = (-(1 + 1j * kr) / R * g)[:, None] * np.cross(rh, p[None, :])
+    return E, H
+
+
+def test_near_field_love_equivalence():
+    """Love's equivalence theorem: the currents n x H and E x n of a source
+    inside a closed surface radiate the source's own field outside it and a
+    null field inside.  A point current element at the centre of the C1
+    sphere, its surface currents projected onto the 15 + 15 static modes
+    (L2 projection; the element's tangential fields are degree-1 harmonics,
+    which the sphere's first multiplets span up to mesh error): the
+    oracle's near-field quadrature reproduces the closed form outside and
+    nearly cancels inside.  Exercises both current operators (L with its
+    scalar-potential term, and K) in the near zone, independently of the
+    PMCHWT solve."""
+    v, t = w.icosphere(0.15, 2)
+    pc = ParticleClass(v, t, w.edge_table(t), 15, 15, 4.0)
+    prob = DenseProblem([pc], np.zeros((1, 3)), [0])
+    bs, mb = pc.bs, pc.mb
+    nrm = np.repeat(mb.normal, mb.nq, axis=0)
+    p = np.array([0.3, -0.2, 1.0])
+    E, H = _dipole_fields(bs.X, p)
+    Psi = np.stack(bs.Psi, -1)                                   # [N][Q][3]
+    G = np.einsum("nqc,mqc,q->nm", Psi, Psi, bs.W)
+
+    def proj(j):
+        return np.linalg.solve(G, np.einsum("nqc,qc,q->n", Psi, j, bs.W))
+
+    x = np.concatenate([proj(np.cross(nrm, H)), proj(np.cross(E, nrm))])[None]
+    rng = np.random.default_rng(4)
+    d = rng.normal(size=(24, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    for rr in (0.22, 0.4, 1.0):
+        Ed, _ = _dipole_fields(rr * d, p)
+        assert np.linalg.norm(near_field(prob, x, rr * d) - Ed) / np.linalg.norm(Ed) < 2e-2, rr
+    for rr in (0.05, 0.08):
+        Ed, _ = _dipole_fields(rr * d, p)
+        assert np.linalg.norm(near_field(prob, x, rr * d)) / np.linalg.norm(Ed) < 5e-3, rr
+
+
+def test_sphere_in_background_medium_vs_mie():
+    """A sphere of eps+ = 4 in a background of eps- = 1.69 (Sec. II's
+    particles in a background medium): the Mie series with the relative
+    index sqrt(eps+ / eps-) and the background wavenumber k0 sqrt(eps-)
+    gives the cross-section and the far amplitudes; the lossless power
+    balance holds as in vacuum."""
+    v, t = w.icosphere(0.15, 2)
+    pc = ParticleClass(v, t, w.edge_table(t), 15, 15, 4.0)
+    eb = 1.69
+    prob = DenseProblem([pc], np.zeros((1, 3)), [0], eps_bg=eb)
+    x = solve_dense(prob, prob.rhs([0, 0, 1], [1, 0, 0]))
+    req = (3 * w.check_closed_mesh(v, t)["volume"] / (4 * np.pi)) ** (1 / 3)
+    k, m = K0 * math.sqrt(eb), math.sqrt(4.0 / eb)
+    ms, _ = mie_cross_sections(req, k, m)
+    cs = scattering_cross_section(prob, x)
+    assert abs(cs / ms - 1) < 0.01
+    th = np.linspace(0.1, np.pi - 0.1, 9)
+    Fe = far_amplitude(prob, x, np.stack([np.sin(th), 0 * th, np.cos(th)], -1))
+    s1, s2 = mie_s1_s2(req, k, m, th)
+    assert np.abs(np.linalg.norm(Fe, axis=1) - np.abs(s2) / k).max() < 0.01 * np.abs(s2 / k).max()
+    ce = extinction_cross_section(prob, x, [0, 0, 1], np.array([1, 0, 0], complex))
+    assert abs(ce / cs - 1) < 1e-3
+    pts = np.array([[0.3, 0.1, 0.2], [-0.4, 0.5, -0.1], [0.0, 0.0, 0.8]])
+    En = near_field(prob, x, pts)
+    Em = mie_near_field(req, k, m, pts)
+    assert np.linalg.norm(En - Em) / np.linalg.norm(Em) < 1e-2
