@@ -34,12 +34,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_c2_40x40.json")
 # the roofline that bounds it
 # (the GEMM stages are named by kernel_of from the row tiles in use)
 KERNELS = [
-    ("aggregate_l", "k_aggregate", "hbm"),
+    ("aggregate_l", "k_agg_stream", "hbm"),
     ("translate", "k_translate", "hbm"),              # all levels with gathered lists, one launch
     ("translate_tiled", "k_translate_tiled", "hbm"),  # all levels in LDS tiles, one launch
-    ("disaggregate_l", "k_disaggregate", "hbm"),
-    ("disaggregate_phi_l", "k_dis_phi", "hbm"),
-    ("disaggregate_theta_l", "k_dis_theta", "hbm"),
+    ("disaggregate_l", "k_dis_stream", "hbm"),
     ("near_sum", "k_near_sum", "hbm"),
 ]
 

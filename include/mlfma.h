@@ -70,12 +70,23 @@ typedef struct mlfma_ctx mlfma_ctx;
 /* Particle array (Sec. II problem statement; Sec. IV grouping: every
  * particle is a finest-level group).  Centres must lie on one plane z = z0
  * at the sites origin + (i, j) * leaf_size of a square lattice, at most one
- * particle per site (empty sites are allowed). */
+ * particle per site (empty sites are allowed).
+ * Background medium (Sec. II: particles (eps+, mu+) in a background
+ * (eps-, mu-), here mu = 1 everywhere): eps_bg is eps- relative to vacuum,
+ * and the permittivities given to mlfma_set_static_modes are relative to
+ * vacuum as well.  With lengths in wavelengths of the background and zeta-
+ * as the unit of impedance, the operator depends on the media only through
+ * eps+ / eps- (k+ / k- = sqrt(eps+ / eps-), zeta+ / zeta- = 1 / that), which
+ * is how the library uses eps_bg.  eps_bg must be real and positive (a
+ * lossy background would make k- complex); 0 + 0j reads as 1 (vacuum), so
+ * a zero-initialised struct keeps the vacuum background.  EINVAL otherwise. */
 typedef struct {
   int32_t n_particles;      /* P >= 1                                     */
   const double* centers;    /* [P][3], background wavelengths             */
   const int32_t* class_id;  /* [P], 0 <= class_id < n_classes             */
   int32_t n_classes;        /* number of particle shapes/materials        */
+  double eps_bg_re;         /* background permittivity eps- (real part)   */
+  double eps_bg_im;         /* imaginary part: must be 0                  */
 } mlfma_problem;
 
 /* Tree and accuracy parameters (Sec. IV; Sec. V: L = 10 at the finest
@@ -124,7 +135,8 @@ void mlfma_default_params(mlfma_tree_params* tp);
  * the caller keeps ownership of pb's arrays.  On success *out owns a new
  * context, released with mlfma_destroy().
  * Errors: EINVAL (null pointers, P < 1, class ids out of range, centres not
- * on one lattice plane, two particles on one site, bad parameters). */
+ * on one lattice plane, two particles on one site, bad parameters, a
+ * background permittivity that is not real and positive). */
 int mlfma_build_tree(const mlfma_problem* pb, const mlfma_tree_params* tp, mlfma_ctx** out);
 
 /* Static modes of one closed particle surface (Sec. III): the N_perp
@@ -145,7 +157,8 @@ int mlfma_static_modes(int32_t nv, const double* verts, int32_t nt, const int32_
 
 /* Attach the mesh, static modes and permittivity of particle class
  * `class_id` (mesh in particle-local coordinates, centred on the particle
- * centre).  M is [(n_perp+n_par)][ne] as produced by mlfma_static_modes.
+ * centre; eps_re + j eps_im is eps+ relative to vacuum, divided by the
+ * problem's eps_bg inside).  M is [(n_perp+n_par)][ne] as produced by mlfma_static_modes.
  * Computes in FP64 on the host: the leaf radiation/receiving patterns of
  * eq. kspace_Rap, the self block Z_s of eq. Zpq_delta (singular quadrature
  * on touching triangle pairs), and its inverse for the block-diagonal
@@ -226,13 +239,14 @@ int mlfma_gmres_solve(mlfma_ctx* ctx, const void* b_dev, void* x_dev, int32_t R,
                       int32_t max_iter, int32_t restart, int32_t flags, mlfma_solve_stats* stats,
                       void* stream);
 
-/* Tile shapes of the interpolation kernels and the matrix-core GEMMs
- * (FP32 contexts): agg_rows[l] parent theta rows
- * per block of the aggregation into level l (l >= 1), dis_rows[l] child
- * theta rows per block of the disaggregation into level l (l < n_levels - 1);
- * 0 selects the built-in planner.  set re-plans the strips (the product's
- * arithmetic is unchanged, only its blocking) and fails with EINVAL if a
- * tile does not fit in LDS; get returns the heights in use.  Prepares the
+/* Work division of the interpolation kernels and the matrix-core GEMMs:
+ * agg_rows[l] parent theta rows per streaming chunk of the aggregation into
+ * level l (l >= 1), dis_rows[l] extended child theta rows per chunk of the
+ * disaggregation into level l (l < n_levels - 1); 0 selects the built-in
+ * planner (chunks that fill the chip for the launch's batch size).  set
+ * re-plans the chunks (the product's arithmetic and its order are
+ * unchanged, only which wave forms an output) and fails with EINVAL for a
+ * negative value; get returns the values set (0: planner).  Prepares the
  * context if needed.  Used by the autotuner of the binding. */
 #define MLFMA_MAX_LEVELS 16
 typedef struct {
@@ -335,14 +349,6 @@ int mlfma_mlp_loss_grad(mlfma_mlp* net, const float* X_dev, const float* T_dev, 
 int mlfma_mlp_train_step(mlfma_mlp* net, const float* X_dev, const float* T_dev, int32_t n, float lr,
                          double* loss, void* stream);
 
-/* Writes the network's prediction for R plane-wave incidences (directions
- * khat [R][3]) into x_dev [R][P][2][N] (context precision).  Features of
- * particle p, in this order: class_param[class of p] / scale, the same for
- * the 8 neighbouring sites (dy, dx in -1..1 row-major, centre skipped; 0
- * where a site holds no particle), khat_x, khat_y.  The network outputs
- * (re, im) of the 2N coefficients with the incident phase removed; the
- * guess multiplies them by exp(-j k khat . r_p).  EINVAL if the network
- * does not have 11 inputs and 4N outputs.  Synchronous. */
 /* The features described below, [R][P][n_classes + 11] FP32, on the host
  * (the inputs a network for mlfma_learned_guess is trained on).  Host-only. */
 int mlfma_guess_features(mlfma_ctx* ctx, const double* class_param, double scale, int32_t R, const double* khat,

@@ -3,11 +3,11 @@
 It times, with the library's dispatch-timed profiling of real products:
 the row tiles per block of the two matrix-core GEMM launches (near field +
 projection, receive: 1, 2 or 4 tiles of 16 rows), then for every level the
-aggregation and the disaggregation with each candidate strip height (theta
-rows per block), and keeps the fastest of each.  A tile shape changes only
-how the kernels block the work, not any output value (each output is
-computed by the same arithmetic in the same order), so the tuned product is
-bitwise identical to the default one.
+aggregation and the disaggregation with each candidate row chunk (rows of
+a pattern per streaming wave), and keeps the fastest of each.  A tile shape
+or chunk changes only how the kernels divide the work, not any output value
+(each output is computed by the same arithmetic in the same order), so the
+tuned product is bitwise identical to the default one.
 """
 from __future__ import annotations
 
@@ -18,7 +18,8 @@ import numpy as np
 
 from . import mlfma
 
-CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48)
+# rows per chunk of the streamed interpolation (0: the planner's chunks)
+CANDIDATES = (0, 8, 16, 32, 64, 128, 100000)
 
 
 def _stage_times(ctx, x, y, reps):
@@ -31,13 +32,8 @@ def _stage_times(ctx, x, y, reps):
 
 
 def _level_time(st, kind, l):
-    """Time of one level's aggregation or disaggregation (the latter may run
-    as the strip kernel or as the two-pass phi + theta kernels)."""
-    if kind == "aggregate":
-        return st.get(f"aggregate_l{l}", float("inf"))
-    names = (f"disaggregate_l{l}", f"disaggregate_phi_l{l}", f"disaggregate_theta_l{l}")
-    found = [st[n] for n in names if n in st]
-    return sum(found) if found else float("inf")
+    """Time of one level's aggregation or disaggregation."""
+    return st.get(f"{kind}_l{l}", float("inf"))
 
 
 def autotune(ctx: "mlfma.Context", R: int = 1, reps: int = 4, candidates=CANDIDATES, log=None):

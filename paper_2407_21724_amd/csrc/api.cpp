@@ -45,6 +45,7 @@ struct mlfma_ctx {
   int P = 0, C = 0;
   std::vector<V3> centers;
   std::vector<int> cls;
+  double eps_bg = 1.0;  // background permittivity (real, > 0)
   V3 origin{0, 0, 0};
   int nx = 0, ny = 0;
   std::vector<int> box_of, part_of_box;
@@ -331,6 +332,9 @@ int mlfma_build_tree(const mlfma_problem* pb, const mlfma_tree_params* tp, mlfma
   if (tp->outer_levels < 0 || tp->outer_levels > 5 || !(tp->digits > 0) || (tp->L_rule != 0 && tp->L_rule != 1))
     return MLFMA_EINVAL;
   ctx->tp = *tp;
+  if (!std::isfinite(pb->eps_bg_re) || !std::isfinite(pb->eps_bg_im)) return MLFMA_ENONFINITE;
+  if (pb->eps_bg_im != 0.0 || pb->eps_bg_re < 0.0) return MLFMA_EINVAL;
+  ctx->eps_bg = pb->eps_bg_re == 0.0 ? 1.0 : pb->eps_bg_re;
   const int P = pb->n_particles;
   if (!finite_all(pb->centers, (size_t)3 * P)) return MLFMA_ENONFINITE;
   ctx->P = P;
@@ -425,7 +429,7 @@ int mlfma_set_static_modes(mlfma_ctx* ctx, int32_t class_id, int32_t nv, const d
     if (!e.empty()) return fail(ctx, MLFMA_EINVAL, e);
     cdt.n_perp = n_perp;
     cdt.n_par = n_par;
-    cdt.eps = cd(eps_re, eps_im);
+    cdt.eps = cd(eps_re, eps_im) / ctx->eps_bg;  // eps+ / eps-
     std::vector<double> Mv(M, M + (size_t)N * ne);
     cdt.smp.build(cdt.mesh, Mv, N);
     cdt.td.build(cdt.mesh, ctx->tp.outer_levels);

@@ -202,8 +202,10 @@ struct GemmJob {
   const int* bcol;  // B column n, segment s: floats B[bcol[n*nseg+s] * ldb + k'] (< 0: zero column)
   float* C;
   const int* ccol;  // C column n: floats C[ccol[n] * ldc + m] (< 0: not written)
-  size_t sB, sC;    // per right-hand side (blockIdx.z) strides of B and C
+  size_t sB, sC;    // per right-hand side strides of B and C
   int M, ncols, nseg, kseg, lda, ldb, ldc, acc, tiles_m, tiles;
+  int fold;         // > 0: the right-hand sides are folded into the columns, column n = (n / fold, RHS
+                    // n % fold), so that the tiles of one block share A over all RHS; 0: RHS = blockIdx.z
   int xcd;          // (job 0 only) blocks in XCD-aware order over the launch grid
   int wtile;        // 1: every wave of a block takes its own tile over all of K (short K); 0: the
                     // block's waves split one tile's K and add their partial sums
@@ -235,26 +237,32 @@ __global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) 
   const int* __restrict__ ccol = second ? j1.ccol : j0.ccol;
   const int* __restrict__ a_off = second ? j1.a_off : j0.a_off;
   const int tm = t % tiles_m, tn = t / tiles_m;
-  // a_off has one entry per 16-column tile; the CT tiles of a block share it
-  const float* __restrict__ A = (second ? j1.A : j0.A) + (a_off ? a_off[tn * CT] : 0);
-  const int m0 = tm * 16 * RT, n0 = tn * 16 * CT, r = blockIdx.z;
+  const int fold = second ? j1.fold : j0.fold, fd = fold > 0 ? fold : 1;
+  const int m0 = tm * 16 * RT, n0 = tn * 16 * CT;
+  // a_off has one entry per 16 (unfolded) columns; the CT tiles of a block
+  // share it (the host keeps a block within one group)
+  const float* __restrict__ A = (second ? j1.A : j0.A) + (a_off ? a_off[(n0 / fd) >> 4] : 0);
   const int i = lane & 15, kq = lane >> 4;
-  const float* __restrict__ Bb = (second ? j1.B : j0.B) + (size_t)r * (second ? j1.sB : j0.sB);
+  const size_t sB = second ? j1.sB : j0.sB, sC = second ? j1.sC : j0.sC;
+  const float* __restrict__ B0 = second ? j1.B : j0.B;
   const int K = nseg * kseg;
   const int nsup = (K + 15) / 16;
   const int s0 = wt ? 0 : (wave * nsup) / W, s1 = wt ? nsup : ((wave + 1) * nsup) / W;
-  // this lane's columns and their source columns: one per column, or per
-  // segment staged in LDS (split-K blocks only, so the barrier is uniform)
-  int ncol[CT], src1[CT];
+  // this lane's columns: unfolded column and RHS, and their source columns
+  // (one per column, or per segment staged in LDS: split-K blocks only, so
+  // the barrier is uniform)
+  int ncol[CT], src1[CT], rc[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
-    ncol[ct] = n0 + 16 * ct + i;
-    src1[ct] = nseg == 1 && ncol[ct] < ncols ? bcol[ncol[ct]] : -1;
+    const int nf = n0 + 16 * ct + i;
+    ncol[ct] = nf < ncols ? nf / fd : -1;
+    rc[ct] = fold > 0 ? nf - (nf / fd) * fd : (int)blockIdx.z;
+    src1[ct] = nseg == 1 && ncol[ct] >= 0 ? bcol[ncol[ct]] : -1;
   }
   if (nseg > 1) {
     for (int e = threadIdx.x; e < 16 * CT * nseg; e += 64 * W) {
       const int c = n0 + e / nseg;
-      sbc[e] = c < ncols ? bcol[(size_t)n0 * nseg + e] : -1;
+      sbc[e] = c < ncols ? bcol[(size_t)(c / fd) * nseg + e % nseg] : -1;
     }
     __syncthreads();
   }
@@ -277,7 +285,8 @@ __global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) 
       if (k < K) {
         const int sg = nseg == 1 ? 0 : k / kseg;
         const int src = nseg == 1 ? src1[ct] : sbc[(16 * ct + i) * nseg + sg];
-        if (src >= 0) b[ct] = *reinterpret_cast<const f32x4*>(Bb + (size_t)src * ldb + (k - sg * kseg));
+        if (src >= 0)
+          b[ct] = *reinterpret_cast<const f32x4*>(B0 + (size_t)rc[ct] * sB + (size_t)src * ldb + (k - sg * kseg));
       }
     }
   };
@@ -316,17 +325,17 @@ __global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) 
 #pragma unroll
         for (int w = 0; w < W - 1; ++w) acc[rt][ct] += red[w][rt * CT + ct][lane];
   }
-  float* __restrict__ Cb = (second ? j1.C : j0.C) + (size_t)r * (second ? j1.sC : j0.sC);
+  float* __restrict__ C0 = second ? j1.C : j0.C;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const f32x4 v = acc[rt][ct];
       const int n = ncol[ct];
-      if (n >= ncols) continue;
+      if (n < 0) continue;
       const int dcol = ccol[n];
       if (dcol < 0) continue;
-      float* __restrict__ col = Cb + (size_t)dcol * ldc;
+      float* __restrict__ col = C0 + (size_t)rc[ct] * sC + (size_t)dcol * ldc;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int m = m0 + 16 * rt + 4 * kq + e;
@@ -547,336 +556,346 @@ __global__ __launch_bounds__(kBlock) void k_receive(int n, int P, int M2, int nb
   }
 }
 
-// -------------------------------------------------------------- aggregate --
-// i / d for 0 <= i < 2^20 by a float reciprocal: (i + 0.5) / d is at least
-// 0.5/d away from an integer and the rounding error stays below that.
-__device__ __forceinline__ int fdiv(int i, float inv_d) { return (int)(((float)i + 0.5f) * inv_d); }
-
-// S_p[r][P][c][s] = sum over children q: phase_q(s) * (Phi Theta S_child)(s).
-// Block = (parent box, component) x strip of ts parent rows x RHS.  The
-// strip's stencil tables and the needed rows [crow_lo, crow_hi] of the
-// children (contiguous in each child pattern) are staged in LDS, all four
-// children at once or, where that does not fit (the largest boxes), one
-// child per pass (nstage = 1); the theta pass writes tmp [nstage][ts][np_c];
-// each thread owns up to kAggVPT outputs of the strip and sums the children
-// in registers.
-constexpr int kAggVPT = 4;
-// staged copies into LDS keep this many loads of each kind in flight per
-// thread (a plain copy loop waits for every load before its LDS store)
-constexpr int kStageU = 2;
-
-// A stencil tap staged in LDS: weight and element offset of its operand.
+// ------------------------------------------------- streamed interpolation --
+// Aggregation and disaggregation as one pass over the rows of a pattern.
+// A work item is one wave: (RHS, parent box, component, column strip, row
+// chunk).  Its lanes hold SW columns of the output grid and, 32 lanes on,
+// the SW columns half a turn further on in phi, so that a theta stencil
+// crossing a pole, which reads its row at phi + pi, takes the partner
+// lane's value (a lane exchange, no second read).  Where half a row has at
+// most 16 columns (SW = 16) one wave takes both components.  The wave walks
+// the extended rows of the input grid (the `order/2` pole reflections, the
+// rows, the reflections at the other pole) once; per row it stages the phi
+// windows of its columns of the four children (aggregation) or of the
+// parent (disaggregation) in LDS, forms the phi stencil of each lane's
+// column, and keeps the last `order` rows in registers, from which the theta
+// stencil of every finished output row is formed.  Each input value is read
+// once per item and each output written once; the next row's loads are in
+// flight while a row is computed (two LDS buffers).
+constexpr int kIStrip = 32;  // output columns per half-wave (16 when two components share a wave)
+constexpr int kIStage = 8;   // staged values per lane and row, at most
 template <typename T>
-struct Tap {
-  T w;
-  int off;
+struct InterpArgs {
+  const C2<T>* src;          // aggregation: child patterns; disaggregation: parent patterns
+  C2<T>* dst;                // aggregation: parent patterns; disaggregation: child patterns (+=)
+  const C2<T>* E;            // [2][K_p] exp(+jk khat . d) for child offsets d = (+a/2, +a/2), (+a/2, -a/2)
+  const int* chunk;          // aggregation: parent rows; disaggregation: extended child rows [nch + 1]
+  const int* chunk_p;        // disaggregation: parent rows of each chunk [nch][2]
+  const int* s0;             // [nt_p] first extended child row of each parent row's theta stencil
+  const T* thw;              // [nt_p][order] theta weights (disaggregation: times wtheta_p / wtheta_c)
+  const int* vrow;           // [nt_c + order] child row of each extended row
+  const int* vflip;          // [nt_c + order] 1 where the extended row is a pole reflection
+  const int* colb;           // [np_out] first input column of each output column's phi stencil
+  const T* colw;             // [np_out][ntap] phi weights (disaggregation: times np_c / np_p)
+  const int* wlo;            // [nst][2] first input column of each half-wave's window
+  int nxc, nyc, ntc, npc, nxp, nyp, ntp, npp;
+  int R, nst, nch, wlen, ntap;
 };
-template <typename T, int ORD>
-__global__ __launch_bounds__(kBlock) void k_aggregate(
-    int order_rt, int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int crows_max,
-    const C2<T>* __restrict__ Sc, C2<T>* __restrict__ Sp, const int* __restrict__ th_row,
-    const T* __restrict__ th_w, const int* __restrict__ th_flip, const int* __restrict__ ph_col,
-    const T* __restrict__ ph_w, const C2<T>* __restrict__ phase, const int* __restrict__ strip_crow, int nstage) {
-  const int order = ORD > 0 ? ORD : order_rt;  // a compile-time order unrolls the stencil loops
+
+template <typename T>
+__device__ __forceinline__ C2<T> shfl_x32(C2<T> v) {
+  return {__shfl_xor(v.x, 32), __shfl_xor(v.y, 32)};
+}
+
+// S_P = sum over the children q of phase_q . (Theta Phi S_q)
+template <typename T, int ORD, int SW>
+__global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
+  constexpr int G = kIStrip / SW;  // components per wave
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* cbuf = reinterpret_cast<C2<T>*>(smem_raw);        // [nstage][crows_max][npc]
-  C2<T>* tmp = cbuf + (size_t)nstage * crows_max * npc;    // [nstage][ts][npc]
-  T* thw = reinterpret_cast<T*>(tmp + (size_t)nstage * ts * npc);
-  T* phw = thw + ts * order;
-  int* thr = reinterpret_cast<int*>(phw + npp * order);  // child row relative to crow_lo; -1-row if flipped
-  int* phc = thr + ts * order;
-  const int pb = blockIdx.x >> 1, comp = blockIdx.x & 1;
-  const int strip = blockIdx.y, r = blockIdx.z;
-  const int r0 = strip * ts;
-  const int nrow = min(ts, ntp - r0);
-  const int clo = strip_crow[2 * strip], crows = strip_crow[2 * strip + 1] - clo + 1;
-  const int PI = pb % nxp, PJ = pb / nxp;
-  const int Kc = ntc * npc, Kp = ntp * npp;
-  const int nbc = nxc * nyc, nbp = nxp * nyp;
-  const int half = npc / 2;
-  const float inv_npc = 1.0f / npc, inv_npp = 1.0f / npp, inv_cs = 1.0f / (crows * npc),
-              inv_ts = 1.0f / (nrow * npc);
-  for (int i = threadIdx.x; i < nrow * order; i += kBlock) {
-    const int e = r0 * order + i;
-    thw[i] = th_w[e];
-    thr[i] = th_flip[e] ? -1 - (th_row[e] - clo) : th_row[e] - clo;
-  }
-  for (int i = threadIdx.x; i < npp * order; i += kBlock) {
-    phw[i] = ph_w[i];
-    phc[i] = ph_col[i];
-  }
-  const int cs = crows * npc, tsz = nrow * npc, nout = nrow * npp;
-  C2<T> acc[kAggVPT];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);  // [2 buffers][G][4 children][2 halves][wlen]
+  const int nbp = A.nxp * A.nyp, nbc = A.nxc * A.nyc;
+  const int ncomp = 2 / G;
+  const int total = A.R * nbp * ncomp * A.nst * A.nch;
+  const int item = xcd_block(blockIdx.x, total);
+  if (item >= total) return;
+  int t = item;
+  const int ch = t % A.nch;
+  t /= A.nch;
+  const int st = t % A.nst;
+  t /= A.nst;
+  const int comp0 = G == 2 ? 0 : t % 2;
+  t /= ncomp;
+  const int pb = t % nbp, r = t / nbp;
+  const int lane = threadIdx.x, h = lane >> 5, g = (lane >> 4) & (G - 1), li = lane & (SW - 1);
+  const int comp = comp0 + g;
+  const int hp = A.npp >> 1, jj = st * SW + li;
+  const bool valid = jj < hp;
+  const int j = (valid ? jj : st * SW) + h * hp;  // idle lanes repeat the strip's first column
+  const int Kc = A.ntc * A.npc, Kp = A.ntp * A.npp;
+  const int wl = A.wlen, nbuf = G * 8 * wl;
+  // this lane's phi stencil: ORD consecutive columns of its window
+  T w[ORD];
 #pragma unroll
-  for (int vv = 0; vv < kAggVPT; ++vv) acc[vv] = C2<T>{0, 0};
-  for (int q0 = 0; q0 < 4; q0 += nstage) {
-    if (q0 > 0) __syncthreads();  // the previous pass has finished with cbuf and tmp
-    for (int i = threadIdx.x; i < nstage * cs; i += kBlock) {
-      const int qs = fdiv(i, inv_cs), j = i - qs * cs, q = q0 + qs;
+  for (int b = 0; b < ORD; ++b) w[b] = A.colw[j * ORD + b];
+  int off = A.colb[j] - A.wlo[st * 2 + h];
+  if (off < 0) off += A.npc;
+  const int lofs = ((g * 4) * 2 + h) * wl + off;  // + q * 2 * wl + buffer * nbuf
+  // staging: value v of a row goes to buffer slot v = ((g * 4 + q) * 2 + hh) * wl + c
+  const int PI = pb % A.nxp, PJ = pb / A.nxp;
+  const C2<T>* sp[kIStage];
+  int nst_l = 0;
+#pragma unroll
+  for (int k = 0; k < kIStage; ++k) {
+    const int v = lane + 64 * k;
+    sp[k] = nullptr;
+    if (v < nbuf) {
+      nst_l = k + 1;
+      const int c = v % wl, rest = v / wl, hh = rest & 1, q = (rest >> 1) & 3, gg = rest >> 3;
       const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
-      cbuf[qs * crows_max * npc + j] =
-          (ci < nxc && cj < nyc) ? Sc[(((size_t)r * nbc + cj * nxc + ci) * 2 + comp) * Kc + (size_t)clo * npc + j]
-                                 : C2<T>{0, 0};
+      const int col = (A.wlo[st * 2 + hh] + c) % A.npc;
+      if (ci < A.nxc && cj < A.nyc)
+        sp[k] = A.src + (((size_t)r * nbc + cj * A.nxc + ci) * 2 + comp0 + gg) * Kc + col;
     }
+  }
+  const int p0 = A.chunk[ch], p1 = A.chunk[ch + 1];
+  const int e0 = A.s0[p0], e1 = A.s0[p1 - 1] + ORD;
+  C2<T> nxt[kIStage];
+  auto fetch = [&](int e) {
+    const size_t ro = (size_t)A.vrow[e] * A.npc;
+#pragma unroll
+    for (int k = 0; k < kIStage; ++k)
+      if (k < nst_l) nxt[k] = sp[k] ? sp[k][ro] : C2<T>{0, 0};
+  };
+  fetch(e0);
+  C2<T> win[4][ORD];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int a = 0; a < ORD; ++a) win[q][a] = C2<T>{0, 0};
+  C2<T>* __restrict__ out = A.dst + (((size_t)r * nbp + pb) * 2 + comp) * Kp + j;
+  int pn = p0;
+  for (int e = e0; e < e1; ++e) {
+    C2<T>* buf = lds + (e & 1) * nbuf;
+#pragma unroll
+    for (int k = 0; k < kIStage; ++k)
+      if (k < nst_l) buf[lane + 64 * k] = nxt[k];
+    if (e + 1 < e1) fetch(e + 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < nstage * tsz; i += kBlock) {
-      const int qs = fdiv(i, inv_ts), j = i - qs * tsz;
-      const int row = fdiv(j, inv_npc), col = j - row * npc;
-      const int colf = col + half < npc ? col + half : col + half - npc;
-      const C2<T>* cq = cbuf + qs * crows_max * npc;
+    C2<T> f[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const C2<T>* __restrict__ lw = buf + lofs + q * 2 * wl;
       C2<T> v{0, 0};
-      for (int a = 0; a < order; ++a) {
-        const int rr = thr[row * order + a];
-        const T w = thw[row * order + a];
-        const C2<T> sv = rr >= 0 ? cq[rr * npc + col] : cq[(-1 - rr) * npc + colf];
-        v.x += w * sv.x;
-        v.y += w * sv.y;
+#pragma unroll
+      for (int b = 0; b < ORD; ++b) {
+        const C2<T> z = lw[b];
+        v.x = fmadd(w[b], z.x, v.x);
+        v.y = fmadd(w[b], z.y, v.y);
       }
-      tmp[qs * ts * npc + j] = v;
+      f[q] = v;
     }
+    if (A.vflip[e]) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) f[q] = shfl_x32(f[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int a = 0; a + 1 < ORD; ++a) win[q][a] = win[q][a + 1];
+      win[q][ORD - 1] = f[q];
+    }
+    // parent rows whose theta stencil ends at this extended row
+    while (pn < p1 && A.s0[pn] + ORD - 1 == e) {
+      const T* __restrict__ tw = A.thw + pn * ORD;
+      C2<T> v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v[q] = C2<T>{0, 0};
+#pragma unroll
+        for (int a = 0; a < ORD; ++a) {
+          v[q].x = fmadd(tw[a], win[q][a].x, v[q].x);
+          v[q].y = fmadd(tw[a], win[q][a].y, v[q].y);
+        }
+      }
+      // phases: child 3 = (+, +) -> E1, child 0 = conj(E1), child 1 =
+      // (+, -) -> E2, child 2 = conj(E2)
+      const size_t s = (size_t)pn * A.npp + j;
+      const C2<T> a1 = A.E[s], a2 = A.E[(size_t)Kp + s];
+      C2<T> o;
+      o.x = a1.x * (v[3].x + v[0].x) - a1.y * (v[3].y - v[0].y) + a2.x * (v[1].x + v[2].x) - a2.y * (v[1].y - v[2].y);
+      o.y = a1.x * (v[3].y + v[0].y) + a1.y * (v[3].x - v[0].x) + a2.x * (v[1].y + v[2].y) + a2.y * (v[1].x - v[2].x);
+      if (valid) out[(size_t)pn * A.npp] = o;
+      ++pn;
+    }
+  }
+}
+
+// G_c += W_c^-1 I^T W_P (conj(phase_c) G_P) for the four children c of a
+// parent box: the transposed stencils, streamed over the parent's rows.  A
+// lane holds one child column (and its partner half a turn on); per parent
+// row it forms the transposed phi stencil of the conjugate-phased parent row
+// for each child, and adds it with the transposed theta weights into the
+// `order` extended child rows that row reaches; an extended row is finished
+// (added to the child's pattern) once no later parent row reaches it.  A
+// pole reflection's sum belongs to the partner column's child row, which is
+// the lane exchange of the transposed stencil.  Chunks own disjoint ranges
+// of extended rows (the reflections with their rows).
+template <typename T, int ORD, int NT, int SW>
+__global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
+  constexpr int G = kIStrip / SW;
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);  // [2 buffers][G][4 children][2 halves][wlen]
+  const int nbp = A.nxp * A.nyp, nbc = A.nxc * A.nyc;
+  const int ncomp = 2 / G;
+  const int total = A.R * nbp * ncomp * A.nst * A.nch;
+  const int item = xcd_block(blockIdx.x, total);
+  if (item >= total) return;
+  int t = item;
+  const int ch = t % A.nch;
+  t /= A.nch;
+  const int st = t % A.nst;
+  t /= A.nst;
+  const int comp0 = G == 2 ? 0 : t % 2;
+  t /= ncomp;
+  const int pb = t % nbp, r = t / nbp;
+  const int lane = threadIdx.x, h = lane >> 5, g = (lane >> 4) & (G - 1), li = lane & (SW - 1);
+  const int comp = comp0 + g;
+  const int hc = A.npc >> 1, cc = st * SW + li;
+  const bool valid = cc < hc;
+  const int c = (valid ? cc : st * SW) + h * hc;  // idle lanes repeat the strip's first column
+  const int Kc = A.ntc * A.npc, Kp = A.ntp * A.npp;
+  const int wl = A.wlen, nbuf = G * 8 * wl;
+  T w[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) w[k] = A.colw[c * NT + k];
+  int off = A.colb[c] - A.wlo[st * 2 + h];
+  if (off < 0) off += A.npp;
+  const int lofs = (g * 4 * 2 + h) * wl + off;
+  const int PI = pb % A.nxp, PJ = pb / A.nxp;
+  C2<T>* cdst[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
+    cdst[q] = (valid && ci < A.nxc && cj < A.nyc) ? A.dst + (((size_t)r * nbc + cj * A.nxc + ci) * 2 + comp) * Kc + c
+                                                  : nullptr;
+  }
+  // staging: parent value v of a row (component gg, half hh, window column
+  // k) times the conjugate phases of the four children goes to slots
+  // ((gg * 4 + q) * 2 + hh) * wl + k
+  constexpr int KS = kIStage / 2;
+  const int nv = G * 2 * wl;
+  const C2<T>* gsrc[KS];
+  int scol[KS], sslot[KS];
+  int nst_l = 0;
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int v = lane + 64 * k;
+    gsrc[k] = nullptr;
+    scol[k] = 0;
+    sslot[k] = 0;
+    if (v < nv) {
+      nst_l = k + 1;
+      const int kk = v % wl, rest = v / wl, hh = rest & 1, gg = rest >> 1;
+      scol[k] = (A.wlo[st * 2 + hh] + kk) % A.npp;
+      sslot[k] = (gg * 8 + hh) * wl + kk;
+      gsrc[k] = A.src + (((size_t)r * nbp + pb) * 2 + comp0 + gg) * Kp + scol[k];
+    }
+  }
+  const int E0 = A.chunk[ch], E1 = A.chunk[ch + 1];
+  const int pfirst = A.chunk_p[2 * ch], plast = A.chunk_p[2 * ch + 1];
+  const int half = ORD / 2, nvr = A.ntc + ORD;
+  C2<T> ng[KS], ne1[KS], ne2[KS];
+  auto fetch = [&](int p) {
+    const size_t ro = (size_t)p * A.npp;
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+      if (k < nst_l) {
+        ng[k] = gsrc[k][ro];
+        ne1[k] = A.E[ro + scol[k]];
+        ne2[k] = A.E[(size_t)Kp + ro + scol[k]];
+      }
+  };
+  fetch(pfirst);
+  C2<T> acc[4][ORD];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int a = 0; a < ORD; ++a) acc[q][a] = C2<T>{0, 0};
+  int ew = A.s0[pfirst];  // extended child row held in acc[.][0]
+  // the oldest held row's translated child values, loaded ahead of its flush
+  C2<T> pend[4];
+  auto load_pend = [&]() {
+    if (ew >= E0 && ew < E1 && ew < nvr) {
+      const size_t o = (size_t)A.vrow[ew] * A.npc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pend[q] = cdst[q] ? cdst[q][o] : C2<T>{0, 0};
+    }
+  };
+  load_pend();
+  // adds the oldest held row to its child row (if this chunk owns it) and
+  // shifts the window
+  auto flush = [&]() {
+    if (ew >= E0 && ew < E1) {
+      const size_t o = (size_t)A.vrow[ew] * A.npc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (cdst[q]) cdst[q][o] = {pend[q].x + acc[q][0].x, pend[q].y + acc[q][0].y};
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int a = 0; a + 1 < ORD; ++a) acc[q][a] = acc[q][a + 1];
+      acc[q][ORD - 1] = C2<T>{0, 0};
+    }
+    ++ew;
+    load_pend();
+  };
+  for (int p = pfirst; p <= plast; ++p) {
+    const int spp = A.s0[p];
+    while (ew < spp) flush();
+    C2<T>* buf = lds + (p & 1) * nbuf;
+    // child 0: E1 g, child 1: conj(E2) g, child 2: E2 g, child 3: conj(E1) g
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+      if (k < nst_l) {
+        C2<T>* d = buf + sslot[k];
+        d[0] = cmul(ne1[k], ng[k]);
+        d[2 * wl] = cmul_conj_a(ne2[k], ng[k]);
+        d[4 * wl] = cmul(ne2[k], ng[k]);
+        d[6 * wl] = cmul_conj_a(ne1[k], ng[k]);
+      }
+    if (p < plast) fetch(p + 1);
     __syncthreads();
+    C2<T> f[4];
 #pragma unroll
-    for (int vv = 0; vv < kAggVPT; ++vv) {
-      const int i = threadIdx.x + vv * kBlock;
-      if (i >= nout) continue;
-      const int row = fdiv(i, inv_npp), ip = i - row * npp;
-      for (int qs = 0; qs < nstage; ++qs) {
-        C2<T> sv{0, 0};
-        const C2<T>* tq = tmp + qs * ts * npc + row * npc;
-        for (int b = 0; b < order; ++b) {
-          const T w = phw[ip * order + b];
-          const C2<T> t = tq[phc[ip * order + b]];
-          sv.x += w * t.x;
-          sv.y += w * t.y;
-        }
-        cfma(acc[vv], phase[(size_t)(q0 + qs) * Kp + (size_t)(r0 + row) * npp + ip], sv);
-      }
-    }
-  }
-  C2<T>* __restrict__ dst = Sp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)r0 * npp;
-#pragma unroll
-  for (int vv = 0; vv < kAggVPT; ++vv) {
-    const int i = threadIdx.x + vv * kBlock;
-    if (i < nout) dst[i] = acc[vv];
-  }
-}
-
-// ----------------------------------------------------------- disaggregate --
-// G_c += W_c^-1 I^T W_p (conj(phase_q) G_parent), the anterpolation written
-// as gathers over the transposed stencils, added to the child's translated
-// pattern.  Block = (child box, component) x strip of ts child rows x RHS,
-// in XCD-aware order over a 1-D grid (child box fastest).  LDS: the strip's
-// transposed theta taps and the transposed phi taps as (weight, offset)
-// pairs, the phase-weighted parent rows [plo, phi] ([rows][np_p]), and their
-// phi anterpolation ([rows][np_c + np_c/2], each row followed by its first
-// half again).  A theta tap that crosses a pole reads its row half a turn
-// further on in phi, i.e. np_c/2 elements later, so every tap is one offset
-// read, one add and two FMAs.
-constexpr int kDisRPT = 4;  // parent rows per thread in the phi pass
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_disaggregate(
-    int nxc, int nyc, int ntc, int npc, int nxp, int nyp, int ntp, int npp, int ts, int tmax, int pmax,
-    int prows_max, const C2<T>* __restrict__ Gp, C2<T>* __restrict__ Gc, const int* __restrict__ tth_row,
-    const T* __restrict__ tth_w, const int* __restrict__ tth_flip, const int* __restrict__ strip_prow,
-    const int* __restrict__ tph_col, const T* __restrict__ tph_w, const C2<T>* __restrict__ phase, int nstrips,
-    int R) {
-  extern __shared__ unsigned char smem_raw[];
-  Tap<T>* tt = reinterpret_cast<Tap<T>*>(smem_raw);  // [ts][tmax]: weight, element offset into tmp
-  Tap<T>* tp = tt + ts * tmax;                        // [np_c][pmax]: weight, parent column
-  C2<T>* par = reinterpret_cast<C2<T>*>(tp + npc * pmax);  // [prows_max][np_p]
-  C2<T>* tmp = par + (size_t)prows_max * npp;              // [prows_max][np_c + np_c / 2]
-  const int total = nxc * nyc * 2 * nstrips * R;
-  const int lb = xcd_block(blockIdx.x, total);
-  if (lb >= total) return;
-  const int bx = lb % (nxc * nyc * 2), rest = lb / (nxc * nyc * 2);
-  const int cb = bx >> 1, comp = bx & 1;
-  const int strip = rest % nstrips, r = rest / nstrips;
-  const int c0 = strip * ts;
-  const int nrow = min(ts, ntc - c0);
-  const int ci = cb % nxc, cj = cb / nxc;
-  const int pb = (cj >> 1) * nxp + (ci >> 1);
-  const int q = (cj & 1) * 2 + (ci & 1);
-  const int Kc = ntc * npc, Kp = ntp * npp;
-  const int nbc = nxc * nyc, nbp = nxp * nyp;
-  const int half = npc / 2, rw = npc + half;
-  const int plo = strip_prow[2 * strip], prows = strip_prow[2 * strip + 1] - plo + 1;
-  const float inv_npc = 1.0f / npc;
-  const C2<T>* __restrict__ ph = phase + (size_t)q * Kp + (size_t)plo * npp;
-  const C2<T>* __restrict__ src = Gp + (((size_t)r * nbp + pb) * 2 + comp) * Kp + (size_t)plo * npp;
-  // the child's translated pattern (first two outputs per thread), loaded
-  // first so its latency overlaps the staging
-  const int nout = nrow * npc;
-  C2<T>* __restrict__ dst = Gc + (((size_t)r * nbc + cb) * 2 + comp) * Kc + (size_t)c0 * npc;
-  C2<T> gpre[2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int i = threadIdx.x + u * kBlock;
-    gpre[u] = i < nout ? dst[i] : C2<T>{0, 0};
-  }
-  // taps and phase-weighted parent rows, kStageU loads of each kind in flight
-  {
-    const int n1 = nrow * tmax, n2 = npc * pmax, n3 = prows * npp;
-    const int nmax = max(n3, max(n1, n2));
-    for (int b = threadIdx.x; b < nmax; b += kStageU * kBlock) {
-      T w1[kStageU], w2[kStageU];
-      int r1[kStageU], f1[kStageU], c2[kStageU];
-      C2<T> g3[kStageU], p3[kStageU];
-#pragma unroll
-      for (int u = 0; u < kStageU; ++u) {
-        const int i = b + u * kBlock;
-        if (i < n1) {
-          const int e = c0 * tmax + i;
-          w1[u] = tth_w[e];
-          r1[u] = tth_row[e];
-          f1[u] = tth_flip[e];
-        }
-        if (i < n2) {
-          w2[u] = tph_w[i];
-          c2[u] = tph_col[i];
-        }
-        if (i < n3) {
-          g3[u] = src[i];
-          p3[u] = ph[i];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kStageU; ++u) {
-        const int i = b + u * kBlock;
-        if (i < n1) tt[i] = Tap<T>{w1[u], (r1[u] - plo) * rw + (f1[u] ? half : 0)};
-        if (i < n2) tp[i] = Tap<T>{w2[u], c2[u]};
-        if (i < n3) par[i] = cmul_conj_a(p3[u], g3[u]);
-      }
-    }
-  }
-  __syncthreads();
-  // phi pass: item = (child column, kDisRPT consecutive parent rows); the
-  // last rows of a strip are clamped (computed twice, stored once)
-  {
-    const int rchunks = (prows + kDisRPT - 1) / kDisRPT;
-    for (int it = threadIdx.x; it < npc * rchunks; it += kBlock) {
-      const int c = it % npc, rr0 = (it / npc) * kDisRPT;
-      int ro[kDisRPT];
-      C2<T> acc[kDisRPT];
-#pragma unroll
-      for (int j = 0; j < kDisRPT; ++j) {
-        ro[j] = min(rr0 + j, prows - 1) * npp;
-        acc[j] = C2<T>{0, 0};
-      }
-      const Tap<T>* __restrict__ tc = tp + c * pmax;
-      for (int e = 0; e < pmax; ++e) {
-        const Tap<T> t = tc[e];
-#pragma unroll
-        for (int j = 0; j < kDisRPT; ++j) {
-          const C2<T> z = par[ro[j] + t.off];
-          acc[j].x = fmadd(t.w, z.x, acc[j].x);
-          acc[j].y = fmadd(t.w, z.y, acc[j].y);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < kDisRPT; ++j)
-        if (rr0 + j < prows) {
-          tmp[(rr0 + j) * rw + c] = acc[j];
-          if (c < half) tmp[(rr0 + j) * rw + npc + c] = acc[j];
-        }
-    }
-  }
-  __syncthreads();
-  // theta pass, added to the child's pattern
-  for (int b = threadIdx.x; b < nout; b += 2 * kBlock) {
-    C2<T> o[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int i = b + u * kBlock;
-      o[u] = b == (int)threadIdx.x ? gpre[u] : (i < nout ? dst[i] : C2<T>{0, 0});
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int i = b + u * kBlock;
-      if (i >= nout) break;
-      const int row = fdiv(i, inv_npc), col = i - row * npc;
-      const Tap<T>* __restrict__ tr = tt + row * tmax;
+    for (int q = 0; q < 4; ++q) {
+      const C2<T>* __restrict__ lw = buf + lofs + q * 2 * wl;
       C2<T> v{0, 0};
-      for (int e = 0; e < tmax; ++e) {
-        const Tap<T> t = tr[e];
-        const C2<T> z = tmp[t.off + col];
-        v.x = fmadd(t.w, z.x, v.x);
-        v.y = fmadd(t.w, z.y, v.y);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        const C2<T> z = lw[k];
+        v.x = fmadd(w[k], z.x, v.x);
+        v.y = fmadd(w[k], z.y, v.y);
       }
-      dst[i] = {o[u].x + v.x, o[u].y + v.y};
+      f[q] = v;
+    }
+    const T* __restrict__ tw = A.thw + p * ORD;
+    if (spp < half || spp + ORD > half + A.ntc) {  // a tap on a pole reflection
+      C2<T> gx[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) gx[q] = shfl_x32(f[q]);
+#pragma unroll
+      for (int a = 0; a < ORD; ++a) {
+        const bool fl = A.vflip[spp + a] != 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const C2<T> z = fl ? gx[q] : f[q];
+          acc[q][a].x = fmadd(tw[a], z.x, acc[q][a].x);
+          acc[q][a].y = fmadd(tw[a], z.y, acc[q][a].y);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < ORD; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[q][a].x = fmadd(tw[a], f[q].x, acc[q][a].x);
+          acc[q][a].y = fmadd(tw[a], f[q].y, acc[q][a].y);
+        }
     }
   }
-}
-
-// Two-pass disaggregation for the largest boxes, where a strip of parent
-// rows does not fit in LDS.  Pass 1 (phi): for every parent box, component,
-// child quadrant q and parent row,
-//   H[q][row][c] = sum_e tph_w[c][e] conj(phase_q[row][tph_col[c][e]]) G_p[row][tph_col[c][e]]
-// Pass 2 (theta): G_c[row][c] += sum_e tth_w[row][e] H[q][tth_row[row][e]][c or c + np/2 if flipped].
-// Block = one parent row of one (RHS, box, component): the row is multiplied
-// by the four quadrants' conjugate phases into LDS ([4][npp]) and every
-// thread forms outputs of all four H rows from it.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dis_phi(int nbp, int ntp, int npp, int npc, int pmax, int R,
-                                                    const C2<T>* __restrict__ Gp, const int* __restrict__ tph_col,
-                                                    const T* __restrict__ tph_w, const C2<T>* __restrict__ phase,
-                                                    C2<T>* __restrict__ H) {
-  extern __shared__ unsigned char smem_raw[];
-  C2<T>* pq = reinterpret_cast<C2<T>*>(smem_raw);  // [4][npp]
-  const long Kp = (long)ntp * npp;
-  const int row = blockIdx.x % ntp;
-  const long bc = blockIdx.x / ntp;  // (r * nbp + pb) * 2 + comp
-  const C2<T>* __restrict__ src = Gp + bc * Kp + (long)row * npp;
-  for (int i = threadIdx.x; i < 4 * npp; i += kBlock) {
-    const int q = i / npp, c = i - q * npp;
-    pq[i] = cmul_conj_a(phase[(long)q * Kp + (long)row * npp + c], src[c]);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 4 * npc; i += kBlock) {
-    const int q = i / npc, c = i - q * npc;
-    const C2<T>* __restrict__ pr = pq + q * npp;
-    C2<T> v{0, 0};
-    for (int e = 0; e < pmax; ++e) {
-      const T w = tph_w[c * pmax + e];
-      const C2<T> z = pr[tph_col[c * pmax + e]];
-      v.x += w * z.x;
-      v.y += w * z.y;
-    }
-    H[((bc * 4 + q) * ntp + row) * npc + c] = v;
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dis_theta(int nxc, int nyc, int ntc, int npc, int nxp, int ntp,
-                                                      int tmax, int R, const C2<T>* __restrict__ H,
-                                                      const int* __restrict__ tth_row, const T* __restrict__ tth_w,
-                                                      const int* __restrict__ tth_flip, C2<T>* __restrict__ Gc,
-                                                      int nyp) {
-  const int nbc = nxc * nyc, nbp = nxp * nyp;
-  const long Kc = (long)ntc * npc;
-  const long total = (long)R * nbc * 2 * Kc;
-  const int half = npc / 2;
-  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < total; i += (long)gridDim.x * kBlock) {
-    const int s = (int)(i % Kc);
-    long t = i / Kc;
-    const int comp = (int)(t % 2);
-    t /= 2;
-    const int cb = (int)(t % nbc), r = (int)(t / nbc);
-    const int row = s / npc, col = s - row * npc;
-    const int ci = cb % nxc, cj = cb / nxc;
-    const int pb = (cj >> 1) * nxp + (ci >> 1), q = (cj & 1) * 2 + (ci & 1);
-    const C2<T>* __restrict__ hq = H + ((((long)r * nbp + pb) * 2 + comp) * 4 + q) * ntp * npc;
-    const int colf = col + half < npc ? col + half : col + half - npc;
-    C2<T> v{0, 0};
-    for (int e = 0; e < tmax; ++e) {
-      const int pr = tth_row[row * tmax + e];
-      const T w = tth_w[row * tmax + e];
-      const C2<T> z = hq[(long)pr * npc + (tth_flip[row * tmax + e] ? colf : col)];
-      v.x += w * z.x;
-      v.y += w * z.y;
-    }
-    const C2<T> o = Gc[i];
-    Gc[i] = {o.x + v.x, o.y + v.y};
-  }
+  const int eend = min(E1, nvr);
+  while (ew < eend) flush();
 }
 
 // -------------------------------------------------------------- translate --
@@ -1644,12 +1663,26 @@ class EngineT final : public Engine {
     DevMem il_cnt, il_src, il_off;  // interaction lists
     DevMem S, G;  // pattern buffers, sized for R_alloc
   };
+  // One level's streamed interpolation plan (aggregation into this level,
+  // disaggregation out of it): stencil tables, windows and row chunks.  The
+  // row chunks are tabulated for a few batch sizes (kChunkR), since a larger
+  // batch needs fewer chunks to fill the chip.
   struct Itp {
-    int order, tmax, pmax, ts_agg, ts_dis, crows_max, prows_max, agg_stage, dis_stage;
-    size_t lds_dis, lds_agg;
-    DevMem strip_crow, strip_prow;
-    DevMem th_row, th_w, th_flip, ph_col, ph_w, tth_row, tth_w, tth_flip, tth_lo, tth_hi, tph_col, tph_w, phase;
+    int order = 0;
+    int a_nst = 0, a_wlen = 0, d_nst = 0, d_wlen = 0, d_ntap = 0;
+    int a_sw = kIStrip, d_sw = kIStrip;         // strip widths (16: two components per wave)
+    int a_rows = 0, d_rows = 0;                 // rows per chunk set by the tuner (0: planner)
+    int a_nch[8] = {}, d_nch[8] = {};           // chunks per batch-size bucket
+    int a_coff[8] = {}, d_coff[8] = {};         // offsets of the buckets' chunk tables
+    DevMem s0, vrow, vflip, thw_a, thw_d, colb_a, colw_a, colb_d, colw_d, wlo_a, wlo_d, E;
+    DevMem chunk_a, chunk_d, chunkp_d;
   };
+  static constexpr int kChunkR[8] = {1, 2, 4, 8, 16, 32, 64, 1 << 30};
+  static int chunk_bucket(int R) {
+    int b = 0;
+    while (b < 7 && kChunkR[b] < R) ++b;
+    return b;
+  }
 
  public:
   int upload(const Upload& u, std::string& err) override {
@@ -1698,27 +1731,8 @@ class EngineT final : public Engine {
       if (int rc = put_i(L.il_src, src, err)) return rc;
       if (int rc = put_i(L.il_off, off, err)) return rc;
     }
-    for (int l = 1; l < ntl_; ++l) {
-      const InterpTables& T0 = tr.it[l];
-      Itp& I = it_[l];
-      I.order = T0.order;
-      I.tmax = T0.tmax;
-      I.pmax = T0.pmax;
-      if (int rc = put_i(I.th_row, T0.th_row, err)) return rc;
-      if (int rc = put_r(I.th_w, T0.th_w, err)) return rc;
-      if (int rc = put_u8(I.th_flip, T0.th_flip, err)) return rc;
-      if (int rc = put_i(I.ph_col, T0.ph_col, err)) return rc;
-      if (int rc = put_r(I.ph_w, T0.ph_w, err)) return rc;
-      if (int rc = put_i(I.tth_row, T0.tth_row, err)) return rc;
-      if (int rc = put_r(I.tth_w, T0.tth_w, err)) return rc;
-      if (int rc = put_u8(I.tth_flip, T0.tth_flip, err)) return rc;
-      if (int rc = put_i(I.tth_lo, T0.tth_lo, err)) return rc;
-      if (int rc = put_i(I.tth_hi, T0.tth_hi, err)) return rc;
-      if (int rc = put_i(I.tph_col, T0.tph_col, err)) return rc;
-      if (int rc = put_r(I.tph_w, T0.tph_w, err)) return rc;
-      if (int rc = put_c(I.phase, T0.phase, err)) return rc;
+    for (int l = 1; l < ntl_; ++l)
       if (int rc = plan_level(l, 0, 0, err)) return rc;
-    }
     // leaf data
     nx0_ = u.nx0;
     ny0_ = u.ny0;
@@ -1990,114 +2004,180 @@ class EngineT final : public Engine {
     return 0;
   }
 
-  // Strip plans of the interpolation kernels into level l (aggregation
-  // l-1 -> l) and out of it (disaggregation l -> l-1): agg_rows parent rows
-  // and dis_rows child rows per block, 0 for the default planner (the
-  // tallest strip whose tile fits the preferred LDS size while the grid keeps
-  // at least kMinBlocks blocks).
+  // Streamed interpolation plan of level l (parent) and l - 1 (child):
+  // tables and, for each batch-size bucket, row chunks so that a launch has
+  // about kStreamItems waves.  agg_rows: parent rows per aggregation chunk,
+  // dis_rows: extended child rows per disaggregation chunk (0: planner).
+  // Chunking changes only which wave computes an output, not its arithmetic.
   int plan_level(int l, int agg_rows, int dis_rows, std::string& err) {
-    // aggregation strips: each thread owns at most kAggVPT outputs; the
-    // strip's child rows and stencil tables are staged in LDS
     const Lvl &C = lv_[l - 1], &Pp = lv_[l];
+    const LevelGrid &gc = tree_->lv[l - 1], &gp = tree_->lv[l];
     const InterpTables& T0 = tree_->it[l];
     Itp& I = it_[l];
-    if (Pp.np > kBlock * kAggVPT) {
-      err = "aggregation: more than " + std::to_string(kBlock * kAggVPT) + " phi samples per row at level " +
-            std::to_string(l);
+    const int ORD = T0.order, nvr = C.nt + ORD;
+    I.order = ORD;
+    if (C.np % 2 || Pp.np % 2 || (int)T0.vrow.size() != nvr) {
+      err = "interpolation: odd phi sample counts at level " + std::to_string(l);
       return -1;
     }
-    const int order = T0.order;
-    int nstage = 4;  // children staged per pass
-    auto agg_plan = [&](int ts, std::vector<int>& rng, int& cmax) {
-      rng.clear();
-      cmax = 0;
-      for (int r0 = 0; r0 < Pp.nt; r0 += ts) {
-        int lo = C.nt, hi = -1;
-        for (int it = r0; it < std::min(Pp.nt, r0 + ts); ++it)
-          for (int a2 = 0; a2 < order; ++a2) {
-            lo = std::min(lo, T0.th_row[(size_t)it * order + a2]);
-            hi = std::max(hi, T0.th_row[(size_t)it * order + a2]);
-          }
-        rng.push_back(lo);
-        rng.push_back(hi);
-        cmax = std::max(cmax, hi - lo + 1);
+    // theta: the stencils on the extended rows must be the recorded taps
+    for (int p = 0; p < Pp.nt; ++p)
+      for (int a = 0; a < ORD; ++a) {
+        const int e = T0.th_s0[p] + a;
+        if (e < 0 || e >= nvr || T0.vrow[e] != T0.th_row[(size_t)p * ORD + a] ||
+            T0.vflip[e] != T0.th_flip[(size_t)p * ORD + a] || (p > 0 && T0.th_s0[p] < T0.th_s0[p - 1])) {
+          err = "interpolation: theta stencils are not runs of extended rows at level " + std::to_string(l);
+          return -1;
+        }
       }
-      return (size_t)nstage * (cmax + ts) * C.np * sizeof(CT) + (size_t)ts * order * (sizeof(T) + 4) +
-             (size_t)Pp.np * order * (sizeof(T) + 4);
-    };
-    // strip height: bounded by the per-thread outputs; split further only
-    // while the grid has fewer than kMinBlocks blocks
-    const int ts_cap = std::max(1, std::min(Pp.nt, (kBlock * kAggVPT) / Pp.np));
-    int ts = ts_cap;
-    while (ts > 1 && (size_t)Pp.nx * Pp.ny * 2 * ((Pp.nt + ts - 1) / ts) < kMinBlocks) ts = (ts + 1) / 2;
-    if (agg_rows > 0) {
-      if (agg_rows > ts_cap) {
-        err = "aggregation strip of " + std::to_string(agg_rows) + " rows exceeds " + std::to_string(ts_cap) +
-              " at level " + std::to_string(l);
+    std::vector<double> thw_d((size_t)Pp.nt * ORD);
+    for (int p = 0; p < Pp.nt; ++p)
+      for (int a = 0; a < ORD; ++a)
+        thw_d[(size_t)p * ORD + a] =
+            T0.th_w[(size_t)p * ORD + a] * gp.wtheta[p] / gc.wtheta[T0.vrow[T0.th_s0[p] + a]];
+    // phi, forward: each parent column reads ORD consecutive child columns
+    std::vector<int> colb_a(Pp.np);
+    for (int j = 0; j < Pp.np; ++j) {
+      colb_a[j] = T0.ph_col[(size_t)j * ORD];
+      for (int b = 0; b < ORD; ++b)
+        if (T0.ph_col[(size_t)j * ORD + b] != (colb_a[j] + b) % C.np) {
+          err = "interpolation: phi stencil is not a run of columns at level " + std::to_string(l);
+          return -1;
+        }
+    }
+    // phi, transposed: each child column gathers the cyclic run of parent
+    // columns whose stencils contain it (a weight may be exactly zero where
+    // a parent node falls on a child node), weight times np_c / np_p
+    std::vector<std::vector<double>> dense((size_t)C.np, std::vector<double>(Pp.np, 0.0));
+    std::vector<std::vector<char>> member((size_t)C.np, std::vector<char>(Pp.np, 0));
+    for (int j = 0; j < Pp.np; ++j)
+      for (int b = 0; b < ORD; ++b) {
+        dense[(colb_a[j] + b) % C.np][j] += T0.ph_w[(size_t)j * ORD + b];
+        member[(colb_a[j] + b) % C.np][j] = 1;
+      }
+    std::vector<int> colb_d(C.np), cnt_d(C.np);
+    int ntap = 0;
+    for (int c = 0; c < C.np; ++c) {
+      int first = -1, cnt = 0;
+      for (int j = 0; j < Pp.np; ++j)
+        if (member[c][j]) {
+          ++cnt;
+          if (!member[c][(j + Pp.np - 1) % Pp.np]) first = j;
+        }
+      if (first < 0 || cnt == Pp.np) {
+        err = "interpolation: transposed phi stencil is not a run at level " + std::to_string(l);
         return -1;
       }
-      ts = agg_rows;
-    }
-    std::vector<int> rng;
-    int cmax = 0;
-    size_t lds = agg_plan(ts, rng, cmax);
-    if (agg_rows == 0)
-      while (ts > 1 && lds > kLdsBudget) lds = agg_plan(--ts, rng, cmax);
-    if (lds > kLdsBudget) {  // largest boxes: one child per pass
-      nstage = 1;
-      lds = agg_plan(ts, rng, cmax);
-    }
-    if (lds > kLdsMax) {
-      err = "aggregation tile exceeds the LDS limit at level " + std::to_string(l);
-      return -1;
-    }
-    I.ts_agg = ts;
-    I.agg_stage = nstage;
-    I.crows_max = cmax;
-    I.lds_agg = lds;
-    if (int rc = put_i(I.strip_crow, rng, err)) return rc;
-    // disaggregation strips: at most kDisRows child rows; the staged parent
-    // rows ([rows][np_p + np_c]) and tables within the LDS budget
-    int stage_par = 1;  // parent rows staged in LDS
-    auto dis_plan = [&](int tsd, std::vector<int>& prng, int& pmax_rows) {
-      prng.clear();
-      pmax_rows = 0;
-      for (int c0 = 0; c0 < C.nt; c0 += tsd) {
-        int lo = Pp.nt, hi = -1;
-        for (int rr = c0; rr < std::min(C.nt, c0 + tsd); ++rr) {
-          lo = std::min(lo, T0.tth_lo[rr]);
-          hi = std::max(hi, T0.tth_hi[rr]);
+      for (int k = 0; k < cnt; ++k)
+        if (!member[c][(first + k) % Pp.np]) {
+          err = "interpolation: transposed phi stencil has a gap at level " + std::to_string(l);
+          return -1;
         }
-        prng.push_back(lo);
-        prng.push_back(hi);
-        pmax_rows = std::max(pmax_rows, hi - lo + 1);
-      }
-      // k_disaggregate: parent rows, the wrapped phi pass, both tap tables
-      return stage_par ? (size_t)pmax_rows * (Pp.np + C.np + C.np / 2) * sizeof(CT) +
-                             ((size_t)tsd * T0.tmax + (size_t)C.np * T0.pmax) * sizeof(Tap<T>)
-                       : (size_t)4 * Pp.np * sizeof(CT);  // two-pass path: k_dis_phi's row buffer
-    };
-    int tsd = C.nt;
-    while (tsd > 1 && (size_t)C.nx * C.ny * 2 * ((C.nt + tsd - 1) / tsd) < kMinBlocks) tsd = (tsd + 1) / 2;
-    if (dis_rows > 0) tsd = std::min(dis_rows, C.nt);
-    std::vector<int> prng;
-    int pmr = 0;
-    size_t ldsd = dis_plan(tsd, prng, pmr);
-    if (dis_rows == 0)
-      while (tsd > 1 && ldsd > kLdsBudget) ldsd = dis_plan(--tsd, prng, pmr);
-    if (ldsd > kLdsBudget || force_two_pass_) {  // largest boxes: two-pass path
-      stage_par = 0;
-      ldsd = dis_plan(tsd, prng, pmr);
+      colb_d[c] = first;
+      cnt_d[c] = cnt;
+      ntap = std::max(ntap, cnt);
     }
-    if (ldsd > kLdsMax) {
-      err = "disaggregation tile exceeds the LDS limit at level " + std::to_string(l);
+    ntap = ntap <= 8 ? 8 : ntap <= 12 ? 12 : ntap <= 16 ? 16 : -1;
+    if (ntap < 0) {
+      err = "interpolation: more than 16 transposed phi taps at level " + std::to_string(l);
       return -1;
     }
-    I.ts_dis = tsd;
-    I.dis_stage = stage_par;
-    I.prows_max = pmr;
-    I.lds_dis = ldsd;
-    if (int rc = put_i(I.strip_prow, prng, err)) return rc;
+    std::vector<double> colw_d((size_t)C.np * ntap, 0.0);
+    for (int c = 0; c < C.np; ++c)
+      for (int k = 0; k < cnt_d[c]; ++k)
+        colw_d[(size_t)c * ntap + k] = dense[c][(colb_d[c] + k) % Pp.np] * (double)C.np / (double)Pp.np;
+    // windows of the half-waves: strips of sw output columns (16 where half a
+    // row fits, so that a wave takes both components)
+    auto windows = [](int nout, int nin, const std::vector<int>& colb, int taps, std::vector<int>& wlo, int& nst,
+                      int& sw) {
+      const int ho = nout / 2;
+      sw = ho <= kIStrip / 2 ? kIStrip / 2 : kIStrip;
+      nst = (ho + sw - 1) / sw;
+      wlo.assign((size_t)2 * nst, 0);
+      int wl = 0;
+      for (int st = 0; st < nst; ++st)
+        for (int h = 0; h < 2; ++h) {
+          const int j0 = st * sw + h * ho, j1 = std::min(st * sw + sw, ho) - 1 + h * ho;
+          wlo[(size_t)st * 2 + h] = colb[j0];
+          wl = std::max(wl, (colb[j1] - colb[j0] + nin) % nin + taps);
+        }
+      return wl;
+    };
+    std::vector<int> wlo_a, wlo_d;
+    I.a_wlen = windows(Pp.np, C.np, colb_a, ORD, wlo_a, I.a_nst, I.a_sw);
+    I.d_wlen = windows(C.np, Pp.np, colb_d, ntap, wlo_d, I.d_nst, I.d_sw);
+    I.d_ntap = ntap;
+    // staged values per lane and row (kIStage for the aggregation's four
+    // children, kIStage / 2 parent values for the disaggregation)
+    if ((kIStrip / I.a_sw) * 8 * I.a_wlen > 64 * kIStage || (kIStrip / I.d_sw) * 2 * I.d_wlen > 64 * (kIStage / 2)) {
+      err = "interpolation: phi windows too wide at level " + std::to_string(l);
+      return -1;
+    }
+    // chunks per batch-size bucket
+    I.a_rows = agg_rows;
+    I.d_rows = dis_rows;
+    std::vector<int> ca, cdv, cpd;
+    const size_t nbp = (size_t)Pp.nx * Pp.ny;
+    for (int b = 0; b < 8; ++b) {
+      const size_t Rb = (size_t)std::min(kChunkR[b], 64);
+      // aggregation: chunks of parent rows
+      const size_t base_a = Rb * nbp * (I.a_sw == kIStrip ? 2 : 1) * I.a_nst;
+      int na = agg_rows > 0 ? (Pp.nt + agg_rows - 1) / agg_rows
+                            : (int)std::min<size_t>((kStreamItems + base_a - 1) / base_a,
+                                                    (size_t)std::max(1, Pp.nt / (2 * ORD)));
+      na = std::max(1, std::min(na, Pp.nt));
+      I.a_nch[b] = na;
+      I.a_coff[b] = (int)ca.size();
+      for (int i = 0; i <= na; ++i) ca.push_back((int)((long long)i * Pp.nt / na));
+      // disaggregation: chunks of extended child rows; interior cuts in
+      // [ORD, nt_c] so that a pole reflection stays with its row
+      const size_t base_d = Rb * nbp * (I.d_sw == kIStrip ? 2 : 1) * I.d_nst;
+      const int span = C.nt - ORD;
+      int nd = dis_rows > 0 ? (nvr + dis_rows - 1) / dis_rows
+                            : (int)std::min<size_t>((kStreamItems + base_d - 1) / base_d,
+                                                    (size_t)std::max(1, C.nt / (2 * ORD)));
+      nd = span <= 0 ? 1 : std::max(1, std::min(nd, span + 1));
+      I.d_nch[b] = nd;
+      I.d_coff[b] = (int)cdv.size();
+      cdv.push_back(0);
+      for (int i = 1; i < nd; ++i) cdv.push_back(ORD + (int)((long long)i * span / nd));
+      cdv.push_back(nvr);
+      for (int i = 0; i < nd; ++i) {
+        const int E0 = cdv[I.d_coff[b] + i], E1 = cdv[I.d_coff[b] + i + 1];
+        int pf = -1, pl = -1;
+        for (int p = 0; p < Pp.nt; ++p) {
+          if (pf < 0 && T0.th_s0[p] + ORD - 1 >= E0) pf = p;
+          if (T0.th_s0[p] <= E1 - 1) pl = p;
+        }
+        if (pf < 0 || pl < pf) {
+          err = "interpolation: empty disaggregation chunk at level " + std::to_string(l);
+          return -1;
+        }
+        cpd.push_back(pf);
+        cpd.push_back(pl);
+      }
+    }
+    std::vector<int> vflip(T0.vflip.begin(), T0.vflip.end());
+    std::vector<cd> E((size_t)2 * Pp.K);
+    for (int s2 = 0; s2 < Pp.K; ++s2) {
+      E[s2] = T0.phase[(size_t)3 * Pp.K + s2];           // child offset (+a/2, +a/2)
+      E[(size_t)Pp.K + s2] = T0.phase[(size_t)1 * Pp.K + s2];  // (+a/2, -a/2)
+    }
+    if (int rc = put_i(I.s0, T0.th_s0, err)) return rc;
+    if (int rc = put_i(I.vrow, T0.vrow, err)) return rc;
+    if (int rc = put_i(I.vflip, vflip, err)) return rc;
+    if (int rc = put_r(I.thw_a, T0.th_w, err)) return rc;
+    if (int rc = put_r(I.thw_d, thw_d, err)) return rc;
+    if (int rc = put_i(I.colb_a, colb_a, err)) return rc;
+    if (int rc = put_r(I.colw_a, T0.ph_w, err)) return rc;
+    if (int rc = put_i(I.colb_d, colb_d, err)) return rc;
+    if (int rc = put_r(I.colw_d, colw_d, err)) return rc;
+    if (int rc = put_i(I.wlo_a, wlo_a, err)) return rc;
+    if (int rc = put_i(I.wlo_d, wlo_d, err)) return rc;
+    if (int rc = put_c(I.E, E, err)) return rc;
+    if (int rc = put_i(I.chunk_a, ca, err)) return rc;
+    if (int rc = put_i(I.chunk_d, cdv, err)) return rc;
+    if (int rc = put_i(I.chunkp_d, cpd, err)) return rc;
     return 0;
   }
 
@@ -2120,6 +2200,16 @@ class EngineT final : public Engine {
   }
 
   int set_tuning(const std::vector<int>& agg_rows, const std::vector<int>& dis_rows, std::string& err) override {
+    for (int v : agg_rows)
+      if (v < 0) {
+        err = "row chunks must be >= 0 (0: planner)";
+        return -1;
+      }
+    for (int v : dis_rows)
+      if (v < 0) {
+        err = "row chunks must be >= 0 (0: planner)";
+        return -1;
+      }
     std::vector<int> pa, pd;
     get_tuning(pa, pd);
     clear_graphs();
@@ -2132,15 +2222,15 @@ class EngineT final : public Engine {
         return rc;
       }
     }
-    return R_alloc_ > 0 ? size_dis_tmp(R_alloc_, err) : 0;
+    return 0;
   }
 
   void get_tuning(std::vector<int>& agg_rows, std::vector<int>& dis_rows) const override {
     agg_rows.assign(std::max(ntl_, 1), 0);
     dis_rows.assign(std::max(ntl_, 1), 0);
     for (int l = 1; l < ntl_; ++l) {
-      agg_rows[l] = it_[l].ts_agg;
-      dis_rows[l - 1] = it_[l].ts_dis;
+      agg_rows[l] = it_[l].a_rows;
+      dis_rows[l - 1] = it_[l].d_rows;
     }
   }
 
@@ -2173,16 +2263,6 @@ class EngineT final : public Engine {
     return j;
   }
 
-  // two-pass disaggregation intermediate (largest boxes) for R RHS
-  int size_dis_tmp(int R, std::string& err) {
-    size_t tmp_max = 0;
-    for (int l = 0; l + 1 < ntl_; ++l)
-      if (!it_[l + 1].dis_stage)
-        tmp_max = std::max(tmp_max, (size_t)R * lv_[l + 1].nx * lv_[l + 1].ny * 2 * 4 * lv_[l + 1].nt * lv_[l].np);
-    if (tmp_max * sizeof(CT) > dis_tmp_.bytes) HIP_TRY(dis_tmp_.alloc(tmp_max * sizeof(CT)));
-    return 0;
-  }
-
   int ensure(int R, std::string& err) {
     if (R <= R_alloc_) return 0;
     for (int l = 0; l < ntl_; ++l) {
@@ -2194,7 +2274,6 @@ class EngineT final : public Engine {
       HIP_TRY(hipMemset(L.G.p, 0, bytes));
     }
     if (mfma_ && !near_uniform_) HIP_TRY(near_part_.alloc((size_t)R * 9 * P_ * 2 * n_ * sizeof(float)));
-    if (int rc = size_dis_tmp(R, err)) return rc;
     HIP_TRY(hipDeviceSynchronize());
     R_alloc_ = R;
     return 0;
@@ -2372,28 +2451,106 @@ class EngineT final : public Engine {
       launch(pr, k_translate<T>, dim3(xcd_grid(gath.total)), blk, 0u, st, gath, R);
     }
   }
-  // rt: 16-row MFMA tiles per block (1, 2 or 4; the jobs' tiles_m must use it)
+  // The FP32 job with its R right-hand sides folded into the columns and
+  // ct column tiles per block (ct divides R, so that a block stays within
+  // one group of columns sharing A)
+  static GemmJob fold_job(GemmJob j, int R, int ct) {
+    if (!j.A) return j;
+    j.fold = R;
+    j.ncols *= R;
+    j.tiles = j.tiles_m * ((j.ncols + 16 * ct - 1) / (16 * ct));
+    return j;
+  }
+  // rt: 16-row MFMA tiles per block (1, 2 or 4; the jobs' tiles_m must use
+  // it).  FP32: the RHS are folded into the columns and a block takes up to
+  // 4 column tiles, so one read of a block's A rows serves 64 columns;
+  // BF16-split: one grid layer per RHS.
   template <int Tag>
-  void launch_gemm(Pending& pr, int rt, const GemmJob& j0, const GemmJob& j1, int R, hipStream_t st) {
-    const int w = bf16_ ? 4 : kGemmW;  // waves per block
-    const int nt = gemm_blocks(j0, w) + gemm_blocks(j1, w);
-    const dim3 grid(j0.xcd ? xcd_grid(nt) : nt, 1, R);
+  void launch_gemm(Pending& pr, int rt, const GemmJob& j0u, const GemmJob& j1u, int R, hipStream_t st) {
     if (bf16_) {
+      const int nt = gemm_blocks(j0u, 4) + gemm_blocks(j1u, 4);
+      const dim3 grid(j0u.xcd ? xcd_grid(nt) : nt, 1, R);
       if (rt == 1)
-        launch(pr, k_gemm_bf16x3<1, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+        launch(pr, k_gemm_bf16x3<1, Tag>, grid, dim3(kBlock), 0u, st, j0u, j1u);
       else if (rt == 2)
-        launch(pr, k_gemm_bf16x3<2, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+        launch(pr, k_gemm_bf16x3<2, Tag>, grid, dim3(kBlock), 0u, st, j0u, j1u);
       else
-        launch(pr, k_gemm_bf16x3<4, Tag>, grid, dim3(kBlock), 0u, st, j0, j1);
+        launch(pr, k_gemm_bf16x3<4, Tag>, grid, dim3(kBlock), 0u, st, j0u, j1u);
       return;
     }
+    const int ct = R % 4 == 0 ? 4 : R % 2 == 0 ? 2 : 1;
+    const GemmJob j0 = fold_job(j0u, R, ct), j1 = fold_job(j1u, R, ct);
+    const int nt = gemm_blocks(j0, kGemmW) + gemm_blocks(j1, kGemmW);
+    const dim3 grid(j0.xcd ? xcd_grid(nt) : nt, 1, 1);
     const dim3 blk(64 * kGemmW);
-    if (rt == 1)
-      launch(pr, k_gemm_stream<1, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
-    else if (rt == 2)
-      launch(pr, k_gemm_stream<2, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+    if (ct == 4) {
+      if (rt == 1) launch(pr, k_gemm_stream<1, 4, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+      else if (rt == 2) launch(pr, k_gemm_stream<2, 4, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+      else launch(pr, k_gemm_stream<4, 4, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+    } else if (ct == 2) {
+      if (rt == 1) launch(pr, k_gemm_stream<1, 2, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+      else if (rt == 2) launch(pr, k_gemm_stream<2, 2, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+      else launch(pr, k_gemm_stream<4, 2, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+    } else {
+      if (rt == 1) launch(pr, k_gemm_stream<1, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+      else if (rt == 2) launch(pr, k_gemm_stream<2, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+      else launch(pr, k_gemm_stream<4, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+    }
+  }
+
+  // the disaggregation kernel of a stencil order, tap count and strip width
+  template <int ORD, int NT>
+  void launch_dis_nt(Pending& pr, bool two, dim3 g, uint32_t sh, hipStream_t st, const InterpArgs<T>& A) {
+    if (two)
+      launch(pr, k_dis_stream<T, ORD, NT, 16>, g, dim3(64), sh, st, A);
     else
-      launch(pr, k_gemm_stream<4, 1, Tag, kGemmW>, grid, blk, 0u, st, j0, j1);
+      launch(pr, k_dis_stream<T, ORD, NT, 32>, g, dim3(64), sh, st, A);
+  }
+  void launch_dis(Pending& pr, int order, int ntap, bool two, dim3 g, uint32_t sh, hipStream_t st,
+                  const InterpArgs<T>& A) {
+    if (order == 6) {
+      if (ntap == 8) launch_dis_nt<6, 8>(pr, two, g, sh, st, A);
+      else if (ntap == 12) launch_dis_nt<6, 12>(pr, two, g, sh, st, A);
+      else launch_dis_nt<6, 16>(pr, two, g, sh, st, A);
+    } else {
+      if (ntap == 8) launch_dis_nt<4, 8>(pr, two, g, sh, st, A);
+      else if (ntap == 12) launch_dis_nt<4, 12>(pr, two, g, sh, st, A);
+      else launch_dis_nt<4, 16>(pr, two, g, sh, st, A);
+    }
+  }
+
+  // Arguments of the streamed interpolation between level l - 1 (child) and
+  // l (parent) for R right-hand sides (chunk tables of batch bucket bk).
+  InterpArgs<T> interp_args(int l, int R, int bk, bool agg) const {
+    const Lvl &C = lv_[l - 1], &Pp = lv_[l];
+    const Itp& I = it_[l];
+    InterpArgs<T> A{};
+    A.src = agg ? C.S.template as<CT>() : Pp.G.template as<CT>();
+    A.dst = agg ? Pp.S.template as<CT>() : C.G.template as<CT>();
+    A.E = I.E.template as<CT>();
+    A.chunk = (agg ? I.chunk_a.template as<int>() : I.chunk_d.template as<int>()) + (agg ? I.a_coff[bk] : I.d_coff[bk]);
+    A.chunk_p = agg ? nullptr : I.chunkp_d.template as<int>() + 2 * (I.d_coff[bk] - bk);
+    A.s0 = I.s0.template as<int>();
+    A.thw = agg ? I.thw_a.template as<T>() : I.thw_d.template as<T>();
+    A.vrow = I.vrow.template as<int>();
+    A.vflip = I.vflip.template as<int>();
+    A.colb = agg ? I.colb_a.template as<int>() : I.colb_d.template as<int>();
+    A.colw = agg ? I.colw_a.template as<T>() : I.colw_d.template as<T>();
+    A.wlo = agg ? I.wlo_a.template as<int>() : I.wlo_d.template as<int>();
+    A.nxc = C.nx;
+    A.nyc = C.ny;
+    A.ntc = C.nt;
+    A.npc = C.np;
+    A.nxp = Pp.nx;
+    A.nyp = Pp.ny;
+    A.ntp = Pp.nt;
+    A.npp = Pp.np;
+    A.R = R;
+    A.nst = agg ? I.a_nst : I.d_nst;
+    A.nch = agg ? I.a_nch[bk] : I.d_nch[bk];
+    A.wlen = agg ? I.a_wlen : I.d_wlen;
+    A.ntap = agg ? I.order : I.d_ntap;
+    return A;
   }
 
   // One product y = Z x: near-field apply and leaf projection (one launch on
@@ -2455,56 +2612,37 @@ class EngineT final : public Engine {
       }
     }
     if (far) {
+      const int bk = chunk_bucket(R);
       for (int l = 1; l < ntl_; ++l) {
         const Lvl &C = lv_[l - 1], &Pp = lv_[l];
         const Itp& I = it_[l];
-        dim3 grid(Pp.nx * Pp.ny * 2, (Pp.nt + I.ts_agg - 1) / I.ts_agg, R);
-        size_t sh = I.lds_agg;
+        InterpArgs<T> A = interp_args(l, R, bk, true);
+        const int items = R * Pp.nx * Pp.ny * (I.a_sw == kIStrip ? 2 : 1) * I.a_nst * I.a_nch[bk];
         auto pr = begin("aggregate_l" + std::to_string(l),
                         cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
-                        2.0 * R * (double)C.nx * C.ny * 2 *
-                            (4.0 * (double)Pp.nt * C.np * I.order + 4.0 * Pp.K * I.order + 8.0 * Pp.K));
-        launch(pr, I.order == 6 ? k_aggregate<T, 6> : k_aggregate<T, 0>, grid, blk, sh, st, I.order, C.nx, C.ny, C.nt, C.np, Pp.nx, Pp.ny, Pp.nt,
-                           Pp.np, I.ts_agg, I.crows_max, C.S.template as<CT>(), Pp.S.template as<CT>(),
-                           I.th_row.template as<int>(), I.th_w.template as<T>(), I.th_flip.template as<int>(),
-                           I.ph_col.template as<int>(), I.ph_w.template as<T>(), I.phase.template as<CT>(),
-                           I.strip_crow.template as<int>(), I.agg_stage);
+                        2.0 * R * (double)Pp.nx * Pp.ny * 2 * 4 *
+                            (4.0 * (double)C.nt * Pp.np * I.order + 4.0 * Pp.K * I.order) + 16.0 * R * Pp.nx * Pp.ny * 2 * Pp.K);
+        const uint32_t sh = (uint32_t)(2 * (kIStrip / I.a_sw) * 8 * I.a_wlen * sizeof(CT));
+        const dim3 g(xcd_grid(items)), b64(64);
+        const bool two = I.a_sw != kIStrip;
+        if (I.order == 6)
+          launch(pr, two ? k_agg_stream<T, 6, 16> : k_agg_stream<T, 6, 32>, g, b64, sh, st, A);
+        else
+          launch(pr, two ? k_agg_stream<T, 4, 16> : k_agg_stream<T, 4, 32>, g, b64, sh, st, A);
       }
       launch_translations(R, st, cb);
-      for (int l = ntl_ - 1; l >= 0; --l) {
-        const Lvl& L = lv_[l];
-        if (l + 1 < ntl_) {
-          const Lvl& Pp = lv_[l + 1];
-          const Itp& I = it_[l + 1];
-          const int nstrips = (L.nt + I.ts_dis - 1) / I.ts_dis;
-          dim3 g2(xcd_grid(L.nx * L.ny * 2 * nstrips * R));
-          size_t sh = I.lds_dis;
-          auto pr = begin((I.dis_stage ? "disaggregate_l" : "disaggregate_phi_l") + std::to_string(l),
-                          cb * 2.0 * R * ((double)Pp.nx * Pp.ny * Pp.K + 2.0 * L.nx * L.ny * L.K),
-                          2.0 * R * (double)L.nx * L.ny * 2 *
-                              (4.0 * (double)Pp.nt * L.np * I.pmax + 4.0 * L.K * I.tmax + 8.0 * Pp.K));
-          if (!I.dis_stage) {  // largest boxes: phi pass into dis_tmp_, then theta pass
-            const int nbp = Pp.nx * Pp.ny;
-            const long nrows = (long)R * nbp * 2 * Pp.nt;
-            launch(pr, k_dis_phi<T>, dim3((unsigned)nrows), blk, (uint32_t)(4 * Pp.np * sizeof(CT)), st,
-                   nbp, Pp.nt, Pp.np, L.np, I.pmax, R, (const CT*)Pp.G.template as<CT>(),
-                   (const int*)I.tph_col.template as<int>(), (const T*)I.tph_w.template as<T>(),
-                   (const CT*)I.phase.template as<CT>(), dis_tmp_.template as<CT>());
-            const long nth = (long)R * L.nx * L.ny * 2 * L.K;
-            auto pt = begin("disaggregate_theta_l" + std::to_string(l), 0.0, 0.0);
-            launch(pt, k_dis_theta<T>, dim3((unsigned)std::min<long>((nth + kBlock - 1) / kBlock, 65535)), blk,
-                               0u, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.nt, I.tmax, R,
-                               (const CT*)dis_tmp_.template as<CT>(), (const int*)I.tth_row.template as<int>(),
-                               (const T*)I.tth_w.template as<T>(), (const int*)I.tth_flip.template as<int>(),
-                               L.G.template as<CT>(), Pp.ny);
-            continue;
-          }
-          launch(pr, k_disaggregate<T>, g2, blk, sh, st, L.nx, L.ny, L.nt, L.np, Pp.nx, Pp.ny, Pp.nt, Pp.np,
-                             I.ts_dis, I.tmax, I.pmax, I.prows_max, Pp.G.template as<CT>(), L.G.template as<CT>(),
-                             I.tth_row.template as<int>(), I.tth_w.template as<T>(), I.tth_flip.template as<int>(),
-                             I.strip_prow.template as<int>(), I.tph_col.template as<int>(),
-                             I.tph_w.template as<T>(), I.phase.template as<CT>(), nstrips, R);
-        }
+      for (int l = ntl_ - 2; l >= 0; --l) {
+        const Lvl &L = lv_[l], &Pp = lv_[l + 1];
+        const Itp& I = it_[l + 1];
+        InterpArgs<T> A = interp_args(l + 1, R, bk, false);
+        const int items = R * Pp.nx * Pp.ny * (I.d_sw == kIStrip ? 2 : 1) * I.d_nst * I.d_nch[bk];
+        // algorithmic bytes: the parent pattern read once (the child's
+        // translated pattern is read and written once more by this kernel)
+        auto pr = begin("disaggregate_l" + std::to_string(l), cb * 2.0 * R * (double)Pp.nx * Pp.ny * Pp.K,
+                        2.0 * R * (double)Pp.nx * Pp.ny * 2 * 4 *
+                            (4.0 * (double)Pp.nt * L.np * I.d_ntap + 4.0 * (double)Pp.nt * L.np * I.order));
+        const uint32_t sh = (uint32_t)(2 * (kIStrip / I.d_sw) * 8 * I.d_wlen * sizeof(CT));
+        launch_dis(pr, I.order, I.d_ntap, I.d_sw != kIStrip, dim3(xcd_grid(items)), sh, st, A);
       }
       if (near && near_grouped) near_sum();
       {
@@ -2639,9 +2777,9 @@ class EngineT final : public Engine {
     long long s = 0;
     for (auto& L : lv_) s += L.TL.bytes + L.S.bytes + L.G.bytes;
     for (auto& I : it_)
-      s += I.th_row.bytes + I.th_w.bytes + I.th_flip.bytes + I.ph_col.bytes + I.ph_w.bytes + I.tth_row.bytes +
-           I.tth_w.bytes + I.tth_flip.bytes + I.tth_lo.bytes + I.tth_hi.bytes + I.tph_col.bytes + I.tph_w.bytes +
-           I.phase.bytes;
+      s += I.s0.bytes + I.vrow.bytes + I.vflip.bytes + I.thw_a.bytes + I.thw_d.bytes + I.colb_a.bytes +
+           I.colw_a.bytes + I.colb_d.bytes + I.colw_d.bytes + I.wlo_a.bytes + I.wlo_d.bytes + I.E.bytes +
+           I.chunk_a.bytes + I.chunk_d.bytes + I.chunkp_d.bytes;
     s += Rm_.bytes + Qm_.bytes + near_mats_.bytes + zinv_.bytes + box_of_.bytes + order_.bytes + near_nbr_.bytes +
          near_slot_.bytes;
     return s;
@@ -2653,7 +2791,7 @@ class EngineT final : public Engine {
   int rt_np_ = 4, rt_recv_ = 4;  // MFMA GEMM row tiles (of 16) per block: near+projection, receive
   static constexpr size_t kLdsBudget = 48 * 1024;  // preferred tile size (occupancy)
   static constexpr size_t kLdsMax = 64 * 1024;     // hard limit per block
-  static constexpr size_t kMinBlocks = 1024;
+  static constexpr size_t kStreamItems = 4096;  // waves per streamed interpolation launch (target)
 
   template <typename U>
   static int put_raw(DevMem& d, const U* h, size_t count, std::string& err) {
@@ -2783,8 +2921,6 @@ class EngineT final : public Engine {
   DevMem Rm_, Qm_, rm_off_, qm_off_;
   DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;
   bool mfma_ = false, near_uniform_ = false;
-  // test switch: every disaggregation takes the two-pass path
-  bool force_two_pass_ = std::getenv("MLFMA_DIS_TWO_PASS") != nullptr;
   // translation kernel forced on every level: 0 = gathered lists, 1/2/3 = LDS
   // tiles of 4x4 / 8x4 / 8x8 boxes; -1 = per level (tiles of 4x4 on grids of
   // at least 8 x 8 boxes)
@@ -2798,7 +2934,6 @@ class EngineT final : public Engine {
   bool bf16_ = false;  // dense contractions as BF16-split matrix-core products
   DevMem gcol_part_, gcol_box_, a_off_proj_, a_off_recv_;  // class-grouped GEMM columns
   DevMem ng_bcol_, ng_ccol_, ng_aoff_, ng_has_, near_part_;  // class-pair near GEMM
-  DevMem dis_tmp_;                                            // two-pass disaggregation
   int ngcols_ = 0;
   int ncols_pad_ = 0;
   std::vector<V3> centers_;
@@ -2960,7 +3095,8 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
     HIP_TRY(hipMemcpyAsync(hcol, n1, (size_t)R * sizeof(Z), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     out.resize(R);
-    for (int r = 0; r < R; ++r) out[r] = std::sqrt(std::max(0.0, hcol[r].x));
+    for (int r = 0; r < R; ++r)  // NaN or Inf in the vector stays visible (max would drop a NaN)
+      out[r] = std::isfinite(hcol[r].x) ? std::sqrt(std::max(0.0, hcol[r].x)) : std::nan("");
     return 0;
   };
   hipLaunchKernelGGL(k_to_z<T>, dim3(grid1d(tot)), blk, 0, st, reinterpret_cast<const CT*>(bv), b, tot);
@@ -2970,6 +3106,22 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
     HIP_TRY(hipMemsetAsync(x, 0, tot * sizeof(Z), st));
   std::vector<double> bnorm, rnorm;
   if (int rc = norms(b, bnorm)) return rc;
+  // NaN or Inf anywhere in b (or in the guess) makes its squared norm
+  // non-finite: rejected before the first product
+  for (int r = 0; r < R; ++r)
+    if (!std::isfinite(bnorm[r])) {
+      err = "gmres: right-hand side " + std::to_string(r) + " holds NaN or Inf";
+      return -5;
+    }
+  if (use_x0) {
+    std::vector<double> xnorm;
+    if (int rc = norms(x, xnorm)) return rc;
+    for (int r = 0; r < R; ++r)
+      if (!std::isfinite(xnorm[r])) {
+        err = "gmres: initial guess " + std::to_string(r) + " holds NaN or Inf";
+        return -5;
+      }
+  }
   res.assign(R, GmresResult{});
   // residual r = b - Z x
   auto residual = [&](Z* out) -> int {

@@ -101,6 +101,9 @@ static void build_interp(const LevelGrid& c, const LevelGrid& p, int order, doub
     ext_row.push_back(c.nt - 1 - m);
     ext_flip.push_back(1);
   }
+  T.vrow = ext_row;
+  T.vflip.assign(ext_flip.begin(), ext_flip.end());
+  T.th_s0.assign(p.nt, 0);
   T.th_row.assign((size_t)p.nt * order, 0);
   T.th_w.assign((size_t)p.nt * order, 0.0);
   T.th_flip.assign((size_t)p.nt * order, 0);
@@ -111,6 +114,7 @@ static void build_interp(const LevelGrid& c, const LevelGrid& p, int order, doub
     int s0 = j0 - half + 1;
     if (s0 < 0 || s0 + order > (int)ext.size()) throw std::runtime_error("interp: theta stencil out of range");
     double wts[8];
+    T.th_s0[it] = s0;
     lagrange_weights(&ext[s0], order, th, wts);
     for (int a = 0; a < order; ++a) {
       const int e = s0 + a;

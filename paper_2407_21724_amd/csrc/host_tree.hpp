@@ -31,6 +31,12 @@ struct InterpTables {
   std::vector<int> th_row;
   std::vector<double> th_w;
   std::vector<uint8_t> th_flip;
+  // the same stencils on the extended child rows: `order/2` pole
+  // reflections, the nt_c rows, `order/2` reflections (virtual row e holds
+  // child row vrow[e], read half a turn on in phi where vflip[e]); parent
+  // row it uses virtual rows th_s0[it] .. th_s0[it] + order - 1
+  std::vector<int> th_s0, vrow;
+  std::vector<uint8_t> vflip;
   // forward phi: for each parent column, `order` (child column, weight)
   std::vector<int> ph_col;
   std::vector<double> ph_w;

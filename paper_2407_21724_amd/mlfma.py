@@ -32,7 +32,8 @@ class MlfmaError(RuntimeError):
 
 class Problem(C.Structure):
     _fields_ = [("n_particles", C.c_int32), ("centers", C.POINTER(C.c_double)),
-                ("class_id", C.POINTER(C.c_int32)), ("n_classes", C.c_int32)]
+                ("class_id", C.POINTER(C.c_int32)), ("n_classes", C.c_int32),
+                ("eps_bg_re", C.c_double), ("eps_bg_im", C.c_double)]
 
 
 class TreeParams(C.Structure):
@@ -178,10 +179,11 @@ def _stream_ptr(stream):
 class Context:
     """An mlfma_ctx: tree, classes and device tables of one particle array."""
 
-    def __init__(self, centers, class_id, n_classes: int, params: TreeParams | None = None):
+    def __init__(self, centers, class_id, n_classes: int, params: TreeParams | None = None, eps_bg=1.0):
         self._centers = np.ascontiguousarray(centers, np.float64)
         self._cls = np.ascontiguousarray(class_id, np.int32)
-        pb = Problem(len(self._centers), _dptr(self._centers), _iptr(self._cls), n_classes)
+        eb = complex(eps_bg)
+        pb = Problem(len(self._centers), _dptr(self._centers), _iptr(self._cls), n_classes, eb.real, eb.imag)
         self.params = params or default_params()
         h = C.c_void_p()
         rc = lib().mlfma_build_tree(C.byref(pb), C.byref(self.params), C.byref(h))

@@ -20,6 +20,11 @@ y = Z x for the seeded x = workloads.random_complex((P, 2N), seed=1):
                     scattered near field on the plane z = 1 over the array
                     (21 x 21 points) and the far-field amplitude on a
                     16 x 32 sphere grid
+  c5_sparse.npz     all 18 particles of the sparse full-extent lens
+                    (workloads c5_sparse: pairs at every level of the
+                    200 x 200 tree), full product and near part
+  c3_40x40_rows.npz rows of the 4 interior particles of the 40 x 40 array
+                    for 64 seeded right-hand sides (seed 2)
 """
 from __future__ import annotations
 
@@ -95,9 +100,57 @@ def make_lens_fields(name: str):
     print(f"{name}: classes {used}, solved and fields in {time.time() - t0:.1f} s -> {out}", flush=True)
 
 
+def make_sparse(name: str):
+    """All rows of the sparse full-extent lens (18 particles, 13 classes):
+    the full product and its near part (self + adjacent sites)."""
+    t0 = time.time()
+    wl = w.workload("c5_sparse")
+    used = sorted(set(wl.class_id.tolist()))
+    pcs = []
+    for c in used:
+        v, t, e = wl.meshes[c]
+        pcs.append(ParticleClass(v, t, e, wl.n_perp, wl.n_par, wl.eps_r))
+    compact = np.array([used.index(c) for c in wl.class_id], np.int32)
+    prob = DenseProblem(pcs, wl.centers, compact)
+    P, n = wl.n_particles, pcs[0].n
+    x = w.random_complex((P, n), SEED)
+    rows = np.arange(P)
+    prob.prefetch([(mu, nu) for mu in rows for nu in range(P)])
+    y = prob.matvec_rows(x, rows)
+    site = np.round(wl.centers[:, :2] / 0.5).astype(int)
+    ynear = np.array([sum(prob.block(mu, nu) @ x[nu] for nu in range(P)
+                          if np.abs(site[nu] - site[mu]).max() <= 1) for mu in rows])
+    out = os.path.join(HERE, name + ".npz")
+    np.savez_compressed(out, M=np.stack([pc.M for pc in pcs]), classes=np.array(used, np.int32), rows=rows, y=y,
+                        ynear=ynear, seed=SEED, eps_r=wl.eps_r, n_perp=wl.n_perp, n_par=wl.n_par)
+    print(f"{name}: {P} rows, classes {used} in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
+def make_batched_rows(name: str):
+    """Rows of 4 interior particles of the 40 x 40 array for 64 seeded
+    right-hand sides (x = random_complex((64, P, 2N), seed=2)): y [4][2N][64]."""
+    t0 = time.time()
+    wl = w.workload("c2")
+    rows = np.array([19 * 40 + 19, 19 * 40 + 20, 20 * 40 + 19, 20 * 40 + 20])
+    pc = _cylinder_class(wl)
+    prob = DenseProblem([pc], wl.centers, wl.class_id)
+    P, n = wl.n_particles, pc.n
+    X = w.random_complex((64, P, n), 2)
+    prob.prefetch([(mu, nu) for mu in rows for nu in range(P)])
+    y = prob.matvec_rows(np.transpose(X, (1, 2, 0)), rows)
+    out = os.path.join(HERE, name + ".npz")
+    np.savez_compressed(out, M=pc.M, rows=rows, y=y, seed=2, rhs=64, eps_r=wl.eps_r, n_perp=wl.n_perp,
+                        n_par=wl.n_par, nx=40, ny=40)
+    print(f"{name}: {len(rows)} rows x 64 RHS in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
 def make(name: str):
     if name == "c5_10x10_fields":
         return make_lens_fields(name)
+    if name == "c5_sparse":
+        return make_sparse(name)
+    if name == "c3_40x40_rows":
+        return make_batched_rows(name)
     if name.startswith("c4_"):
         return make_lens(name)
     t0 = time.time()

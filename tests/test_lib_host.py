@@ -37,11 +37,13 @@ def _problem(centers, cls, ncls=1, **kw):
 
 
 @pytest.mark.parametrize("case", ["off_lattice", "duplicate", "non_planar", "bad_class", "nan", "bad_order",
-                                  "bad_precision"])
+                                  "bad_precision", "lossy_background", "negative_background", "nan_background"])
 def test_build_tree_rejects(case):
     cen = w.lattice(3, 3, 0.5)
     cls = np.zeros(9, np.int32)
     kw = {}
+    eps_bg = {"lossy_background": 1.69 - 0.1j, "negative_background": -2.0,
+              "nan_background": complex(float("nan"), 0.0)}.get(case, 1.0)
     if case == "off_lattice":
         cen[4, 0] += 0.1
     elif case == "duplicate":
@@ -57,7 +59,15 @@ def test_build_tree_rejects(case):
     elif case == "bad_precision":
         kw["precision"] = 7
     with pytest.raises(mlfma.MlfmaError):
-        mlfma.Context(cen, cls, 1, mlfma.default_params(**kw))
+        mlfma.Context(cen, cls, 1, mlfma.default_params(**kw), eps_bg=eps_bg)
+
+
+def test_background_permittivity_accepted():
+    """A real, positive background permittivity (and 0, read as vacuum) is
+    accepted by the host-only tree build."""
+    cen = w.lattice(3, 3, 0.5)
+    for eb in (1.0, 1.69, 0.0):
+        mlfma.Context(cen, np.zeros(9, np.int32), 1, mlfma.default_params(), eps_bg=eb).close()
 
 
 def test_tree_levels_and_truncation():

@@ -293,7 +293,9 @@ def workload(name: str, nx: int | None = None, ny: int | None = None) -> Workloa
     diameters from the focusing profile of ``lens_diameters`` (focal length
     20), 32 diameter classes, one mesh per class (jitter seed 2407 + class).
     ``c5``: the 200x200 lens (focal length 50) with 16 incidences tilted up
-    to 20 degrees.  ``nx``/``ny`` give a smaller lens of the same recipe."""
+    to 20 degrees.  ``nx``/``ny`` give a smaller lens of the same recipe.
+    ``c5_sparse``: 18 particles of the c5 lens at the sites SPARSE_SITES,
+    spanning its full 200 x 200 extent (all seven tree levels)."""
     name = name.lower()
     if name == "c1":
         nx, ny = nx or 4, ny or 4
@@ -315,4 +317,22 @@ def workload(name: str, nx: int | None = None, ny: int | None = None) -> Workloa
         meshes = [_mesh_with_edges(cylinder(float(d), 0.6, seed=2407 + c)) for c, d in enumerate(dia)]
         inc = [normal_incidence_x()] if name == "c4" else tilted_incidences(16, 20.0)
         return Workload(name, lattice(nx, ny, 0.5), cls, meshes, 6.25 + 0j, 15, 15, 0.5, inc)
+    if name == "c5_sparse":
+        # 18 particles of the 200x200 lens at sites spread over the whole
+        # aperture (the corners fix the extent), so that particle pairs are
+        # separated at every level of its tree; each keeps the class the
+        # lens gives its site
+        cls, dia = lens_diameters(200, 200, 0.5, 50.0)
+        meshes = [_mesh_with_edges(cylinder(float(d), 0.6, seed=2407 + c)) for c, d in enumerate(dia)]
+        sites = np.array(SPARSE_SITES)
+        cen = np.zeros((len(sites), 3))
+        cen[:, :2] = 0.5 * sites
+        return Workload(name, cen, cls[sites[:, 1] * 200 + sites[:, 0]], meshes, 6.25 + 0j, 15, 15, 0.5,
+                        tilted_incidences(2, 20.0))
     raise ValueError(f"unknown workload {name}")
+
+
+# (ix, iy) lattice sites of the sparse full-extent lens: pairs adjacent (near
+# field) and separated at each of the seven levels of the 200 x 200 tree
+SPARSE_SITES = [(0, 0), (2, 0), (0, 5), (9, 3), (20, 1), (37, 12), (70, 40), (120, 30), (199, 199), (150, 180),
+                (100, 100), (101, 100), (100, 101), (60, 140), (10, 190), (190, 10), (130, 130), (103, 98)]
