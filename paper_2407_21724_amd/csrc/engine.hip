@@ -596,13 +596,21 @@ template <typename T>
 __device__ __forceinline__ C2<T> shfl_x32(C2<T> v) {
   return {__shfl_xor(v.x, 32), __shfl_xor(v.y, 32)};
 }
+// Read-only tables indexed uniformly over the wave (rows, stencil starts,
+// theta weights), read through the constant address space so that they
+// become scalar loads: a vector load of them would make the wave wait for
+// every load in flight, the next row's prefetch included.
+template <typename U>
+__device__ __forceinline__ const __attribute__((address_space(4))) U* uni(const U* p) {
+  return (const __attribute__((address_space(4))) U*)p;
+}
 
 // S_P = sum over the children q of phase_q . (Theta Phi S_q)
 template <typename T, int ORD, int SW>
 __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   constexpr int G = kIStrip / SW;  // components per wave
   extern __shared__ unsigned char smem_raw[];
-  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);  // [2 buffers][G][4 children][2 halves][wlen]
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);  // [2 buffers][64 KS]: [G][4 children][2 halves][wlen]
   const int nbp = A.nxp * A.nyp, nbc = A.nxc * A.nyc;
   const int ncomp = 2 / G;
   const int total = A.R * nbp * ncomp * A.nst * A.nch;
@@ -627,34 +635,42 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   T w[ORD];
 #pragma unroll
   for (int b = 0; b < ORD; ++b) w[b] = A.colw[j * ORD + b];
-  int off = A.colb[j] - A.wlo[st * 2 + h];
+  int off = A.colb[j] - uni(A.wlo)[st * 2 + h];
   if (off < 0) off += A.npc;
   const int lofs = ((g * 4) * 2 + h) * wl + off;  // + q * 2 * wl + buffer * nbuf
-  // staging: value v of a row goes to buffer slot v = ((g * 4 + q) * 2 + hh) * wl + c
+  // staging: value v of a row goes to buffer slot v = ((g * 4 + q) * 2 + hh) * wl + c;
+  // its source as an offset into this RHS's child patterns (-1: no child)
+  constexpr int KS = SW == kIStrip ? kIStage / 2 : 3 * kIStage / 4;
   const int PI = pb % A.nxp, PJ = pb / A.nxp;
-  const C2<T>* sp[kIStage];
-  int nst_l = 0;
+  const C2<T>* __restrict__ srcr = A.src + (size_t)r * nbc * 2 * Kc;
+  // (every lane loads and stores KS values: a missing child or a slot past
+  // the windows reads a valid address and stores zero, so that no load is
+  // conditional and the next row's loads stay in flight)
+  int so[KS];
+  unsigned zmask = 0;
 #pragma unroll
-  for (int k = 0; k < kIStage; ++k) {
+  for (int k = 0; k < KS; ++k) {
     const int v = lane + 64 * k;
-    sp[k] = nullptr;
+    so[k] = 0;
+    bool live = false;
     if (v < nbuf) {
-      nst_l = k + 1;
       const int c = v % wl, rest = v / wl, hh = rest & 1, q = (rest >> 1) & 3, gg = rest >> 3;
       const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
-      const int col = (A.wlo[st * 2 + hh] + c) % A.npc;
-      if (ci < A.nxc && cj < A.nyc)
-        sp[k] = A.src + (((size_t)r * nbc + cj * A.nxc + ci) * 2 + comp0 + gg) * Kc + col;
+      const int col = (uni(A.wlo)[st * 2 + hh] + c) % A.npc;
+      if (ci < A.nxc && cj < A.nyc) {
+        so[k] = ((cj * A.nxc + ci) * 2 + comp0 + gg) * Kc + col;
+        live = true;
+      }
     }
+    if (!live) zmask |= 1u << k;
   }
-  const int p0 = A.chunk[ch], p1 = A.chunk[ch + 1];
-  const int e0 = A.s0[p0], e1 = A.s0[p1 - 1] + ORD;
-  C2<T> nxt[kIStage];
+  const int p0 = uni(A.chunk)[ch], p1 = uni(A.chunk)[ch + 1];
+  const int e0 = uni(A.s0)[p0], e1 = uni(A.s0)[p1 - 1] + ORD;
+  C2<T> nxt[KS];
   auto fetch = [&](int e) {
-    const size_t ro = (size_t)A.vrow[e] * A.npc;
+    const int ro = uni(A.vrow)[e] * A.npc;
 #pragma unroll
-    for (int k = 0; k < kIStage; ++k)
-      if (k < nst_l) nxt[k] = sp[k] ? sp[k][ro] : C2<T>{0, 0};
+    for (int k = 0; k < KS; ++k) nxt[k] = srcr[so[k] + ((zmask >> k) & 1 ? 0 : ro)];
   };
   fetch(e0);
   C2<T> win[4][ORD];
@@ -665,10 +681,19 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   C2<T>* __restrict__ out = A.dst + (((size_t)r * nbp + pb) * 2 + comp) * Kp + j;
   int pn = p0;
   for (int e = e0; e < e1; ++e) {
-    C2<T>* buf = lds + (e & 1) * nbuf;
+    C2<T>* buf = lds + (e & 1) * 64 * KS;
 #pragma unroll
-    for (int k = 0; k < kIStage; ++k)
-      if (k < nst_l) buf[lane + 64 * k] = nxt[k];
+    for (int k = 0; k < KS; ++k) buf[lane + 64 * k] = (zmask >> k) & 1 ? C2<T>{0, 0} : nxt[k];
+    // the phases of the parent rows this extended row finishes (loaded before
+    // the next row's values, so that using them waits for these only)
+    C2<T> ea1[3], ea2[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int pu = min(pn + u, p1 - 1);
+      const size_t sidx = (size_t)pu * A.npp + j;
+      ea1[u] = A.E[sidx];
+      ea2[u] = A.E[(size_t)Kp + sidx];
+    }
     if (e + 1 < e1) fetch(e + 1);
     __syncthreads();
     C2<T> f[4];
@@ -684,7 +709,7 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       }
       f[q] = v;
     }
-    if (A.vflip[e]) {
+    if (uni(A.vflip)[e]) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) f[q] = shfl_x32(f[q]);
     }
@@ -694,9 +719,15 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       for (int a = 0; a + 1 < ORD; ++a) win[q][a] = win[q][a + 1];
       win[q][ORD - 1] = f[q];
     }
-    // parent rows whose theta stencil ends at this extended row
-    while (pn < p1 && A.s0[pn] + ORD - 1 == e) {
-      const T* __restrict__ tw = A.thw + pn * ORD;
+    // parent rows whose theta stencil ends at this extended row (at most 3):
+    // all three candidates are formed, since their phases are in flight for
+    // every row, and the ones that end here are stored
+    int nemit = 0;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int pu = min(pn + u, p1 - 1);
+      const bool ends = pn + u < p1 && uni(A.s0)[pn + u] + ORD - 1 == e;
+      const auto tw = uni(A.thw) + pu * ORD;
       C2<T> v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -709,14 +740,14 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       }
       // phases: child 3 = (+, +) -> E1, child 0 = conj(E1), child 1 =
       // (+, -) -> E2, child 2 = conj(E2)
-      const size_t s = (size_t)pn * A.npp + j;
-      const C2<T> a1 = A.E[s], a2 = A.E[(size_t)Kp + s];
+      const C2<T> a1 = ea1[u], a2 = ea2[u];
       C2<T> o;
       o.x = a1.x * (v[3].x + v[0].x) - a1.y * (v[3].y - v[0].y) + a2.x * (v[1].x + v[2].x) - a2.y * (v[1].y - v[2].y);
       o.y = a1.x * (v[3].y + v[0].y) + a1.y * (v[3].x - v[0].x) + a2.x * (v[1].y + v[2].y) + a2.y * (v[1].x - v[2].x);
-      if (valid) out[(size_t)pn * A.npp] = o;
-      ++pn;
+      if (ends && valid) out[(size_t)pu * A.npp] = o;
+      nemit += ends ? 1 : 0;
     }
+    pn += nemit;
   }
 }
 
@@ -758,52 +789,57 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
   T w[NT];
 #pragma unroll
   for (int k = 0; k < NT; ++k) w[k] = A.colw[c * NT + k];
-  int off = A.colb[c] - A.wlo[st * 2 + h];
+  int off = A.colb[c] - uni(A.wlo)[st * 2 + h];
   if (off < 0) off += A.npp;
   const int lofs = (g * 4 * 2 + h) * wl + off;
   const int PI = pb % A.nxp, PJ = pb / A.nxp;
-  C2<T>* cdst[4];
+  // the four children's patterns at this lane's column, as offsets into
+  // this RHS's child patterns (-1: no child, or an idle lane)
+  C2<T>* __restrict__ dstr = A.dst + (size_t)r * nbc * 2 * Kc;
+  int co[4];
+  unsigned cmask = 0;  // children this lane writes
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
-    cdst[q] = (valid && ci < A.nxc && cj < A.nyc) ? A.dst + (((size_t)r * nbc + cj * A.nxc + ci) * 2 + comp) * Kc + c
-                                                  : nullptr;
+    const bool has = valid && ci < A.nxc && cj < A.nyc;
+    co[q] = has ? ((cj * A.nxc + ci) * 2 + comp) * Kc + c : 0;
+    if (has) cmask |= 1u << q;
   }
   // staging: parent value v of a row (component gg, half hh, window column
   // k) times the conjugate phases of the four children goes to slots
   // ((gg * 4 + q) * 2 + hh) * wl + k
-  constexpr int KS = kIStage / 2;
+  constexpr int KS = 3 * kIStage / 8;
   const int nv = G * 2 * wl;
-  const C2<T>* gsrc[KS];
-  int scol[KS], sslot[KS];
-  int nst_l = 0;
+  const C2<T>* __restrict__ gpr = A.src + ((size_t)r * nbp + pb) * 2 * Kp;
+  // (every lane loads KS values; a value past the windows reads column 0
+  // and goes to spare slots after the buffer, so that no load is
+  // conditional and the next row's loads stay in flight)
+  int scol[KS], sslot[KS], sgo[KS];
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
     const int v = lane + 64 * k;
-    gsrc[k] = nullptr;
     scol[k] = 0;
-    sslot[k] = 0;
+    sslot[k] = nbuf + lane;
+    sgo[k] = comp0 * Kp;
     if (v < nv) {
-      nst_l = k + 1;
       const int kk = v % wl, rest = v / wl, hh = rest & 1, gg = rest >> 1;
-      scol[k] = (A.wlo[st * 2 + hh] + kk) % A.npp;
+      scol[k] = (uni(A.wlo)[st * 2 + hh] + kk) % A.npp;
       sslot[k] = (gg * 8 + hh) * wl + kk;
-      gsrc[k] = A.src + (((size_t)r * nbp + pb) * 2 + comp0 + gg) * Kp + scol[k];
+      sgo[k] = (comp0 + gg) * Kp + scol[k];
     }
   }
-  const int E0 = A.chunk[ch], E1 = A.chunk[ch + 1];
-  const int pfirst = A.chunk_p[2 * ch], plast = A.chunk_p[2 * ch + 1];
+  const int E0 = uni(A.chunk)[ch], E1 = uni(A.chunk)[ch + 1];
+  const int pfirst = uni(A.chunk_p)[2 * ch], plast = uni(A.chunk_p)[2 * ch + 1];
   const int half = ORD / 2, nvr = A.ntc + ORD;
   C2<T> ng[KS], ne1[KS], ne2[KS];
   auto fetch = [&](int p) {
-    const size_t ro = (size_t)p * A.npp;
+    const int ro = p * A.npp;
 #pragma unroll
-    for (int k = 0; k < KS; ++k)
-      if (k < nst_l) {
-        ng[k] = gsrc[k][ro];
-        ne1[k] = A.E[ro + scol[k]];
-        ne2[k] = A.E[(size_t)Kp + ro + scol[k]];
-      }
+    for (int k = 0; k < KS; ++k) {
+      ng[k] = gpr[sgo[k] + ro];
+      ne1[k] = A.E[ro + scol[k]];
+      ne2[k] = A.E[Kp + ro + scol[k]];
+    }
   };
   fetch(pfirst);
   C2<T> acc[4][ORD];
@@ -811,25 +847,25 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int a = 0; a < ORD; ++a) acc[q][a] = C2<T>{0, 0};
-  int ew = A.s0[pfirst];  // extended child row held in acc[.][0]
-  // the oldest held row's translated child values, loaded ahead of its flush
+  int ew = uni(A.s0)[pfirst];  // extended child row held in acc[.][0]
+  // the oldest held row's translated child values: loaded once per parent
+  // row, every row the same loads (so that the next row's loads, issued
+  // after them, stay in flight while the flush waits for these)
   C2<T> pend[4];
   auto load_pend = [&]() {
-    if (ew >= E0 && ew < E1 && ew < nvr) {
-      const size_t o = (size_t)A.vrow[ew] * A.npc;
+    const int o = uni(A.vrow)[min(ew, nvr - 1)] * A.npc;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) pend[q] = cdst[q] ? cdst[q][o] : C2<T>{0, 0};
-    }
+    for (int q = 0; q < 4; ++q) pend[q] = dstr[co[q] + o];
   };
   load_pend();
   // adds the oldest held row to its child row (if this chunk owns it) and
   // shifts the window
   auto flush = [&]() {
     if (ew >= E0 && ew < E1) {
-      const size_t o = (size_t)A.vrow[ew] * A.npc;
+      const int o = uni(A.vrow)[ew] * A.npc;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (cdst[q]) cdst[q][o] = {pend[q].x + acc[q][0].x, pend[q].y + acc[q][0].y};
+        if ((cmask >> q) & 1) dstr[co[q] + o] = {pend[q].x + acc[q][0].x, pend[q].y + acc[q][0].y};
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -838,23 +874,28 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
       acc[q][ORD - 1] = C2<T>{0, 0};
     }
     ++ew;
-    load_pend();
   };
   for (int p = pfirst; p <= plast; ++p) {
-    const int spp = A.s0[p];
-    while (ew < spp) flush();
-    C2<T>* buf = lds + (p & 1) * nbuf;
+    const int spp = uni(A.s0)[p];
+    if (ew < spp) {
+      flush();
+      while (ew < spp) {  // a second row finished by the same parent row (rare)
+        load_pend();
+        flush();
+      }
+    }
+    load_pend();
+    C2<T>* buf = lds + (p & 1) * (nbuf + 6 * wl + 64);
     // child 0: E1 g, child 1: conj(E2) g, child 2: E2 g, child 3: conj(E1) g
 #pragma unroll
-    for (int k = 0; k < KS; ++k)
-      if (k < nst_l) {
+    for (int k = 0; k < KS; ++k) {
         C2<T>* d = buf + sslot[k];
         d[0] = cmul(ne1[k], ng[k]);
         d[2 * wl] = cmul_conj_a(ne2[k], ng[k]);
         d[4 * wl] = cmul(ne2[k], ng[k]);
         d[6 * wl] = cmul_conj_a(ne1[k], ng[k]);
       }
-    if (p < plast) fetch(p + 1);
+    fetch(min(p + 1, plast));
     __syncthreads();
     C2<T> f[4];
 #pragma unroll
@@ -869,14 +910,14 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
       }
       f[q] = v;
     }
-    const T* __restrict__ tw = A.thw + p * ORD;
+    const auto tw = uni(A.thw) + p * ORD;
     if (spp < half || spp + ORD > half + A.ntc) {  // a tap on a pole reflection
       C2<T> gx[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) gx[q] = shfl_x32(f[q]);
 #pragma unroll
       for (int a = 0; a < ORD; ++a) {
-        const bool fl = A.vflip[spp + a] != 0;
+        const bool fl = uni(A.vflip)[spp + a] != 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const C2<T> z = fl ? gx[q] : f[q];
@@ -895,7 +936,10 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
     }
   }
   const int eend = min(E1, nvr);
-  while (ew < eend) flush();
+  while (ew < eend) {
+    flush();
+    load_pend();
+  }
 }
 
 // -------------------------------------------------------------- translate --
@@ -2030,6 +2074,18 @@ class EngineT final : public Engine {
           return -1;
         }
       }
+    {
+      std::vector<int> ends(nvr, 0);
+      for (int p = 0; p < Pp.nt; ++p)
+        if (++ends[T0.th_s0[p] + ORD - 1] > 3) {
+          err = "interpolation: more than 3 parent rows end at one child row at level " + std::to_string(l);
+          return -1;
+        }
+      if (C.nt < ORD) {
+        err = "interpolation: fewer child rows than stencil points at level " + std::to_string(l);
+        return -1;
+      }
+    }
     std::vector<double> thw_d((size_t)Pp.nt * ORD);
     for (int p = 0; p < Pp.nt; ++p)
       for (int a = 0; a < ORD; ++a)
@@ -2107,9 +2163,10 @@ class EngineT final : public Engine {
     I.a_wlen = windows(Pp.np, C.np, colb_a, ORD, wlo_a, I.a_nst, I.a_sw);
     I.d_wlen = windows(C.np, Pp.np, colb_d, ntap, wlo_d, I.d_nst, I.d_sw);
     I.d_ntap = ntap;
-    // staged values per lane and row (kIStage for the aggregation's four
-    // children, kIStage / 2 parent values for the disaggregation)
-    if ((kIStrip / I.a_sw) * 8 * I.a_wlen > 64 * kIStage || (kIStrip / I.d_sw) * 2 * I.d_wlen > 64 * (kIStage / 2)) {
+    // staged values per lane and row: the aggregation's four children (4, or
+    // 6 with two components per wave), the disaggregation's parent (3)
+    const int ks_a = I.a_sw == kIStrip ? kIStage / 2 : 3 * kIStage / 4, ks_d = 3 * kIStage / 8;
+    if ((kIStrip / I.a_sw) * 8 * I.a_wlen > 64 * ks_a || (kIStrip / I.d_sw) * 2 * I.d_wlen > 64 * ks_d) {
       err = "interpolation: phi windows too wide at level " + std::to_string(l);
       return -1;
     }
@@ -2622,7 +2679,7 @@ class EngineT final : public Engine {
                         cb * 2.0 * R * ((double)C.nx * C.ny * C.K + (double)Pp.nx * Pp.ny * Pp.K),
                         2.0 * R * (double)Pp.nx * Pp.ny * 2 * 4 *
                             (4.0 * (double)C.nt * Pp.np * I.order + 4.0 * Pp.K * I.order) + 16.0 * R * Pp.nx * Pp.ny * 2 * Pp.K);
-        const uint32_t sh = (uint32_t)(2 * (kIStrip / I.a_sw) * 8 * I.a_wlen * sizeof(CT));
+        const uint32_t sh = (uint32_t)(2 * 64 * (I.a_sw == kIStrip ? kIStage / 2 : 3 * kIStage / 4) * sizeof(CT));
         const dim3 g(xcd_grid(items)), b64(64);
         const bool two = I.a_sw != kIStrip;
         if (I.order == 6)
@@ -2641,7 +2698,7 @@ class EngineT final : public Engine {
         auto pr = begin("disaggregate_l" + std::to_string(l), cb * 2.0 * R * (double)Pp.nx * Pp.ny * Pp.K,
                         2.0 * R * (double)Pp.nx * Pp.ny * 2 * 4 *
                             (4.0 * (double)Pp.nt * L.np * I.d_ntap + 4.0 * (double)Pp.nt * L.np * I.order));
-        const uint32_t sh = (uint32_t)(2 * (kIStrip / I.d_sw) * 8 * I.d_wlen * sizeof(CT));
+        const uint32_t sh = (uint32_t)(2 * ((kIStrip / I.d_sw) * 8 * I.d_wlen + 6 * I.d_wlen + 64) * sizeof(CT));
         launch_dis(pr, I.order, I.d_ntap, I.d_sw != kIStrip, dim3(xcd_grid(items)), sh, st, A);
       }
       if (near && near_grouped) near_sum();
