@@ -1052,8 +1052,11 @@ template <typename T>
 struct alignas(16) Vec16 {
   C2<T> c[16 / sizeof(C2<T>)];
 };
+// A block takes one tile and sample chunk for `rpb` consecutive RHS: the 49
+// operators are staged once, and the next RHS's halo is loaded into
+// registers while the current one is summed.
 template <typename T, int TX, int TY>
-__global__ __launch_bounds__(kBlock) void k_translate_tiled(TrLevels<T> L, int R) {
+__global__ __launch_bounds__(kBlock) void k_translate_tiled(TrLevels<T> L, int R, int rpb) {
   constexpr int NS = TrNS<T>::v, HX = TX + 6, HY = TY + 6;
   constexpr int VPU = 16 / sizeof(C2<T>), NV = NS / VPU;  // complex values per load, loads per row
   constexpr int NSL = HY * HX * 2 * NV, NTL = 49 * NV;    // loads of the halo and of the operators
@@ -1071,51 +1074,135 @@ __global__ __launch_bounds__(kBlock) void k_translate_tiled(TrLevels<T> L, int R
   const int tx = (nx + TX - 1) / TX, ntile = tx * ((ny + TY - 1) / TY);
   const int nch = (K + NS - 1) / NS;
   const int tile = lb % ntile, rest = lb / ntile;
-  const int ch = rest % nch, r = rest / nch;
+  const int ch = rest % nch, rg = rest / nch;
+  const int r0 = rg * rpb, r1 = min(R, r0 + rpb);
   const int bx0 = (tile % tx) * TX, by0 = (tile / tx) * TY, s0 = ch * NS;
   const int nb = nx * ny;
-  const C2<T>* __restrict__ Sr = S + (size_t)r * nb * 2 * K;
-  // all loads of this thread in flight at once, then the LDS stores (K is
-  // even and chunks start at multiples of NS, so a 16-byte unit never
-  // straddles the end of a pattern)
-  Vec16<T> bs[IS], bt[IT];
+  // this thread's halo loads: source offset within one RHS's patterns (-1:
+  // outside the grid or past the pattern's end, a zero)
+  int hoff[IS];
 #pragma unroll
   for (int u = 0; u < IS; ++u) {
     const int i = threadIdx.x + u * kBlock;
-    bs[u] = Vec16<T>{};
+    hoff[u] = -1;
     if (i < NSL) {
       const int s = (i % NV) * VPU, t = i / NV;
       const int h = t >> 1, gx = bx0 - 3 + h % HX, gy = by0 - 3 + h / HX;
       if (gx >= 0 && gy >= 0 && gx < nx && gy < ny && s0 + s < K)
-        bs[u] = *reinterpret_cast<const Vec16<T>*>(Sr + ((size_t)(gy * nx + gx) * 2 + (t & 1)) * K + s0 + s);
+        hoff[u] = ((gy * nx + gx) * 2 + (t & 1)) * K + s0 + s;
     }
   }
+  Vec16<T> bs[IS];
+  auto fetch = [&](int r) {
+    const C2<T>* __restrict__ Sr = S + (size_t)r * nb * 2 * K;
+#pragma unroll
+    for (int u = 0; u < IS; ++u) bs[u] = hoff[u] >= 0 ? *reinterpret_cast<const Vec16<T>*>(Sr + hoff[u]) : Vec16<T>{};
+  };
+  fetch(r0);
+  // the operators (K is even and chunks start at multiples of NS, so a
+  // 16-byte unit never straddles the end of a pattern)
 #pragma unroll
   for (int u = 0; u < IT; ++u) {
     const int i = threadIdx.x + u * kBlock;
-    bt[u] = Vec16<T>{};
     if (i < NTL) {
       const int s = (i % NV) * VPU, o = i / NV;
-      if (s0 + s < K) bt[u] = *reinterpret_cast<const Vec16<T>*>(TL + (size_t)o * K + s0 + s);
+      sTv[i] = s0 + s < K ? *reinterpret_cast<const Vec16<T>*>(TL + (size_t)o * K + s0 + s) : Vec16<T>{};
     }
   }
-#pragma unroll
-  for (int u = 0; u < IS; ++u)
-    if (threadIdx.x + u * kBlock < NSL) sSv[threadIdx.x + u * kBlock] = bs[u];
-#pragma unroll
-  for (int u = 0; u < IT; ++u)
-    if (threadIdx.x + u * kBlock < NTL) sTv[threadIdx.x + u * kBlock] = bt[u];
-  __syncthreads();
   const C2<T>* __restrict__ sS = sSv[0].c;
   const C2<T>* __restrict__ sT = sTv[0].c;
   const int lane = threadIdx.x & 63;
-  C2<T>* __restrict__ Gr = G + (size_t)r * nb * 2 * K;
-  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // wave index = box parity
-    case 0: tr_tile_sums<T, TX, TY, 0, 0>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
-    case 1: tr_tile_sums<T, TX, TY, 1, 0>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
-    case 2: tr_tile_sums<T, TX, TY, 0, 1>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
-    default: tr_tile_sums<T, TX, TY, 1, 1>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+  for (int r = r0; r < r1; ++r) {
+    if (r > r0) __syncthreads();  // the previous RHS's sums have read the halo
+#pragma unroll
+    for (int u = 0; u < IS; ++u)
+      if (threadIdx.x + u * kBlock < NSL) sSv[threadIdx.x + u * kBlock] = bs[u];
+    if (r + 1 < r1) fetch(r + 1);
+    __syncthreads();
+    C2<T>* __restrict__ Gr = G + (size_t)r * nb * 2 * K;
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {  // wave index = box parity
+      case 0: tr_tile_sums<T, TX, TY, 0, 0>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+      case 1: tr_tile_sums<T, TX, TY, 1, 0>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+      case 2: tr_tile_sums<T, TX, TY, 0, 1>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+      default: tr_tile_sums<T, TX, TY, 1, 1>(sS, sT, lane, bx0, by0, s0, nx, ny, K, Gr); break;
+    }
   }
+}
+
+// FP32 translation with no LDS: one wave per 4 x 4 tile of receiving boxes
+// and 64 consecutive samples (one per lane).  A lane holds the 40 operators
+// of its sample that a tile uses (offsets with |dx| or |dy| >= 2) and the
+// 16 boxes' two sums in registers, and reads each of the tile's 10 x 10
+// source boxes once; the interaction lists are known at compile time (a
+// tile starts at even box indices, so a receiver's parity fixes its list).
+// Terms are added in the order of the gathered lists (dy outer, dx inner).
+constexpr int kTrRegTile = 4;
+__host__ __device__ constexpr bool tr_in_list(int rx, int ry, int dx, int dy) {
+  return (dx < -1 || dx > 1 || dy < -1 || dy > 1) && dx >= ((rx & 1) ? -3 : -2) && dx <= ((rx & 1) ? 2 : 3) &&
+         dy >= ((ry & 1) ? -3 : -2) && dy <= ((ry & 1) ? 2 : 3);
+}
+__global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) {
+  constexpr int TT = kTrRegTile, H = TT + 6;
+  const int gb = xcd_block(blockIdx.x, L.total);
+  if (gb >= L.total) return;
+  const TrLevel<float>& V = L.lv[tr_level(L, gb)];
+  const int nx = V.nx, ny = V.ny, K = V.K, lb = gb - V.start;
+  const int tx = (nx + TT - 1) / TT, ntile = tx * ((ny + TT - 1) / TT);
+  const int nch = (K + 63) / 64;
+  const int tile = lb % ntile, rest = lb / ntile;
+  const int ch = rest % nch, r = rest / nch;
+  const int bx0 = (tile % tx) * TT, by0 = (tile / tx) * TT;
+  const int s = ch * 64 + (int)threadIdx.x;
+  const bool live = s < K;
+  const int sl = live ? s : K - 1;
+  const size_t nb = (size_t)nx * ny;
+  const C2<float>* __restrict__ Sr = V.S + (size_t)r * nb * 2 * K + sl;
+  C2<float>* __restrict__ Gr = V.G + (size_t)r * nb * 2 * K + sl;
+  C2<float> t[7][7];
+#pragma unroll
+  for (int dy = -3; dy <= 3; ++dy)
+#pragma unroll
+    for (int dx = -3; dx <= 3; ++dx)
+      t[dy + 3][dx + 3] = (dx < -1 || dx > 1 || dy < -1 || dy > 1) ? V.TL[(size_t)((dy + 3) * 7 + dx + 3) * K + sl]
+                                                                  : C2<float>{0.f, 0.f};
+  C2<float> acc[TT * TT][2];
+#pragma unroll
+  for (int b = 0; b < TT * TT; ++b) acc[b][0] = acc[b][1] = C2<float>{0.f, 0.f};
+  // sources in the order that keeps each receiver's terms in list order:
+  // for each receiver the list runs dy outer, dx inner, i.e. source row
+  // outer, source column inner, which this loop order is for every receiver
+#pragma unroll
+  for (int hy = 0; hy < H; ++hy) {
+    const int gy = by0 - 3 + hy;
+    if (gy < 0 || gy >= ny) continue;
+#pragma unroll
+    for (int hx = 0; hx < H; ++hx) {
+      const int gx = bx0 - 3 + hx;
+      if (gx < 0 || gx >= nx) continue;
+      const C2<float>* src = Sr + ((size_t)gy * nx + gx) * 2 * K;
+      const C2<float> s0 = src[0], s1 = src[K];
+#pragma unroll
+      for (int ry = 0; ry < TT; ++ry)
+#pragma unroll
+        for (int rx = 0; rx < TT; ++rx) {
+          const int dx = hx - 3 - rx, dy = hy - 3 - ry;
+          if (dx < -3 || dx > 3 || dy < -3 || dy > 3 || !tr_in_list(rx, ry, dx, dy)) continue;
+          cfma(acc[ry * TT + rx][0], t[dy + 3][dx + 3], s0);
+          cfma(acc[ry * TT + rx][1], t[dy + 3][dx + 3], s1);
+        }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int ry = 0; ry < TT; ++ry)
+#pragma unroll
+    for (int rx = 0; rx < TT; ++rx) {
+      const int gx = bx0 + rx, gy = by0 + ry;
+      if (gx >= nx || gy >= ny) continue;
+      C2<float>* dst = Gr + ((size_t)gy * nx + gx) * 2 * K;
+      dst[0] = acc[ry * TT + rx][0];
+      dst[K] = acc[ry * TT + rx][1];
+    }
 }
 
 // ----------------------------------------------------------------- fields --
@@ -2301,7 +2388,7 @@ class EngineT final : public Engine {
     j.a_off = ng_aoff_.template as<int>();
     j.B = reinterpret_cast<const float*>(x);
     j.bcol = ng_bcol_.template as<int>();
-    j.C = near_part_.template as<float>();
+    j.C = pNear_;
     j.ccol = ng_ccol_.template as<int>();
     j.sB = (size_t)P_ * nf;
     j.sC = (size_t)9 * P_ * nf;
@@ -2320,7 +2407,16 @@ class EngineT final : public Engine {
     return j;
   }
 
+  // The pattern buffers the product's kernels use.
+  void bind_context_buffers() {
+    for (int l = 0; l < ntl_; ++l) {
+      pS_[l] = lv_[l].S.template as<CT>();
+      pG_[l] = lv_[l].G.template as<CT>();
+    }
+    pNear_ = near_part_.template as<float>();
+  }
   int ensure(int R, std::string& err) {
+    bind_context_buffers();
     if (R <= R_alloc_) return 0;
     for (int l = 0; l < ntl_; ++l) {
       Lvl& L = lv_[l];
@@ -2333,6 +2429,7 @@ class EngineT final : public Engine {
     if (mfma_ && !near_uniform_) HIP_TRY(near_part_.alloc((size_t)R * 9 * P_ * 2 * n_ * sizeof(float)));
     HIP_TRY(hipDeviceSynchronize());
     R_alloc_ = R;
+    bind_context_buffers();
     return 0;
   }
 
@@ -2418,7 +2515,7 @@ class EngineT final : public Engine {
     j.a_off = a_off_proj_.template as<int>();
     j.B = reinterpret_cast<const float*>(x);
     j.bcol = gcol_part_.template as<int>();
-    j.C = reinterpret_cast<float*>(lv_[0].S.template as<CT>());
+    j.C = reinterpret_cast<float*>(pS_[0]);
     j.ccol = gcol_box_.template as<int>();
     j.sB = (size_t)P_ * nf;
     j.sC = (size_t)lv_[0].nx * lv_[0].ny * 2 * M2_;
@@ -2443,7 +2540,7 @@ class EngineT final : public Engine {
     j.Ah = A_recv_h_.template as<unsigned short>();
     j.Al = A_recv_l_.template as<unsigned short>();
     j.a_off = a_off_recv_.template as<int>();
-    j.B = reinterpret_cast<const float*>(lv_[0].G.template as<CT>());
+    j.B = reinterpret_cast<const float*>(pG_[0]);
     j.bcol = gcol_box_.template as<int>();
     j.C = reinterpret_cast<float*>(y);
     j.ccol = gcol_part_.template as<int>();
@@ -2463,27 +2560,52 @@ class EngineT final : public Engine {
     return j;
   }
   // All translation levels, in two launches: LDS tiles on grids of at least
-  // 8 x 8 boxes (smaller grids waste most of a tile's halo and their gathered
-  // lists are shorter), gathered lists on the others; largest level first so
-  // the small ones fill the tail.  The 16-byte tile staging needs an even
-  // sample count (np = 2L always is).
+  // 8 x 8 boxes, and on all grids for batches of 4 or more RHS (for one RHS,
+  // smaller grids waste most of a tile's halo and their gathered lists are
+  // shorter), gathered lists on the others; largest level first so the small
+  // ones fill the tail.  The 16-byte tile staging needs an even sample count
+  // (np = 2L always is).
   void launch_translations(int R, hipStream_t st, double cb) {
+    if constexpr (std::is_same<T, float>::value) {
+      // FP32: every level in one launch of the register-tiled kernel (no LDS)
+      if (tr_force_ < 0 || tr_force_ == 4) {
+        TrLevels<float> reg{};
+        double bytes = 0, flops = 0;
+        for (int l = 0; l < ntl_; ++l) {
+          const Lvl& L = lv_[l];
+          TrLevel<float>& V = reg.lv[reg.n++];
+          V = TrLevel<float>{pS_[l], pG_[l], L.TL.template as<CT>(), nullptr, nullptr, nullptr, L.nx, L.ny, L.K,
+                             reg.total};
+          reg.total += ((L.nx + kTrRegTile - 1) / kTrRegTile) * ((L.ny + kTrRegTile - 1) / kTrRegTile) *
+                       ((L.K + 63) / 64) * R;
+          bytes += cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K);
+          flops += 16.0 * R * (double)pairs_[l] * L.K;
+        }
+        auto pr = begin("translate", bytes, flops);
+        launch(pr, k_translate_reg, dim3(xcd_grid(reg.total)), dim3(64), 0u, st, reg, R);
+        return;
+      }
+    }
     TrLevels<T> tiled{}, gath{};
+    const int rpb = std::min(R, tr_rpb_);  // RHS per tiled block
     double tb = 0, tf = 0, gbytes = 0, gf = 0;
     int trm_all = 0;
     for (int l = 0; l < ntl_; ++l) {
       const Lvl& L = lv_[l];
-      const int trm = L.K % 2 != 0 ? 0 : tr_force_ >= 0 ? tr_force_ : (L.nx >= 8 && L.ny >= 8 ? 1 : 0);
+      // LDS tiles on grids of at least 8 x 8 boxes, and on every grid once
+      // several RHS share the launch (the gathered lists re-read each source
+      // sample 27 times from L2)
+      const int trm = L.K % 2 != 0 ? 0 : tr_force_ >= 0 ? tr_force_ : ((L.nx >= 8 && L.ny >= 8) || R >= 4 ? 1 : 0);
       TrLevels<T>& D = trm ? tiled : gath;
       TrLevel<T>& V = D.lv[D.n++];
-      V = TrLevel<T>{L.S.template as<CT>(), L.G.template as<CT>(), L.TL.template as<CT>(),
+      V = TrLevel<T>{pS_[l], pG_[l], L.TL.template as<CT>(),
                      L.il_cnt.template as<int>(), L.il_src.template as<int>(), L.il_off.template as<int>(),
                      L.nx, L.ny, L.K, D.total};
       const double bytes = cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K), flops = 16.0 * R * (double)pairs_[l] * L.K;
       if (trm) {
         trm_all = trm;
         const int TX = trm == 1 ? 4 : 8, TY = trm == 3 ? 8 : 4, NS = TrNS<T>::v;
-        D.total += ((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY) * ((L.K + NS - 1) / NS) * R;
+        D.total += ((L.nx + TX - 1) / TX) * ((L.ny + TY - 1) / TY) * ((L.K + NS - 1) / NS) * ((R + rpb - 1) / rpb);
         tb += bytes;
         tf += flops;
       } else {
@@ -2497,11 +2619,11 @@ class EngineT final : public Engine {
       auto pr = begin("translate_tiled", tb, tf);
       const dim3 g(xcd_grid(tiled.total));
       if (trm_all == 1)
-        launch(pr, k_translate_tiled<T, 4, 4>, g, blk, 0u, st, tiled, R);
+        launch(pr, k_translate_tiled<T, 4, 4>, g, blk, 0u, st, tiled, R, rpb);
       else if (trm_all == 2)
-        launch(pr, k_translate_tiled<T, 8, 4>, g, blk, 0u, st, tiled, R);
+        launch(pr, k_translate_tiled<T, 8, 4>, g, blk, 0u, st, tiled, R, rpb);
       else
-        launch(pr, k_translate_tiled<T, 8, 8>, g, blk, 0u, st, tiled, R);
+        launch(pr, k_translate_tiled<T, 8, 8>, g, blk, 0u, st, tiled, R, rpb);
     }
     if (gath.n) {
       auto pr = begin("translate", gbytes, gf);
@@ -2582,8 +2704,8 @@ class EngineT final : public Engine {
     const Lvl &C = lv_[l - 1], &Pp = lv_[l];
     const Itp& I = it_[l];
     InterpArgs<T> A{};
-    A.src = agg ? C.S.template as<CT>() : Pp.G.template as<CT>();
-    A.dst = agg ? Pp.S.template as<CT>() : C.G.template as<CT>();
+    A.src = agg ? pS_[l - 1] : pG_[l];
+    A.dst = agg ? pS_[l] : pG_[l - 1];
     A.E = I.E.template as<CT>();
     A.chunk = (agg ? I.chunk_a.template as<int>() : I.chunk_d.template as<int>()) + (agg ? I.a_coff[bk] : I.d_coff[bk]);
     A.chunk_p = agg ? nullptr : I.chunkp_d.template as<int>() + 2 * (I.d_coff[bk] - bk);
@@ -2632,7 +2754,7 @@ class EngineT final : public Engine {
       const int nf = 2 * n_;
       auto pr = begin("near_sum", 4.0 * R * (9.0 + 1.0) * P_ * nf, 0.0);
       launch(pr, k_near_sum, dim3(std::min(grid1d((size_t)P_ * nf), 2048), R), blk, 0, st, P_, nf,
-             (const float*)near_part_.template as<float>(), (const int*)ng_has_.template as<int>(),
+             (const float*)pNear_, (const int*)ng_has_.template as<int>(),
              reinterpret_cast<float*>(y));
     };
     if (near && far && (near_mfma || near_grouped)) {
@@ -2661,7 +2783,7 @@ class EngineT final : public Engine {
           dim3 grid(ntiles_, (M2_ + kProjBlock - 1) / kProjBlock, R);
           size_t sh = (size_t)kTP * n_ * sizeof(CT);
           launch(pr, k_project<T, kTP>, grid, dim3(kProjBlock), sh, st, n_, P_, M2_, nb0, x,
-                             L0->S.template as<CT>(), Rm_.template as<CT>(), rm_off_.template as<int>(),
+                             pS_[0], Rm_.template as<CT>(), rm_off_.template as<int>(),
                              order_.template as<int>(), tile_start_.template as<int>(),
                              tile_count_.template as<int>(), tile_class_.template as<int>(),
                              box_of_.template as<int>());
@@ -2709,7 +2831,7 @@ class EngineT final : public Engine {
           launch_gemm<3>(pr, rt_recv_, receive_job(y, rt_recv_), none, R, st);
         } else {
           dim3 grid(ntiles_, R);
-          launch(pr, k_receive<T, kTP>, grid, blk, 0, st, n_, P_, M2_, nb0, y, L0->G.template as<CT>(),
+          launch(pr, k_receive<T, kTP>, grid, blk, 0, st, n_, P_, M2_, nb0, y, pG_[0],
                              Qm_.template as<CT>(), qm_off_.template as<int>(), order_.template as<int>(),
                              tile_start_.template as<int>(), tile_count_.template as<int>(),
                              tile_class_.template as<int>(), box_of_.template as<int>());
@@ -2968,6 +3090,9 @@ class EngineT final : public Engine {
   }
 
   int N_ = 0, n_ = 0, P_ = 0, nc_ = 0, ntl_ = 0, nx0_ = 0, ny0_ = 0, ntiles_ = 0, tp_ = 0, M2_ = 0, R_alloc_ = 0;
+  CT* pS_[kMaxTrLv] = {};  // pattern buffers in use (see bind_context_buffers)
+  CT* pG_[kMaxTrLv] = {};
+  float* pNear_ = nullptr;
   std::vector<Lvl> lv_;
   std::vector<Itp> it_;
   const Tree* tree_ = nullptr;
@@ -2978,13 +3103,15 @@ class EngineT final : public Engine {
   DevMem Rm_, Qm_, rm_off_, qm_off_;
   DevMem near_mats_, near_nbr_, near_slot_, zinv_, self_nbr_, self_slot_, near_tile_slot_, self_tile_slot_;
   bool mfma_ = false, near_uniform_ = false;
+  int tr_rpb_ = 1;  // RHS per block of the tiled translation (16 measured slower on the full-scale lens)
   // translation kernel forced on every level: 0 = gathered lists, 1/2/3 = LDS
-  // tiles of 4x4 / 8x4 / 8x8 boxes; -1 = per level (tiles of 4x4 on grids of
-  // at least 8 x 8 boxes)
+  // tiles of 4x4 / 8x4 / 8x8 boxes, 4 = register tiles (FP32); -1 = the
+  // default (register tiles in FP32; in FP64 LDS tiles of 4x4 on grids of at
+  // least 8 x 8 boxes or with 4 or more RHS, gathered lists otherwise)
   int tr_force_ = [] {
     const char* e = std::getenv("MLFMA_TRANSLATE");
     const int m = e ? std::atoi(e) : -1;
-    return m >= 0 && m <= 3 ? m : -1;
+    return m >= 0 && m <= (std::is_same<T, float>::value ? 4 : 3) ? m : -1;
   }();
   DevMem A_proj_, A_recv_, A_near_, iota_;
   DevMem A_proj_h_, A_proj_l_, A_recv_h_, A_recv_l_, A_near_h_, A_near_l_;  // BF16-split copies
