@@ -190,6 +190,21 @@ int mlfma_plane_wave_rhs(mlfma_ctx* ctx, int32_t R, const double* khat, const do
  * grow to the largest R seen. */
 int mlfma_matvec(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream);
 
+/* y = Z x as mlfma_matvec, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the product's pattern buffers (and the class-pair near
+ * partials) are laid out in a static device array of the library, 64 MiB per
+ * GPU, held until the process ends; the call makes no allocation, no graph
+ * and no memset (the leaf buffer is cleared by a kernel) and launches the
+ * kernels of mlfma_matvec directly on `stream`.  The context must already be
+ * prepared (mlfma_prepare or any earlier call that prepares it; ENOTREADY
+ * otherwise).  EINVAL if the buffers for R RHS exceed the 64 MiB (about a
+ * 40 x 40 array at R = 1; larger arrays use mlfma_matvec).  Every call on a
+ * GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (two streams, two threads, two contexts) race and must
+ * be serialised by the caller. */
+int mlfma_matvec_noalloc(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream);
+
 /* As mlfma_matvec, restricted to the near part (self + adjacent blocks),
  * the far part (multilevel expansion), or both (MLFMA_PART_*). */
 int mlfma_matvec_parts(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, int32_t parts,

@@ -599,6 +599,22 @@ int mlfma_matvec(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void
   return mlfma_matvec_parts(ctx, x_dev, y_dev, R, MLFMA_PART_ALL, stream);
 }
 
+int mlfma_matvec_noalloc(mlfma_ctx* ctx, const void* x_dev, void* y_dev, int32_t R, void* stream) {
+  if (!ctx) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    if (!x_dev || !y_dev || R < 1) return fail(ctx, MLFMA_EINVAL, "matvec_noalloc arguments");
+    if (((uintptr_t)x_dev | (uintptr_t)y_dev) & 15) return fail(ctx, MLFMA_EINVAL, "x and y must be 16-byte aligned");
+    if (!ctx->prepared)
+      return fail(ctx, MLFMA_ENOTREADY, "matvec_noalloc: the context is not prepared (call mlfma_prepare first)");
+    const size_t bytes = (size_t)R * ctx->P * 2 * ctx->N * (ctx->tp.precision == MLFMA_C128 ? 16 : 8);
+    const char *xa = (const char*)x_dev, *ya = (const char*)y_dev;
+    if (xa < ya + bytes && ya < xa + bytes) return fail(ctx, MLFMA_EINVAL, "x and y overlap");
+    std::string err;
+    int rc = ctx->eng->matvec_noalloc(x_dev, y_dev, R, stream, err);
+    return rc ? fail(ctx, rc == -1 ? MLFMA_EINVAL : rc, err) : MLFMA_OK;
+  });
+}
+
 int mlfma_fields(mlfma_ctx* ctx, const void* x_dev, int32_t R, int32_t n_points, const double* points, void* E_dev,
                  void* stream) {
   if (!ctx) return MLFMA_EINVAL;

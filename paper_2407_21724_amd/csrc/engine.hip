@@ -19,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -61,6 +62,40 @@ __device__ __forceinline__ C2<T> cmul_conj_a(C2<T> a, C2<T> b) {
 }
 
 constexpr int kBlock = 256;
+
+// Static device scratch of the no-allocation product (mlfma_matvec_noalloc):
+// its pattern buffers live here instead of in context allocations.  Every
+// GPU the library runs on holds one copy until the process ends; calls on one
+// GPU share it and keep the last call's contents.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device with that device current (the array's name in host code is not a
+// device address).
+int scratch_address(void** out, std::string& err) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    err = std::string("hipGetDevice failed: ") + hipGetErrorString(e);
+    return -3;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      return -3;
+    }
+    it = addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return 0;
+}
 
 
 #define HIP_TRY(expr)                                                     \
@@ -2407,7 +2442,8 @@ class EngineT final : public Engine {
     return j;
   }
 
-  // The pattern buffers the product's kernels use.
+  // The pattern buffers the product's kernels use: the context's own, or
+  // the no-allocation entry point's static scratch.
   void bind_context_buffers() {
     for (int l = 0; l < ntl_; ++l) {
       pS_[l] = lv_[l].S.template as<CT>();
@@ -2476,6 +2512,51 @@ class EngineT final : public Engine {
     g->used = ++use_clock_;
     HIP_TRY(hipGraphLaunch(g->exec, st));
     return 0;
+  }
+
+  // The product with the pattern buffers (and the class-pair near partials)
+  // laid out in the static scratch: no allocation, no graph, direct
+  // launches.  Fails with EINVAL if they need more than kScratchBytes.
+  int matvec_noalloc(const void* xv, void* yv, int R, void* stream, std::string& err) override {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    size_t off = 0;
+    size_t offS[kMaxTrLv] = {}, offG[kMaxTrLv] = {}, offN = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) / 256 * 256;
+      return o;
+    };
+    for (int l = 0; l < ntl_; ++l) {
+      const size_t bytes = (size_t)R * lv_[l].nx * lv_[l].ny * 2 * lv_[l].K * sizeof(CT);
+      offS[l] = take(bytes);
+      offG[l] = take(bytes);
+    }
+    if (mfma_ && !near_uniform_) offN = take((size_t)R * 9 * P_ * 2 * n_ * sizeof(float));
+    if (off > kScratchBytes) {
+      err = "matvec_noalloc: the product needs " + std::to_string(off) + " bytes of scratch for " +
+            std::to_string(R) + " RHS, above the limit of " + std::to_string(kScratchBytes);
+      return -1;
+    }
+    void* base = nullptr;
+    if (int rc = scratch_address(&base, err)) return rc;
+    unsigned char* b = static_cast<unsigned char*>(base);
+    for (int l = 0; l < ntl_; ++l) {
+      pS_[l] = reinterpret_cast<CT*>(b + offS[l]);
+      pG_[l] = reinterpret_cast<CT*>(b + offG[l]);
+    }
+    pNear_ = reinterpret_cast<float*>(b + offN);
+    // the leaf patterns of empty boxes must read zero: clear them with a
+    // kernel (no memset node, should the caller capture this stream)
+    if (ntl_ > 0) {
+      const size_t cnt = (size_t)R * lv_[0].nx * lv_[0].ny * 2 * lv_[0].K;
+      hipLaunchKernelGGL(k_fill_zero<T>, dim3(grid1d(cnt)), dim3(kBlock), 0, st, pS_[0], cnt);
+    }
+    const bool prof = prof_on_;
+    prof_on_ = false;  // no per-stage events: their creation may allocate
+    const int rc = enqueue(xv, yv, R, 3, st, err);
+    prof_on_ = prof;
+    bind_context_buffers();
+    return rc;
   }
 
   // one wave per tile where K is short (at most 16 k-steps of 16) and B

@@ -60,6 +60,8 @@ class Engine {
   virtual ~Engine() = default;
   virtual int upload(const Upload& u, std::string& err) = 0;
   virtual int matvec(const void* x, void* y, int R, int parts, void* stream, std::string& err) = 0;
+  // the product with its scratch in the library's static device array (no allocation)
+  virtual int matvec_noalloc(const void* x, void* y, int R, void* stream, std::string& err) = 0;
   virtual int precondition(const void* x, void* y, int R, void* stream, std::string& err) = 0;
   // b[r][p] = -exp(-j k khat_r . r_p) * pat[class_p][r] with pat [C][R][n]
   virtual int rhs(const std::vector<cd>& pat, const std::vector<V3>& khat, int R, void* b, void* stream,

@@ -65,7 +65,7 @@ class SolveStats(C.Structure):
 
 EXPORTS = [
     "mlfma_default_params", "mlfma_build_tree", "mlfma_static_modes", "mlfma_set_static_modes",
-    "mlfma_prepare", "mlfma_plane_wave_rhs", "mlfma_matvec", "mlfma_matvec_parts",
+    "mlfma_prepare", "mlfma_plane_wave_rhs", "mlfma_matvec", "mlfma_matvec_parts", "mlfma_matvec_noalloc",
     "mlfma_precondition", "mlfma_gmres_solve", "mlfma_fields", "mlfma_info", "mlfma_destroy", "mlfma_last_error",
     "mlfma_debug_near_block", "mlfma_debug_pair_block_device", "mlfma_debug_leaf_pattern", "mlfma_debug_level_grid",
     "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read", "mlfma_share_setup",
@@ -91,6 +91,7 @@ def load_library(path: str = _LIB_PATH):
         "mlfma_prepare": (C.c_int, [ctxp]),
         "mlfma_plane_wave_rhs": (C.c_int, [ctxp, C.c_int32, dp, dp, vp, vp]),
         "mlfma_matvec": (C.c_int, [ctxp, vp, vp, C.c_int32, vp]),
+        "mlfma_matvec_noalloc": (C.c_int, [ctxp, vp, vp, C.c_int32, vp]),
         "mlfma_matvec_parts": (C.c_int, [ctxp, vp, vp, C.c_int32, C.c_int32, vp]),
         "mlfma_precondition": (C.c_int, [ctxp, vp, vp, C.c_int32, vp]),
         "mlfma_fields": (C.c_int, [ctxp, vp, C.c_int32, C.c_int32, dp, vp, vp]),
@@ -319,6 +320,14 @@ class Context:
             out = torch.empty_like(x)
         self._check(lib().mlfma_matvec(self._h, self._dev(x, R), self._dev(out, R), R, _stream_ptr(stream)),
                     "matvec")
+        return out
+
+    def matvec_noalloc(self, x, out, stream=None):
+        """mlfma_matvec_noalloc: the product with the library's static
+        scratch (the context must be prepared; `out` is caller-allocated)."""
+        R = x.shape[0]
+        self._check(lib().mlfma_matvec_noalloc(self._h, self._dev(x, R), self._dev(out, R), R,
+                                               _stream_ptr(stream)), "matvec_noalloc")
         return out
 
     def precondition(self, x, out=None, stream=None):
