@@ -34,25 +34,38 @@ FP32_VALU_PEAK = 157.3e12   # MI355X FP32 vector peak
 ENGINE_SRC = os.path.join(ROOT, "paper_2407_21724_amd", "csrc", "engine.hip")
 
 # product stages (as named by mlfma_profile_read) -> kernel symbol prefix and
-# the roofline that bounds it
-# (the GEMM stages are named by kernel_of from the row tiles in use)
+# the roofline that bounds it (FP32 product; the GEMM stages are named by
+# kernel_of from the dispatch rules of the engine)
 KERNELS = [
     ("aggregate_l", "k_agg_stream", "hbm"),
-    ("translate", "k_translate", "hbm"),              # all levels with gathered lists, one launch
-    ("translate_tiled", "k_translate_tiled", "hbm"),  # all levels in LDS tiles, one launch
+    ("translate", "k_translate_reg", "hbm"),          # FP32: every level in one launch, tiles in registers
     ("disaggregate_l", "k_dis_stream", "hbm"),
     ("near_sum", "k_near_sum", "hbm"),
 ]
 
 
-def kernel_of(stage, gemm_rows=(4, 4), R=1):
-    """Kernel symbol and roofline bound of a product stage; the GEMM symbols
-    carry the row tiles the context runs with and the column tiles per block
-    (4 when R is a multiple of 4, 2 when even, else 1; 8 waves per block)."""
+def kernel_of(stage, gemm_rows=(4, 4), R=1, multi_class=True):
+    """Kernel symbol and roofline bound of a product stage of the FP32
+    product.  The GEMM stages follow the engine's dispatch: the LDS-staged
+    kernel k_gemm_lds<mode, waves, column tiles, tag> when R is a multiple
+    of 4 and both jobs of the launch take the same mode (mode 0: K fits one
+    chunk; mode 1: M does), else k_gemm_stream<row tiles, column tiles, tag,
+    8> with 4 column tiles when R is a multiple of 4, 2 when even, else 1.
+    The near job of a single-class array (nine blocks side by side, mode 1)
+    and the projection (mode 0) share a launch, so that launch stays on
+    k_gemm_stream."""
     rn, rr = gemm_rows
     ct = 4 if R % 4 == 0 else 2 if R % 2 == 0 else 1
-    gemm = {"near+project": f"k_gemm_stream<{rn}, {ct}, 0, 8>", "near": f"k_gemm_stream<{rn}, {ct}, 1, 8>",
-            "project": f"k_gemm_stream<{rn}, {ct}, 2, 8>", "receive": f"k_gemm_stream<{rr}, {ct}, 3, 8>"}
+    lds = R % 4 == 0 and os.environ.get("MLFMA_GEMM") != "stream"
+    w0, c0 = (8, 2) if R % 16 == 0 else (8, 1) if R % 8 == 0 else (4, 1)   # mode 0
+    w1 = 8 if R % 8 == 0 else 4                                            # mode 1
+    near_mode = 0 if multi_class else 1
+    gemm = {
+        "near+project": f"k_gemm_lds<0, {w0}, {c0}, 0>" if lds and multi_class else f"k_gemm_stream<{rn}, {ct}, 0, 8>",
+        "near": (f"k_gemm_lds<0, {w0}, {c0}, 1>" if near_mode == 0 else f"k_gemm_lds<1, {w1}, 1, 1>") if lds
+        else f"k_gemm_stream<{rn}, {ct}, 1, 8>",
+        "project": f"k_gemm_lds<0, {w0}, {c0}, 2>" if lds else f"k_gemm_stream<{rn}, {ct}, 2, 8>",
+        "receive": f"k_gemm_lds<1, {w1}, 1, 3>" if lds else f"k_gemm_stream<{rr}, {ct}, 3, 8>"}
     if stage in gemm:
         return gemm[stage], "mfma"
     for prefix, sym, bound in KERNELS:
@@ -67,12 +80,16 @@ def source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def kernel_table(stages, gemm_rows=(4, 4), R=1):
-    """Group per-stage event timings by kernel symbol (the unit rocprofv3
-    reports): total time, launches, algorithmic bytes and flops per launch."""
+def kernel_table(stages, gemm_rows=(4, 4), R=1, multi_class=True):
+    """Group per-stage event timings by the symbol of the kernel each stage
+    launched (the unit rocprofv3 reports, template arguments included, as
+    the library records it): total time, launches, algorithmic bytes and
+    flops.  Stages without a recorded symbol fall back to kernel_of."""
     groups = {}
     for s in stages:
-        sym, bound = kernel_of(s["name"], gemm_rows, R)
+        fsym, bound = kernel_of(s["name"], gemm_rows, R, multi_class)
+        sym = s.get("kernel") or fsym
+        bound = "mfma" if sym.startswith("k_gemm") else bound
         g = groups.setdefault(sym, {"kernel": sym, "bound": bound, "total_ms": 0.0, "launches": 0,
                                     "bytes": 0.0, "flops": 0.0, "stages": []})
         g["total_ms"] += s["total_ms"]
@@ -570,7 +587,7 @@ def main():
 
     # roofline of the dominant kernel (largest share of the product's time)
     gemm_rows = ctx.get_gemm_tiles()
-    groups = kernel_table(stages, gemm_rows, R)
+    groups = kernel_table(stages, gemm_rows, R, len(set(wl.class_id.tolist())) > 1)
     dom = max(groups.values(), key=lambda g: g["total_ms"])
     avg_s = dom["total_ms"] / dom["launches"] * 1e-3
     if dom["bound"] == "hbm":

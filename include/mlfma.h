@@ -295,11 +295,15 @@ int mlfma_fields(mlfma_ctx* ctx, const void* x_dev, int32_t R, int32_t n_points,
  * bracketed by HIP events recorded on the launch stream.  Enabling clears
  * the accumulated table. */
 typedef struct {
-  char name[32];               /* kernel and level, e.g. "translate_l0"    */
+  char name[32];               /* stage and level, e.g. "aggregate_l1"     */
   double total_ms;             /* summed event time over the launches      */
   int64_t launches;
   double bytes_per_launch;     /* algorithmic HBM bytes of one launch      */
   double flops_per_launch;     /* algorithmic real floating-point ops      */
+  char kernel[96];             /* symbol of the launched kernel with its
+                                  template arguments, e.g.
+                                  "k_dis_stream<float, 6, 12, 16>" (the unit
+                                  kernel traces report; "" if unknown)     */
 } mlfma_stage_time;
 
 int mlfma_profile(mlfma_ctx* ctx, int32_t enable);

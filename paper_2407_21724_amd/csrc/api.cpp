@@ -717,6 +717,8 @@ int mlfma_profile_read(mlfma_ctx* ctx, int32_t max, mlfma_stage_time* out, int32
       out[i].launches = t[i].launches;
       out[i].bytes_per_launch = t[i].bytes;
       out[i].flops_per_launch = t[i].flops;
+      std::memset(out[i].kernel, 0, sizeof(out[i].kernel));
+      std::strncpy(out[i].kernel, t[i].kernel.c_str(), sizeof(out[i].kernel) - 1);
     }
     return MLFMA_OK;
   });

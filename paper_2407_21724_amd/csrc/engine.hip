@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cstdint>
 #include <chrono>
+#include <cxxabi.h>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -59,6 +61,30 @@ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
 template <typename T>
 __device__ __forceinline__ C2<T> cmul_conj_a(C2<T> a, C2<T> b) {
   return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+
+// Short symbol of a kernel (name and template arguments, without namespace,
+// return type or parameter list), as the runtime names it: the unit in
+// which kernel traces report.
+inline std::string kernel_symbol(const void* fn, hipStream_t st) {
+  const char* m = hipKernelNameRefByPtr(fn, st);
+  if (!m) return std::string();
+  int status = 0;
+  char* d = abi::__cxa_demangle(m, nullptr, nullptr, &status);
+  std::string n = (status == 0 && d) ? std::string(d) : std::string(m);
+  std::free(d);
+  for (const char* pre : {"void ", "mlfma::", "(anonymous namespace)::"}) {
+    size_t at;
+    while ((at = n.find(pre)) != std::string::npos) n.erase(at, std::strlen(pre));
+  }
+  // cut the parameter list: the first '(' outside template brackets
+  int depth = 0;
+  for (size_t i = 0; i < n.size(); ++i) {
+    if (n[i] == '<') ++depth;
+    else if (n[i] == '>') --depth;
+    else if (n[i] == '(' && depth == 0) return n.substr(0, i);
+  }
+  return n;
 }
 
 constexpr int kBlock = 256;
@@ -380,18 +406,224 @@ __global__ __launch_bounds__(64 * W) void k_gemm_stream(GemmJob j0, GemmJob j1) 
 }
 
 // y[r][p][:] = sum over the neighbours o of p of partial[r][o * P + p][:]
-// (nf floats per particle), in a fixed order.
+// (nf floats per particle, nf a multiple of 4), in a fixed order.  One lane
+// per 4 floats; the nine partial loads are issued together (absent
+// neighbours contribute exact zeros: their partial rows are never written).
 __global__ __launch_bounds__(kBlock) void k_near_sum(int P, int nf, const float* __restrict__ partial,
                                                       const int* __restrict__ has, float* __restrict__ y) {
-  const size_t cnt = (size_t)P * nf;
+  const int nq = nf >> 2;
+  const size_t cnt = (size_t)P * nq;
   const int r = blockIdx.y;
+  const f32x4* __restrict__ pr = reinterpret_cast<const f32x4*>(partial) + (size_t)r * 9 * cnt;
+  f32x4* __restrict__ yr = reinterpret_cast<f32x4*>(y) + (size_t)r * cnt;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (size_t)gridDim.x * kBlock) {
-    const int p = (int)(i / nf), m = (int)(i - (size_t)p * nf);
-    const float* pr = partial + (size_t)r * 9 * cnt;
-    float acc = 0.f;
-    for (int o = 0; o < 9; ++o)
-      if (has[p * 9 + o]) acc += pr[((size_t)o * P + p) * nf + m];
-    y[(size_t)r * cnt + i] = acc;
+    const int p = (int)(i / nq);
+    f32x4 v[9];
+#pragma unroll
+    for (int o = 0; o < 9; ++o) {
+      v[o] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (has[p * 9 + o]) v[o] = pr[(size_t)o * cnt + i];
+    }
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 0; o < 9; ++o) acc += v[o];
+    yr[i] = acc;
+  }
+}
+
+// LDS-staged variant of k_gemm_stream for the FP32 jobs with the
+// right-hand sides folded into the columns.  A block of W waves shares one
+// A matrix (one column group): A passes through LDS in chunks of kLM rows
+// by kLK k, and only the even rows of its real 2x2-block form are staged:
+// row 2i holds (Re z, -Im z) of the complex entries z, and a lane rebuilds
+// the real row it needs, (Re, -Im) for an even row or (Im, Re) for an odd
+// one.  This halves the A bytes that leave L2.
+//   MODE 0 (K <= kLK, one B segment): a wave keeps the B columns of its CT
+//     column tiles in registers over all of K, reads them from memory once,
+//     and walks the row chunks one 16-row tile at a time.
+//   MODE 1 (M <= kLM): a wave keeps its C tiles (every row) in registers
+//     and walks the k chunks; B is read once, its next chunk loaded
+//     before the barrier that ends the current one.
+// The next A chunk is loaded while the current one is multiplied; chunks
+// alternate between two LDS buffers.  Every C tile is summed over k in
+// increasing order by one wave, as in the one-wave tiles of k_gemm_stream.
+// A block covers W * CT column tiles of 16 folded columns; the host keeps
+// them inside one column group (W * CT divides the fold).  Requires M, K,
+// kseg, lda, ldb and ldc multiples of 4 and 16-byte aligned bases.
+constexpr int kLM = 128, kLK = 128, kLS4 = kLK / 4 + 1;  // f32x4 per staged row (one of padding)
+__host__ __device__ inline int lds_mode(const GemmJob& j) {
+  if (!j.A) return -1;
+  if (j.nseg == 1 && j.kseg <= kLK) return 0;
+  return j.M <= kLM ? 1 : -1;
+}
+__host__ __device__ inline int lds_blocks(const GemmJob& j, int W, int CT) {
+  if (!j.A) return 0;
+  const long long cols = (long long)j.ncols * (j.fold > 0 ? j.fold : 1);
+  return (int)((cols + 16LL * W * CT - 1) / (16LL * W * CT));
+}
+__device__ __forceinline__ f32x4 expand_row(f32x4 v, bool odd) {
+  // v = (Re z0, -Im z0, Re z1, -Im z1) from even row 2i; row 2i + 1 is
+  // (Im z0, Re z0, Im z1, Re z1)
+  return odd ? f32x4{-v[1], v[0], -v[3], v[2]} : v;
+}
+template <int MODE, int W, int CT, int Tag>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_lds(GemmJob j0, GemmJob j1) {
+  constexpr int NP = (kLM / 2) * (kLK / 4) / (64 * W);  // staged f32x4 per thread and chunk
+  constexpr int NS = kLK / 16;                          // k-steps per chunk
+  __shared__ f32x4 sA[2][kLM / 2][kLS4];
+  // XCD-aware order per job: the hardware deals block b to XCD b % 8, and
+  // each XCD takes an eighth of job 1's blocks, then an eighth of job 0's
+  // (consecutive blocks of a job share their A matrix in that XCD's L2).
+  // Splitting each job evenly keeps the XCDs balanced when the jobs' blocks
+  // differ in cost (a projection block does eight times the work of a
+  // near-block block).
+  const int nb0 = lds_blocks(j0, W, CT), nb1 = lds_blocks(j1, W, CT);
+  const int p0 = (nb0 + 7) >> 3, p1 = (nb1 + 7) >> 3;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const bool second = slot < p1;
+  const int bl = second ? xcd * p1 + slot : xcd * p0 + (slot - p1);  // block within its job
+  if (bl >= (second ? nb1 : nb0)) return;  // whole block
+#define JF(f) (second ? j1.f : j0.f)
+  const int M = JF(M), nseg = JF(nseg), kseg = JF(kseg), K = nseg * kseg;
+  const int lda = JF(lda), ldb = JF(ldb), ldc = JF(ldc), accumulate = JF(acc), ncols = JF(ncols);
+  const int fd = JF(fold) > 0 ? JF(fold) : 1;
+  const int* __restrict__ bcol = JF(bcol);
+  const int* __restrict__ ccol = JF(ccol);
+  const int* __restrict__ a_off = JF(a_off);
+  const size_t sB = JF(sB), sC = JF(sC);
+  const float* __restrict__ B0 = JF(B);
+  float* __restrict__ C0 = JF(C);
+  const int nblk0 = bl * W * CT * 16;  // the block's first folded column
+  const float* __restrict__ A = JF(A) + (a_off ? a_off[(nblk0 / fd) >> 4] : 0);
+#undef JF
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+  const bool odd = i & 1;
+  int base[CT], rc[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int n = nblk0 + (wave * CT + ct) * 16 + i, b = n / fd;
+    base[ct] = b < ncols ? b : -1;
+    rc[ct] = n - b * fd;
+  }
+  // A chunk: even rows m0 + 2 jr (jr < kLM / 2), k0 .. k0 + kLK
+  f32x4 st[NP];
+  auto stage_load = [&](int m0, int k0) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int p = threadIdx.x + u * 64 * W, jr = p / (kLK / 4), q = p % (kLK / 4);
+      const int m = m0 + 2 * jr, k = k0 + 4 * q;
+      // unconditional load from a clamped (valid) address, then a select:
+      // no divergent branches around the staging registers
+      const f32x4 v = *reinterpret_cast<const f32x4*>(A + (size_t)min(m, M - 2) * lda + min(k, K - 4));
+      st[u] = (m < M && k < K) ? v : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto stage_store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int p = threadIdx.x + u * 64 * W;
+      sA[buf][p / (kLK / 4)][p % (kLK / 4)] = st[u];
+    }
+  };
+  // B of this lane's columns for the k-steps of chunk k0
+  auto load_b = [&](int k0, f32x4(&b)[CT][NS]) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        // clamped indices and unconditional loads, as in the staging
+        const int k = k0 + 16 * s + 4 * kq, kc = min(k, K - 4);
+        const int sg = nseg == 1 ? 0 : kc / kseg;
+        const int src = bcol[(size_t)max(base[ct], 0) * nseg + sg];
+        const bool ok = base[ct] >= 0 && k < K && src >= 0;
+        const f32x4 v = *reinterpret_cast<const f32x4*>(B0 + (size_t)rc[ct] * sB + (size_t)max(src, 0) * ldb +
+                                                        (kc - sg * kseg));
+        b[ct][s] = ok ? v : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  auto store_c = [&](int ct, int m, f32x4 v) {
+    if (base[ct] < 0 || m >= M) return;
+    const int dcol = ccol[base[ct]];
+    if (dcol < 0) return;
+    f32x4* dst = reinterpret_cast<f32x4*>(C0 + (size_t)rc[ct] * sC + (size_t)dcol * ldc + m);
+    *dst = accumulate ? *dst + v : v;
+  };
+  f32x4 b[CT][NS];
+  if constexpr (MODE == 0) {
+    load_b(0, b);
+    const int nmc = (M + kLM - 1) / kLM;
+    stage_load(0, 0);
+    stage_store(0);
+    __syncthreads();
+    for (int mc = 0; mc < nmc; ++mc) {
+      const int buf = mc & 1;
+      if (mc + 1 < nmc) stage_load((mc + 1) * kLM, 0);
+      for (int rt = 0; rt < kLM / 16; ++rt) {
+        const int mt = mc * kLM + 16 * rt;
+        if (mt >= M) break;
+        f32x4 acc[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (16 * s >= K) break;
+          const f32x4 a = expand_row(sA[buf][8 * rt + (i >> 1)][4 * s + kq], odd);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[ct][s][q], acc[ct], 0, 0, 0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) store_c(ct, mt + 4 * kq, acc[ct]);
+      }
+      if (mc + 1 < nmc) {
+        stage_store(buf ^ 1);
+        __syncthreads();
+      }
+    }
+  } else {
+    constexpr int RT = kLM / 16;
+    f32x4 acc[RT][CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nkc = (K + kLK - 1) / kLK;
+    load_b(0, b);
+    stage_load(0, 0);
+    stage_store(0);
+    __syncthreads();
+    for (int kc = 0; kc < nkc; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nkc) stage_load(0, (kc + 1) * kLK);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (kc * kLK + 16 * s >= K) break;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          if (16 * rt >= M) break;
+          const f32x4 a = expand_row(sA[buf][8 * rt + (i >> 1)][4 * s + kq], odd);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[ct][s][q], acc[rt][ct], 0, 0, 0);
+        }
+        // one k-step's A reads at a time (hoisting all of a chunk's would
+        // need more registers than four waves per SIMD have)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (kc + 1 < nkc) {
+        load_b((kc + 1) * kLK, b);  // in flight across the barrier
+        stage_store(buf ^ 1);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) store_c(ct, 16 * rt + 4 * kq, acc[rt][ct]);
   }
 }
 
@@ -754,14 +986,17 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       for (int a = 0; a + 1 < ORD; ++a) win[q][a] = win[q][a + 1];
       win[q][ORD - 1] = f[q];
     }
-    // parent rows whose theta stencil ends at this extended row (at most 3):
-    // all three candidates are formed, since their phases are in flight for
-    // every row, and the ones that end here are stored
+    // parent rows whose theta stencil ends at this extended row (at most 3,
+    // in order); the test is uniform over the wave, so only the rows that
+    // end here are formed (their phases were loaded for all three
+    // candidates, unconditionally, ahead of the next row's values)
     int nemit = 0;
+    pn = __builtin_amdgcn_readfirstlane(pn);  // uniform: the tests below branch on the scalar unit
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       const int pu = min(pn + u, p1 - 1);
       const bool ends = pn + u < p1 && uni(A.s0)[pn + u] + ORD - 1 == e;
+      if (!ends) break;
       const auto tw = uni(A.thw) + pu * ORD;
       C2<T> v[4];
 #pragma unroll
@@ -779,8 +1014,8 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       C2<T> o;
       o.x = a1.x * (v[3].x + v[0].x) - a1.y * (v[3].y - v[0].y) + a2.x * (v[1].x + v[2].x) - a2.y * (v[1].y - v[2].y);
       o.y = a1.x * (v[3].y + v[0].y) + a1.y * (v[3].x - v[0].x) + a2.x * (v[1].y + v[2].y) + a2.y * (v[1].x - v[2].x);
-      if (ends && valid) out[(size_t)pu * A.npp] = o;
-      nemit += ends ? 1 : 0;
+      if (valid) out[(size_t)pu * A.npp] = o;
+      ++nemit;
     }
     pn += nemit;
   }
@@ -1166,9 +1401,9 @@ __global__ __launch_bounds__(kBlock) void k_translate_tiled(TrLevels<T> L, int R
 
 // FP32 translation with no LDS: one wave per 4 x 4 tile of receiving boxes
 // and 64 consecutive samples (one per lane).  A lane holds the 40 operators
-// of its sample that a tile uses (offsets with |dx| or |dy| >= 2) and the
-// 16 boxes' two sums in registers, and reads each of the tile's 10 x 10
-// source boxes once; the interaction lists are known at compile time (a
+// of its sample that a tile uses (offsets with |dx| or |dy| >= 2) and, one
+// field component at a time, the 16 boxes' sums in registers, and reads
+// each of the tile's 10 x 10 source boxes once per component; the interaction lists are known at compile time (a
 // tile starts at even box indices, so a receiver's parity fixes its list).
 // Terms are added in the order of the gathered lists (dy outer, dx inner).
 constexpr int kTrRegTile = 4;
@@ -1176,6 +1411,97 @@ __host__ __device__ constexpr bool tr_in_list(int rx, int ry, int dx, int dy) {
   return (dx < -1 || dx > 1 || dy < -1 || dy > 1) && dx >= ((rx & 1) ? -3 : -2) && dx <= ((rx & 1) ? 2 : 3) &&
          dy >= ((ry & 1) ? -3 : -2) && dy <= ((ry & 1) ? 2 : 3);
 }
+// One 4 x 4 tile of k_translate_reg, one field component at a time (16
+// accumulators instead of 32 leave registers for source loads in flight).
+// Sources are visited row by row, column by column, which keeps every
+// receiver's terms in the order of its interaction list (dy outer, dx inner).
+// The terms a source row adds to the tile's receivers:
+__device__ __forceinline__ void tr_reg_row(C2<float> (&acc)[kTrRegTile * kTrRegTile], const C2<float> (&t)[7][7],
+                                           const C2<float>* sv, int hy, bool ok_row, int bx0, int nx) {
+  constexpr int TT = kTrRegTile, H = TT + 6;
+#pragma unroll
+  for (int hx = 0; hx < H; ++hx) {
+    const int gx = bx0 - 3 + hx;
+    if (!ok_row || gx < 0 || gx >= nx) continue;
+#pragma unroll
+    for (int ry = 0; ry < TT; ++ry)
+#pragma unroll
+      for (int rx = 0; rx < TT; ++rx) {
+        const int dx = hx - 3 - rx, dy = hy - 3 - ry;
+        if (dx < -3 || dx > 3 || dy < -3 || dy > 3 || !tr_in_list(rx, ry, dx, dy)) continue;
+        cfma(acc[ry * TT + rx], t[dy + 3][dx + 3], sv[hx]);
+      }
+  }
+}
+// INTERIOR: the 10 x 10 source window lies inside the grid.  Its rows are
+// loaded one row ahead of the row being summed, with no bounds test between
+// a load and its use (a load inside a conditional block makes the compiler
+// wait for every outstanding load there); a scheduling barrier after each
+// row keeps the compiler from hoisting more rows than two rows' registers.
+template <bool INTERIOR, bool PIPE>
+__device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2<float>* __restrict__ Gr,
+                                            const C2<float> (&t)[7][7], int bx0, int by0, int nx, int ny, int K,
+                                            bool live) {
+  constexpr int TT = kTrRegTile, H = TT + 6;
+#pragma unroll 1
+  for (int comp = 0; comp < 2; ++comp) {
+    C2<float> acc[TT * TT];
+#pragma unroll
+    for (int b = 0; b < TT * TT; ++b) acc[b] = C2<float>{0.f, 0.f};
+    const C2<float>* __restrict__ Sc = Sr + (size_t)comp * K;
+    if constexpr (INTERIOR) {
+      C2<float> cur[H], nxt[H];
+      auto load_row = [&](int hy, C2<float>(&dst)[H]) {
+        const C2<float>* row = Sc + ((size_t)(by0 - 3 + hy) * nx + (bx0 - 3)) * 2 * K;
+#pragma unroll
+        for (int hx = 0; hx < H; ++hx) dst[hx] = row[(size_t)hx * 2 * K];
+      };
+      if constexpr (PIPE) {
+        load_row(0, cur);
+#pragma unroll
+        for (int hy = 0; hy < H; ++hy) {
+          if (hy + 1 < H) load_row(hy + 1, nxt);
+          tr_reg_row(acc, t, cur, hy, true, bx0, nx);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int hx = 0; hx < H; ++hx) cur[hx] = nxt[hx];
+        }
+      } else {  // one row's loads at a time (fewer registers, more waves per SIMD)
+#pragma unroll
+        for (int hy = 0; hy < H; ++hy) {
+          load_row(hy, cur);
+          tr_reg_row(acc, t, cur, hy, true, bx0, nx);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int hy = 0; hy < H; ++hy) {
+        const int gy = by0 - 3 + hy;
+        if (gy < 0 || gy >= ny) continue;
+        C2<float> sv[H];
+        const C2<float>* row = Sc + ((size_t)gy * nx + (bx0 - 3)) * 2 * K;
+#pragma unroll
+        for (int hx = 0; hx < H; ++hx) {
+          const int gx = bx0 - 3 + hx;
+          sv[hx] = (gx >= 0 && gx < nx) ? row[(ptrdiff_t)hx * 2 * K] : C2<float>{0.f, 0.f};
+        }
+        tr_reg_row(acc, t, sv, hy, true, bx0, nx);
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int ry = 0; ry < TT; ++ry)
+#pragma unroll
+        for (int rx = 0; rx < TT; ++rx) {
+          const int gx = bx0 + rx, gy = by0 + ry;
+          if (!INTERIOR && (gx >= nx || gy >= ny)) continue;
+          Gr[((size_t)gy * nx + gx) * 2 * K + (size_t)comp * K] = acc[ry * TT + rx];
+        }
+    }
+  }
+}
+template <bool PIPE>
 __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) {
   constexpr int TT = kTrRegTile, H = TT + 6;
   const int gb = xcd_block(blockIdx.x, L.total);
@@ -1200,44 +1526,14 @@ __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) 
     for (int dx = -3; dx <= 3; ++dx)
       t[dy + 3][dx + 3] = (dx < -1 || dx > 1 || dy < -1 || dy > 1) ? V.TL[(size_t)((dy + 3) * 7 + dx + 3) * K + sl]
                                                                   : C2<float>{0.f, 0.f};
-  C2<float> acc[TT * TT][2];
-#pragma unroll
-  for (int b = 0; b < TT * TT; ++b) acc[b][0] = acc[b][1] = C2<float>{0.f, 0.f};
-  // sources in the order that keeps each receiver's terms in list order:
-  // for each receiver the list runs dy outer, dx inner, i.e. source row
-  // outer, source column inner, which this loop order is for every receiver
-#pragma unroll
-  for (int hy = 0; hy < H; ++hy) {
-    const int gy = by0 - 3 + hy;
-    if (gy < 0 || gy >= ny) continue;
-#pragma unroll
-    for (int hx = 0; hx < H; ++hx) {
-      const int gx = bx0 - 3 + hx;
-      if (gx < 0 || gx >= nx) continue;
-      const C2<float>* src = Sr + ((size_t)gy * nx + gx) * 2 * K;
-      const C2<float> s0 = src[0], s1 = src[K];
-#pragma unroll
-      for (int ry = 0; ry < TT; ++ry)
-#pragma unroll
-        for (int rx = 0; rx < TT; ++rx) {
-          const int dx = hx - 3 - rx, dy = hy - 3 - ry;
-          if (dx < -3 || dx > 3 || dy < -3 || dy > 3 || !tr_in_list(rx, ry, dx, dy)) continue;
-          cfma(acc[ry * TT + rx][0], t[dy + 3][dx + 3], s0);
-          cfma(acc[ry * TT + rx][1], t[dy + 3][dx + 3], s1);
-        }
-    }
-  }
-  if (!live) return;
-#pragma unroll
-  for (int ry = 0; ry < TT; ++ry)
-#pragma unroll
-    for (int rx = 0; rx < TT; ++rx) {
-      const int gx = bx0 + rx, gy = by0 + ry;
-      if (gx >= nx || gy >= ny) continue;
-      C2<float>* dst = Gr + ((size_t)gy * nx + gx) * 2 * K;
-      dst[0] = acc[ry * TT + rx][0];
-      dst[K] = acc[ry * TT + rx][1];
-    }
+  // tiles whose 10 x 10 source window lies inside the grid take a path with
+  // no bounds tests, so that no branch separates a load from its use and
+  // the loads of later sources stay in flight (a load inside a conditional
+  // block makes the compiler wait for every outstanding load there)
+  if (bx0 >= 3 && by0 >= 3 && bx0 + TT + 3 <= nx && by0 + TT + 3 <= ny)
+    tr_reg_tile<true, PIPE>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
+  else
+    tr_reg_tile<false, PIPE>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
 }
 
 // ----------------------------------------------------------------- fields --
@@ -2649,7 +2945,7 @@ class EngineT final : public Engine {
   void launch_translations(int R, hipStream_t st, double cb) {
     if constexpr (std::is_same<T, float>::value) {
       // FP32: every level in one launch of the register-tiled kernel (no LDS)
-      if (tr_force_ < 0 || tr_force_ == 4) {
+      if (tr_force_ < 0 || tr_force_ >= 4) {
         TrLevels<float> reg{};
         double bytes = 0, flops = 0;
         for (int l = 0; l < ntl_; ++l) {
@@ -2663,7 +2959,10 @@ class EngineT final : public Engine {
           flops += 16.0 * R * (double)pairs_[l] * L.K;
         }
         auto pr = begin("translate", bytes, flops);
-        launch(pr, k_translate_reg, dim3(xcd_grid(reg.total)), dim3(64), 0u, st, reg, R);
+        if (tr_force_ == 5)  // interior rows loaded one at a time (no row ahead)
+          launch(pr, k_translate_reg<false>, dim3(xcd_grid(reg.total)), dim3(64), 0u, st, reg, R);
+        else
+          launch(pr, k_translate_reg<true>, dim3(xcd_grid(reg.total)), dim3(64), 0u, st, reg, R);
         return;
       }
     }
@@ -2737,6 +3036,27 @@ class EngineT final : public Engine {
       else
         launch(pr, k_gemm_bf16x3<4, Tag>, grid, dim3(kBlock), 0u, st, j0u, j1u);
       return;
+    }
+    // the LDS-staged kernel where both jobs take the same mode and blocks of
+    // W * CT column tiles stay inside one column group (W * CT divides R)
+    const int md0 = lds_mode(j0u), md1 = j1u.A ? lds_mode(j1u) : md0;
+    if (gemm_lds_ && md0 >= 0 && md0 == md1) {
+      int W = 0, C = 0;
+      if (md0 == 0 && R % 16 == 0) W = 8, C = 2;
+      else if (R % 8 == 0) W = 8, C = 1;
+      else if (R % 4 == 0) W = 4, C = 1;
+      if (W) {
+        GemmJob a = j0u, b = j1u;
+        a.fold = R;
+        if (b.A) b.fold = R;
+        const dim3 grid(8 * ((lds_blocks(a, W, C) + 7) / 8 + (lds_blocks(b, W, C) + 7) / 8)), blk(64 * W);
+        if (md0 == 0 && C == 2) launch(pr, k_gemm_lds<0, 8, 2, Tag>, grid, blk, 0u, st, a, b);
+        else if (md0 == 0 && W == 8) launch(pr, k_gemm_lds<0, 8, 1, Tag>, grid, blk, 0u, st, a, b);
+        else if (md0 == 0) launch(pr, k_gemm_lds<0, 4, 1, Tag>, grid, blk, 0u, st, a, b);
+        else if (W == 8) launch(pr, k_gemm_lds<1, 8, 1, Tag>, grid, blk, 0u, st, a, b);
+        else launch(pr, k_gemm_lds<1, 4, 1, Tag>, grid, blk, 0u, st, a, b);
+        return;
+      }
     }
     const int ct = R % 4 == 0 ? 4 : R % 2 == 0 ? 2 : 1;
     const GemmJob j0 = fold_job(j0u, R, ct), j1 = fold_job(j1u, R, ct);
@@ -2834,7 +3154,7 @@ class EngineT final : public Engine {
     auto near_sum = [&]() {
       const int nf = 2 * n_;
       auto pr = begin("near_sum", 4.0 * R * (9.0 + 1.0) * P_ * nf, 0.0);
-      launch(pr, k_near_sum, dim3(std::min(grid1d((size_t)P_ * nf), 2048), R), blk, 0, st, P_, nf,
+      launch(pr, k_near_sum, dim3(std::min(grid1d((size_t)P_ * nf / 4), 2048), R), blk, 0, st, P_, nf,
              (const float*)pNear_, (const int*)ng_has_.template as<int>(),
              reinterpret_cast<float*>(y));
     };
@@ -3116,6 +3436,12 @@ class EngineT final : public Engine {
   // waits for the graph's completion signal), more than the host's launch
   // time it saves.
   bool gmres_graphs_ = std::getenv("MLFMA_GMRES_GRAPHS") != nullptr;
+  bool gmres_progress_ = std::getenv("MLFMA_GMRES_PROGRESS") != nullptr;
+  // FP32 GEMMs through the LDS-staged kernel where it applies (MLFMA_GEMM=stream: always k_gemm_stream)
+  bool gemm_lds_ = [] {
+    const char* e = std::getenv("MLFMA_GEMM");
+    return !(e && std::string(e) == "stream");
+  }();
 
   static void destroy_entry(GraphEntry& e) {
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
@@ -3154,6 +3480,7 @@ class EngineT final : public Engine {
     if (p.a) {
       hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, p.a, p.b, 0, args...);
       rec_.push_back({p.stage, p.a, p.b});
+      if (table_[p.stage].kernel.empty()) table_[p.stage].kernel = kernel_symbol(reinterpret_cast<const void*>(kernel), st);
       p = Pending{};
     } else {
       hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
@@ -3192,7 +3519,7 @@ class EngineT final : public Engine {
   int tr_force_ = [] {
     const char* e = std::getenv("MLFMA_TRANSLATE");
     const int m = e ? std::atoi(e) : -1;
-    return m >= 0 && m <= (std::is_same<T, float>::value ? 4 : 3) ? m : -1;
+    return m >= 0 && m <= (std::is_same<T, float>::value ? 5 : 3) ? m : -1;
   }();
   DevMem A_proj_, A_recv_, A_near_, iota_;
   DevMem A_proj_h_, A_proj_l_, A_recv_h_, A_recv_l_, A_near_h_, A_near_l_;  // BF16-split copies
@@ -3555,6 +3882,17 @@ int EngineT<T>::gmres_t(const void* bv, void* xv, int R, double rtol, int max_it
     if (int rc = norms(w, rnorm)) return rc;
     for (int r = 0; r < R; ++r)
       if (!done[r] && rnorm[r] <= rtol * bnorm[r]) done[r] = 1;
+    if (gmres_progress_) {  // one line per restart cycle (MLFMA_GMRES_PROGRESS)
+      double worst = 0;
+      int nd = 0;
+      for (int r = 0; r < R; ++r) {
+        worst = std::max(worst, bnorm[r] > 0 ? rnorm[r] / bnorm[r] : 0.0);
+        nd += done[r] ? 1 : 0;
+      }
+      std::fprintf(stderr, "gmres: %d iterations, largest true rel. residual %.3e, %d of %d RHS converged\n",
+                   total_it, worst, nd, R);
+      std::fflush(stderr);
+    }
   }
   hipLaunchKernelGGL(k_from_z<T>, dim3(grid1d(tot)), blk, 0, st, x, reinterpret_cast<CT*>(xv), tot);
   HIP_TRY(hipGetLastError());

@@ -48,6 +48,7 @@ struct GmresResult {
 
 struct StageTime {
   std::string name;
+  std::string kernel;  // symbol of the kernel the stage launched (template arguments included)
   double total_ms = 0;
   long long launches = 0;
   double bytes = 0, flops = 0;

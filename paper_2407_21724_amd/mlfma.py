@@ -50,7 +50,8 @@ class Info(C.Structure):
 
 class StageTime(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("total_ms", C.c_double), ("launches", C.c_int64),
-                ("bytes_per_launch", C.c_double), ("flops_per_launch", C.c_double)]
+                ("bytes_per_launch", C.c_double), ("flops_per_launch", C.c_double),
+                ("kernel", C.c_char * 96)]
 
 
 class Tuning(C.Structure):
@@ -376,7 +377,8 @@ class Context:
         cnt = C.c_int32()
         self._check(lib().mlfma_profile_read(self._h, 128, arr, C.byref(cnt)), "profile_read")
         return [dict(name=a.name.decode(), total_ms=a.total_ms, launches=a.launches,
-                     bytes_per_launch=a.bytes_per_launch, flops_per_launch=a.flops_per_launch)
+                     bytes_per_launch=a.bytes_per_launch, flops_per_launch=a.flops_per_launch,
+                     kernel=a.kernel.decode())
                 for a in arr[: cnt.value]]
 
     def info(self) -> dict:

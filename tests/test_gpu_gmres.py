@@ -145,8 +145,10 @@ def test_c3_batched_64_incidences(prec):
     """64 incidences (polar 5i deg x azimuth 45j deg, TE/TM alternating) on a
     12 x 12 subarray of the cylinders, solved in one batched GMRES with FP32
     or BF16-split products: every RHS reaches its own true residual, the
-    batched product equals the single-RHS products bitwise, and two RHS
-    agree with their single solves."""
+    batched product agrees with the single-RHS products to FP32 rounding
+    (with 64 RHS the FP32 receive GEMM runs on the LDS-staged kernel, which
+    sums its 968 terms in another order than the one-RHS launch), and two
+    RHS agree with their single solves."""
     wl = w.workload("c3", 12, 12)
     v, t, e = wl.meshes[0]
     M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
@@ -157,7 +159,8 @@ def test_c3_batched_64_incidences(prec):
     assert b.shape[0] == 64
     yb = ctx.matvec(b)
     for r in (0, 17, 63):
-        assert torch.equal(ctx.matvec(b[r:r + 1].contiguous()), yb[r:r + 1])
+        y1 = ctx.matvec(b[r:r + 1].contiguous())
+        assert float(torch.linalg.vector_norm(y1 - yb[r:r + 1]) / torch.linalg.vector_norm(y1)) < 2e-6
     x, stats, rc = ctx.gmres_solve(b, rtol=1e-4, max_iter=2000, restart=200)
     res = [s["true_rel_res"] for s in stats]
     its = [s["iterations"] for s in stats]

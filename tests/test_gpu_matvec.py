@@ -180,17 +180,20 @@ def test_interpolation_chunks_do_not_change_the_product(prec):
 @pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C128])
 def test_tiled_translation_matches_gathered_lists(prec):
     """The LDS-tiled translation (4x4, 8x4 and 8x8 box tiles) and, in FP32,
-    the register-tiled one (4x4 boxes, the FP32 default) add the same terms
-    in the same order as the kernel that gathers each box's interaction list,
-    on the 13 x 11 grid (ragged against every tile size) with two RHS.  Only the compiler's choice of fused
-    multiply-adds inside a complex product may differ, so the products agree
-    to a few units in the last place."""
+    the register-tiled one (4x4 boxes, the FP32 default; mode 4 loads the
+    rows of an interior tile's sources one row ahead, mode 5 one row at a
+    time) add the same terms in the same order as the kernel that gathers
+    each box's interaction list, on the 13 x 11 grid (ragged against every
+    tile size, with one interior tile at the finest level) with two RHS.
+    Only the compiler's choice of fused multiply-adds inside a complex
+    product may differ, so the products agree to a few units in the last
+    place."""
     wl = w.workload("c2", 13, 11)
     v, t, e = wl.meshes[0]
     M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
     x = w.random_complex((2, wl.n_particles, 60), 5)
     ys = {}
-    modes = ("0", "1", "2", "3", "4") if prec == mlfma.C64 else ("0", "1", "2", "3")
+    modes = ("0", "1", "2", "3", "4", "5") if prec == mlfma.C64 else ("0", "1", "2", "3")
     for mode in modes:
         os.environ["MLFMA_TRANSLATE"] = mode
         try:
@@ -409,3 +412,53 @@ def test_background_medium_scaling():
     eb_err = rel_err(b, b_exp)
     note(f"background eps 1.69: product rel err {err:.3e}, right-hand side {eb_err:.3e}")
     assert err < TOL and eb_err < 1e-10
+
+
+def _stream_gemm_ctx(wl, M, prec):
+    """A context whose FP32 GEMMs all take k_gemm_stream (the switch is read
+    when the context's engine is created)."""
+    os.environ["MLFMA_GEMM"] = "stream"
+    try:
+        ctx = make_ctx(wl, M, prec)
+        ctx.prepare()
+    finally:
+        del os.environ["MLFMA_GEMM"]
+    return ctx
+
+
+@pytest.mark.parametrize("case,R", [("lens", 16), ("lens", 8), ("lens", 4), ("lens", 12), ("lens", 3),
+                                    ("c2", 8), ("c2", 4)])
+def test_lds_gemm_vs_oracle_and_stream_kernel(case, R):
+    """Batched products through the LDS-staged GEMM (right-hand sides folded
+    into the columns, A staged by its complex entries): RHS 0 is the
+    golden input, checked against the oracle; every RHS against the same
+    product on k_gemm_stream.  Where both kernels sum every tile over k in
+    the same order in one wave (near blocks and projection of the lens,
+    whose K fits one chunk) the near part is equal bit for bit; the receive
+    (K = 968) is summed in another order, so the far part agrees to FP32
+    rounding.  R = 3 takes k_gemm_stream in both contexts."""
+    name = "c4_8x8" if case == "lens" else "c2_6x6"
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path)
+    nx = int(g["nx"])
+    wl = w.workload("c4" if case == "lens" else "c2", nx, nx)
+    M = {int(c): g["M"][i] for i, c in enumerate(g["classes"])} if case == "lens" else g["M"]
+    ctx = make_ctx(wl, M, mlfma.C64)
+    ref = _stream_gemm_ctx(wl, M, mlfma.C64)
+    X = w.random_complex((R, wl.n_particles, 60), 40 + R)
+    X[0] = w.random_complex((1, wl.n_particles, 60), int(g["seed"]))[0]
+    xd = to_dev(X, ctx)
+    y = ctx.matvec(xd).cpu().numpy()
+    yr = ref.matvec(xd).cpu().numpy()
+    yn = ctx.matvec_parts(xd, mlfma.PART_NEAR)
+    ynr = ref.matvec_parts(xd, mlfma.PART_NEAR)
+    err = rel_err(y[0][g["rows"]], g["y"])
+    d = max(rel_err(y[r], yr[r]) for r in range(R))
+    note(f"{name} R={R}: RHS 0 vs oracle {err:.3e}; max per-RHS difference to k_gemm_stream {d:.1e}; "
+         f"near part equal: {bool(torch.equal(yn, ynr))}")
+    assert err < TOL
+    assert d < 2e-6
+    if case == "lens":
+        assert torch.equal(yn, ynr)
