@@ -947,7 +947,12 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
     for (int a = 0; a < ORD; ++a) win[q][a] = C2<T>{0, 0};
   C2<T>* __restrict__ out = A.dst + (((size_t)r * nbp + pb) * 2 + comp) * Kp + j;
   int pn = p0;
-  for (int e = e0; e < e1; ++e) {
+  // one extended row; row e0 + n * ORD + PH goes to window slot PH, so the
+  // window (oldest row first) is slots PH + 1, ..., PH + ORD (mod ORD) and
+  // rotates by renaming instead of moving registers (rows come ORD per
+  // outer iteration, each at its compile-time phase)
+  auto row = [&](auto phase, int e) {
+    constexpr int PH = decltype(phase)::value;
     C2<T>* buf = lds + (e & 1) * 64 * KS;
 #pragma unroll
     for (int k = 0; k < KS; ++k) buf[lane + 64 * k] = (zmask >> k) & 1 ? C2<T>{0, 0} : nxt[k];
@@ -981,11 +986,7 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       for (int q = 0; q < 4; ++q) f[q] = shfl_x32(f[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int a = 0; a + 1 < ORD; ++a) win[q][a] = win[q][a + 1];
-      win[q][ORD - 1] = f[q];
-    }
+    for (int q = 0; q < 4; ++q) win[q][PH] = f[q];
     // parent rows whose theta stencil ends at this extended row (at most 3,
     // in order); the test is uniform over the wave, so only the rows that
     // end here are formed (their phases were loaded for all three
@@ -1004,8 +1005,9 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
         v[q] = C2<T>{0, 0};
 #pragma unroll
         for (int a = 0; a < ORD; ++a) {
-          v[q].x = fmadd(tw[a], win[q][a].x, v[q].x);
-          v[q].y = fmadd(tw[a], win[q][a].y, v[q].y);
+          const C2<T> z = win[q][(PH + 1 + a) % ORD];
+          v[q].x = fmadd(tw[a], z.x, v[q].x);
+          v[q].y = fmadd(tw[a], z.y, v[q].y);
         }
       }
       // phases: child 3 = (+, +) -> E1, child 0 = conj(E1), child 1 =
@@ -1018,6 +1020,16 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       ++nemit;
     }
     pn += nemit;
+  };
+  for (int e = e0; e < e1; e += ORD) {
+    row(std::integral_constant<int, 0>{}, e);
+    if (e + 1 < e1) row(std::integral_constant<int, 1>{}, e + 1);
+    if (e + 2 < e1) row(std::integral_constant<int, 2>{}, e + 2);
+    if (e + 3 < e1) row(std::integral_constant<int, 3>{}, e + 3);
+    if constexpr (ORD > 4) {
+      if (e + 4 < e1) row(std::integral_constant<int, 4 % ORD>{}, e + 4);
+      if (e + 5 < e1) row(std::integral_constant<int, 5 % ORD>{}, e + 5);
+    }
   }
 }
 
