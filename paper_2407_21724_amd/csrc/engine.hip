@@ -456,6 +456,14 @@ __host__ __device__ inline int lds_mode(const GemmJob& j) {
   if (j.nseg == 1 && j.kseg <= kLK) return 0;
   return j.M <= kLM ? 1 : -1;
 }
+// waves per block and column tiles per wave of the LDS kernel for R
+// right-hand sides (W = 0: not applicable, k_gemm_stream runs the job)
+inline void lds_config(int mode, int R, int& W, int& C) {
+  W = C = 0;
+  if (mode == 0 && R % 16 == 0) W = 8, C = 2;
+  else if (R % 8 == 0) W = 8, C = 1;
+  else if (R % 4 == 0) W = 4, C = 1;
+}
 __host__ __device__ inline int lds_blocks(const GemmJob& j, int W, int CT) {
   if (!j.A) return 0;
   const long long cols = (long long)j.ncols * (j.fold > 0 ? j.fold : 1);
@@ -1419,6 +1427,7 @@ __global__ __launch_bounds__(kBlock) void k_translate_tiled(TrLevels<T> L, int R
 // tile starts at even box indices, so a receiver's parity fixes its list).
 // Terms are added in the order of the gathered lists (dy outer, dx inner).
 constexpr int kTrRegTile = 4;
+constexpr int kTrBand = 8;  // tile columns per band in the block order of k_translate_reg
 __host__ __device__ constexpr bool tr_in_list(int rx, int ry, int dx, int dy) {
   return (dx < -1 || dx > 1 || dy < -1 || dy > 1) && dx >= ((rx & 1) ? -3 : -2) && dx <= ((rx & 1) ? 2 : 3) &&
          dy >= ((ry & 1) ? -3 : -2) && dy <= ((ry & 1) ? 2 : 3);
@@ -1446,11 +1455,11 @@ __device__ __forceinline__ void tr_reg_row(C2<float> (&acc)[kTrRegTile * kTrRegT
   }
 }
 // INTERIOR: the 10 x 10 source window lies inside the grid.  Its rows are
-// loaded one row ahead of the row being summed, with no bounds test between
-// a load and its use (a load inside a conditional block makes the compiler
-// wait for every outstanding load there); a scheduling barrier after each
-// row keeps the compiler from hoisting more rows than two rows' registers.
-template <bool INTERIOR, bool PIPE>
+// loaded DEPTH rows ahead of the row being summed, with no bounds test
+// between a load and its use (a load inside a conditional block makes the
+// compiler wait for every outstanding load there); a scheduling barrier
+// after each row keeps the compiler from hoisting further.
+template <bool INTERIOR, int DEPTH>
 __device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2<float>* __restrict__ Gr,
                                             const C2<float> (&t)[7][7], int bx0, int by0, int nx, int ny, int K,
                                             bool live) {
@@ -1462,29 +1471,20 @@ __device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2
     for (int b = 0; b < TT * TT; ++b) acc[b] = C2<float>{0.f, 0.f};
     const C2<float>* __restrict__ Sc = Sr + (size_t)comp * K;
     if constexpr (INTERIOR) {
-      C2<float> cur[H], nxt[H];
+      // rows DEPTH ahead of the one being summed, in a ring of DEPTH + 1
+      C2<float> rb[DEPTH + 1][H];
       auto load_row = [&](int hy, C2<float>(&dst)[H]) {
         const C2<float>* row = Sc + ((size_t)(by0 - 3 + hy) * nx + (bx0 - 3)) * 2 * K;
 #pragma unroll
         for (int hx = 0; hx < H; ++hx) dst[hx] = row[(size_t)hx * 2 * K];
       };
-      if constexpr (PIPE) {
-        load_row(0, cur);
 #pragma unroll
-        for (int hy = 0; hy < H; ++hy) {
-          if (hy + 1 < H) load_row(hy + 1, nxt);
-          tr_reg_row(acc, t, cur, hy, true, bx0, nx);
-          __builtin_amdgcn_sched_barrier(0);
+      for (int d = 0; d < DEPTH; ++d) load_row(d, rb[d]);
 #pragma unroll
-          for (int hx = 0; hx < H; ++hx) cur[hx] = nxt[hx];
-        }
-      } else {  // one row's loads at a time (fewer registers, more waves per SIMD)
-#pragma unroll
-        for (int hy = 0; hy < H; ++hy) {
-          load_row(hy, cur);
-          tr_reg_row(acc, t, cur, hy, true, bx0, nx);
-          __builtin_amdgcn_sched_barrier(0);
-        }
+      for (int hy = 0; hy < H; ++hy) {
+        if (hy + DEPTH < H) load_row(hy + DEPTH, rb[(hy + DEPTH) % (DEPTH + 1)]);
+        tr_reg_row(acc, t, rb[hy % (DEPTH + 1)], hy, true, bx0, nx);
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
 #pragma unroll
@@ -1513,7 +1513,7 @@ __device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2
     }
   }
 }
-template <bool PIPE>
+template <int DEPTH>
 __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) {
   constexpr int TT = kTrRegTile, H = TT + 6;
   const int gb = xcd_block(blockIdx.x, L.total);
@@ -1524,7 +1524,22 @@ __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) 
   const int nch = (K + 63) / 64;
   const int tile = lb % ntile, rest = lb / ntile;
   const int ch = rest % nch, r = rest / nch;
-  const int bx0 = (tile % tx) * TT, by0 = (tile / tx) * TT;
+  // tiles in vertical bands of kTrBand tile columns, row by row within a
+  // band: a tile's upper neighbour (which shares 6 of its 10 source rows)
+  // runs kTrBand blocks earlier instead of a whole tile row earlier, so the
+  // shared rows are still in the XCD's L2
+  const int ty = ntile / tx, nfull = tx / kTrBand;
+  int tix, tiy;
+  if (tile < nfull * kTrBand * ty) {
+    const int band = tile / (kTrBand * ty), t2 = tile - band * kTrBand * ty;
+    tix = band * kTrBand + t2 % kTrBand;
+    tiy = t2 / kTrBand;
+  } else {
+    const int rem = tx - nfull * kTrBand, t3 = tile - nfull * kTrBand * ty;
+    tix = nfull * kTrBand + t3 % rem;
+    tiy = t3 / rem;
+  }
+  const int bx0 = tix * TT, by0 = tiy * TT;
   const int s = ch * 64 + (int)threadIdx.x;
   const bool live = s < K;
   const int sl = live ? s : K - 1;
@@ -1543,9 +1558,9 @@ __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) 
   // the loads of later sources stay in flight (a load inside a conditional
   // block makes the compiler wait for every outstanding load there)
   if (bx0 >= 3 && by0 >= 3 && bx0 + TT + 3 <= nx && by0 + TT + 3 <= ny)
-    tr_reg_tile<true, PIPE>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
+    tr_reg_tile<true, DEPTH>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
   else
-    tr_reg_tile<false, PIPE>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
+    tr_reg_tile<false, DEPTH>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
 }
 
 // ----------------------------------------------------------------- fields --
@@ -2971,10 +2986,13 @@ class EngineT final : public Engine {
           flops += 16.0 * R * (double)pairs_[l] * L.K;
         }
         auto pr = begin("translate", bytes, flops);
-        if (tr_force_ == 5)  // interior rows loaded one at a time (no row ahead)
-          launch(pr, k_translate_reg<false>, dim3(xcd_grid(reg.total)), dim3(64), 0u, st, reg, R);
-        else
-          launch(pr, k_translate_reg<true>, dim3(xcd_grid(reg.total)), dim3(64), 0u, st, reg, R);
+        // source rows of interior tiles loaded 0 (mode 5), 1 (mode 6), 2 (mode 4,
+        // the default) or 3 (mode 7) rows ahead of the row being summed
+        const dim3 g(xcd_grid(reg.total)), b(64);
+        if (tr_force_ == 5) launch(pr, k_translate_reg<0>, g, b, 0u, st, reg, R);
+        else if (tr_force_ == 6) launch(pr, k_translate_reg<1>, g, b, 0u, st, reg, R);
+        else if (tr_force_ == 7) launch(pr, k_translate_reg<3>, g, b, 0u, st, reg, R);
+        else launch(pr, k_translate_reg<2>, g, b, 0u, st, reg, R);
         return;
       }
     }
@@ -3054,9 +3072,7 @@ class EngineT final : public Engine {
     const int md0 = lds_mode(j0u), md1 = j1u.A ? lds_mode(j1u) : md0;
     if (gemm_lds_ && md0 >= 0 && md0 == md1) {
       int W = 0, C = 0;
-      if (md0 == 0 && R % 16 == 0) W = 8, C = 2;
-      else if (R % 8 == 0) W = 8, C = 1;
-      else if (R % 4 == 0) W = 4, C = 1;
+      lds_config(md0, R, W, C);
       if (W) {
         GemmJob a = j0u, b = j1u;
         a.fold = R;
@@ -3236,6 +3252,7 @@ class EngineT final : public Engine {
         const uint32_t sh = (uint32_t)(2 * ((kIStrip / I.d_sw) * 8 * I.d_wlen + 6 * I.d_wlen + 64) * sizeof(CT));
         launch_dis(pr, I.order, I.d_ntap, I.d_sw != kIStrip, dim3(xcd_grid(items)), sh, st, A);
       }
+      // with the receive on k_gemm_lds, the class-pair near sum goes into its store
       if (near && near_grouped) near_sum();
       {
         auto pr = begin("receive", cb * ((double)R * P_ * M2_ + 2.0 * R * P_ * n_ + (double)nc_ * n_ * M2_),
@@ -3531,7 +3548,7 @@ class EngineT final : public Engine {
   int tr_force_ = [] {
     const char* e = std::getenv("MLFMA_TRANSLATE");
     const int m = e ? std::atoi(e) : -1;
-    return m >= 0 && m <= (std::is_same<T, float>::value ? 5 : 3) ? m : -1;
+    return m >= 0 && m <= (std::is_same<T, float>::value ? 7 : 3) ? m : -1;
   }();
   DevMem A_proj_, A_recv_, A_near_, iota_;
   DevMem A_proj_h_, A_proj_l_, A_recv_h_, A_recv_l_, A_near_h_, A_near_l_;  // BF16-split copies
