@@ -344,6 +344,9 @@ def lens_gmres(torch, w, mlfma):
     res = {"workload": "80x80 metalens, 32 classes, 384000 unknowns, normal incidence, FP32 product",
            "restart": 300, "setup_s": setup_s,
            "tuning": os.path.relpath(tfile, ROOT) if os.path.exists(tfile) else "default tile shapes"}
+    # a short solve first allocates the Krylov basis and loads the kernels,
+    # so that neither timed solve pays for them
+    ctx.gmres_solve(b, rtol=1e-4, max_iter=20, restart=300)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, st, _ = ctx.gmres_solve(b, rtol=1e-4, max_iter=4000, restart=300)
