@@ -1764,7 +1764,7 @@ constexpr int kDotMinBlocks = 2048;  // blocks k_dots aims for, over stretches a
 // (the Arnoldi step index on the device) and the group size is derived
 // from it as the host derives it (dot_group); groups past the basis exit.
 template <typename VB>
-constexpr int dot_vu() { return sizeof(VB) == 4 ? 8 : 4; }  // basis vectors loaded per step
+constexpr int dot_vu() { return 4; }  // basis vectors loaded per step
 // vectors per group for nv basis vectors: at most gcap groups (the number
 // of w stretches that makes kDotMinBlocks blocks), each a multiple of VU
 __host__ __device__ inline int dot_group(int nv, int VU, int gcap) {
@@ -1783,9 +1783,9 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, int gsz,
     nv = *jd + 1;
     gsz = dot_group(nv, dot_vu<VB>(), gcap);
   }
-  // per wave: E elements per lane of w held in registers while the group's
-  // basis vectors stream past them once; per-vector wave sums accumulate in
-  // LDS red[vector][wave] (dynamic, (gsz + want_norm) * kBlock / 64 entries)
+  // per wave: its stretches of w (E elements per lane and sweep) against
+  // the group's basis vectors; the wave's sum for each vector goes to LDS
+  // red[vector][wave] (dynamic, (gsz + want_norm) * kBlock / 64 entries)
   extern __shared__ unsigned char smem_raw[];
   Z* red = reinterpret_cast<Z*>(smem_raw);
   constexpr int NW = kBlock / 64;
@@ -1800,14 +1800,23 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, int gsz,
   const Z* wr = w + (size_t)r * Nt;
   const C2<VB>* Vr = V + (size_t)r * Nt + (size_t)v0 * vstride;
   const size_t sweep = (size_t)nblk * NW * 64 * E;
-  for (size_t base = ((size_t)blk * NW + wave) * 64 * E; base < Nt; base += sweep) {
-    Z wv[E];
+  const size_t first = ((size_t)blk * NW + wave) * 64 * E;
+  // per step of VU basis vectors, each lane sums its elements over all of
+  // the wave's sweeps first and the wave reduces once per vector (a wave
+  // reduction costs a chain of six cross-lane exchanges; one per sweep made
+  // the pass four times slower than the subtraction pass over the same
+  // basis); the wave's stretch of w is re-read per step from L2
+  for (int i0 = 0; i0 < cnt; i0 += VU) {
+    double ax[VU], ay[VU];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const size_t k = base + (size_t)e * 64 + lane;
-      wv[e] = k < Nt ? wr[k] : Z{0, 0};
-    }
-    for (int i0 = 0; i0 < cnt; i0 += VU) {
+    for (int u = 0; u < VU; ++u) ax[u] = ay[u] = 0;
+    for (size_t base = first; base < Nt; base += sweep) {
+      Z wv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const size_t k = base + (size_t)e * 64 + lane;
+        wv[e] = k < Nt ? wr[k] : Z{0, 0};
+      }
       C2<VB> v[VU][E];
 #pragma unroll
       for (int u = 0; u < VU; ++u)
@@ -1817,30 +1826,32 @@ __global__ __launch_bounds__(kBlock) void k_dots(int nv, int want_norm, int gsz,
           v[u][e] = (i0 + u < cnt && k < Nt) ? Vr[(size_t)(i0 + u) * vstride + k] : C2<VB>{0, 0};
         }
 #pragma unroll
-      for (int u = 0; u < VU; ++u) {
-        double ax = 0, ay = 0;
+      for (int u = 0; u < VU; ++u)
 #pragma unroll
         for (int e = 0; e < E; ++e) {  // conj(v) w
           const double a = (double)v[u][e].x, b = (double)v[u][e].y;
-          ax += a * wv[e].x + b * wv[e].y;
-          ay += a * wv[e].y - b * wv[e].x;
+          ax[u] += a * wv[e].x + b * wv[e].y;
+          ay[u] += a * wv[e].y - b * wv[e].x;
         }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        if (lane == 0 && i0 + u < cnt) {
-          Z& o = red[(i0 + u) * NW + wave];
-          o.x += ax;
-          o.y += ay;
-        }
+    }
+#pragma unroll
+    for (int u = 0; u < VU; ++u) {
+      const double sx = wave_sum(ax[u]), sy = wave_sum(ay[u]);
+      if (lane == 0 && i0 + u < cnt) red[(i0 + u) * NW + wave] = Z{sx, sy};
+    }
+  }
+  if (norm) {
+    double nn = 0;
+    for (size_t base = first; base < Nt; base += sweep) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const size_t k = base + (size_t)e * 64 + lane;
+        const Z z = k < Nt ? wr[k] : Z{0, 0};
+        nn += z.x * z.x + z.y * z.y;
       }
     }
-    if (norm) {
-      double nn = 0;
-#pragma unroll
-      for (int e = 0; e < E; ++e) nn += wv[e].x * wv[e].x + wv[e].y * wv[e].y;
-      nn = wave_sum(nn);
-      if (lane == 0) red[cnt * NW + wave].x += nn;
-    }
+    nn = wave_sum(nn);
+    if (lane == 0) red[cnt * NW + wave] = Z{nn, 0};
   }
   __syncthreads();
   for (int i = threadIdx.x; i < ns; i += kBlock) {
@@ -2375,7 +2386,7 @@ class EngineT final : public Engine {
     // (padding columns are -1: zero input, not written); one matrix offset
     // per column tile.
     {
-      std::vector<int> part, box, aop, aor;
+      std::vector<int> part, box, aop, aor, aoz;
       const int nf0 = 2 * n_;
       size_t i = 0;
       while (i < u.order.size()) {
@@ -2393,6 +2404,7 @@ class EngineT final : public Engine {
         while (aop.size() < part.size() / 16) {
           aop.push_back(c * 2 * M2_ * nf0);
           aor.push_back(c * nf0 * 2 * M2_);
+          aoz.push_back(c * nf0 * nf0);
         }
         i = e;
       }
@@ -2401,6 +2413,17 @@ class EngineT final : public Engine {
       if (int rc = put_i(gcol_box_, box, err)) return rc;
       if (int rc = put_i(a_off_proj_, aop, err)) return rc;
       if (int rc = put_i(a_off_recv_, aor, err)) return rc;
+      if (int rc = put_i(a_off_zinv_, aoz, err)) return rc;
+      // inverse self blocks of the classes (the block-diagonal preconditioner)
+      std::vector<float> Az((size_t)nc_ * nf0 * nf0, 0.f);
+      for (int c = 0; c < nc_; ++c) {
+        const cd* Zt = u.Zinv[c].data();  // transposed: [k][j]
+        std::vector<float> a((size_t)nf0 * nf0, 0.f);
+        for (int j2 = 0; j2 < n; ++j2)
+          for (int k2 = 0; k2 < n; ++k2) block2(a, nf0, 2 * j2, 2 * k2, Zt[(size_t)k2 * n + j2]);
+        std::copy(a.begin(), a.end(), Az.begin() + (size_t)c * a.size());
+      }
+      if (int rc = put_f(A_zinv_, Az)) return rc;
     }
     if (ntl_ > 0) {
       const int M2 = M2_;
@@ -3313,10 +3336,39 @@ class EngineT final : public Engine {
   int precondition(const void* xv, void* yv, int R, void* stream, std::string& err) override {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     Pending none;
-    launch_near(none, reinterpret_cast<const CT*>(xv), reinterpret_cast<CT*>(yv), R, zinv_.template as<CT>(),
-                self_nbr_.template as<int>(), self_slot_.template as<int>(), self_tile_slot_.template as<int>(), 1, st);
+    if (mfma_ && !bf16_) {  // FP32: each class's inverse self block on the matrix cores, columns grouped by class
+      launch_gemm<4>(none, rt_np_, precond_job(reinterpret_cast<const CT*>(xv), reinterpret_cast<CT*>(yv), rt_np_),
+                     GemmJob{}, R, st);
+    } else {
+      launch_near(none, reinterpret_cast<const CT*>(xv), reinterpret_cast<CT*>(yv), R, zinv_.template as<CT>(),
+                  self_nbr_.template as<int>(), self_slot_.template as<int>(), self_tile_slot_.template as<int>(), 1,
+                  st);
+    }
     HIP_TRY(hipGetLastError());
     return 0;
+  }
+  // y_p = Z_s(class p)^-1 x_p for every particle: the projection's column
+  // grouping with the classes' inverse self blocks as A
+  GemmJob precond_job(const CT* x, CT* y, int rt) const {
+    const int nf = 2 * n_;
+    GemmJob j{};
+    j.A = A_zinv_.template as<float>();
+    j.a_off = a_off_zinv_.template as<int>();
+    j.B = reinterpret_cast<const float*>(x);
+    j.bcol = gcol_part_.template as<int>();
+    j.C = reinterpret_cast<float*>(y);
+    j.ccol = gcol_part_.template as<int>();
+    j.sB = j.sC = (size_t)P_ * nf;
+    j.M = nf;
+    j.ncols = ncols_pad_;
+    j.nseg = 1;
+    j.kseg = nf;
+    j.lda = j.ldb = j.ldc = nf;
+    j.acc = 0;
+    j.tiles_m = (nf + 16 * rt - 1) / (16 * rt);
+    j.tiles = j.tiles_m * (ncols_pad_ / 16);
+    j.wtile = short_k(j);
+    return j;
   }
 
   void launch_near(Pending& pr, const CT* x, CT* y, int R, const CT* mats, const int* nbr, const int* slot,
@@ -3554,6 +3606,7 @@ class EngineT final : public Engine {
   DevMem A_proj_h_, A_proj_l_, A_recv_h_, A_recv_l_, A_near_h_, A_near_l_;  // BF16-split copies
   bool bf16_ = false;  // dense contractions as BF16-split matrix-core products
   DevMem gcol_part_, gcol_box_, a_off_proj_, a_off_recv_;  // class-grouped GEMM columns
+  DevMem A_zinv_, a_off_zinv_;  // the preconditioner's inverse self blocks for the matrix cores
   DevMem ng_bcol_, ng_ccol_, ng_aoff_, ng_has_, near_part_;  // class-pair near GEMM
   int ngcols_ = 0;
   int ncols_pad_ = 0;
