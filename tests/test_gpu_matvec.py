@@ -462,3 +462,28 @@ def test_lds_gemm_vs_oracle_and_stream_kernel(case, R):
     assert d < 2e-6
     if case == "lens":
         assert torch.equal(yn, ynr)
+
+
+@pytest.mark.parametrize("R", [1, 16])
+def test_preconditioner_on_matrix_cores(R):
+    """The block-diagonal preconditioner of an FP32 context runs as a
+    class-grouped GEMM on the matrix cores (the LDS-staged kernel at 16 RHS).
+    On the 8 x 8 lens (six classes) it must match the FP64 context's
+    preconditioner (the per-particle kernel in FP64, which
+    test_c1_rhs_and_preconditioner holds to the oracle's self-block solve to
+    1e-10) to FP32 accuracy, every particle and RHS."""
+    path = os.path.join(GOLDEN, "c4_8x8.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path)
+    nx = int(g["nx"])
+    wl = w.workload("c4", nx, nx)
+    M = {int(c): g["M"][i] for i, c in enumerate(g["classes"])}
+    X = w.random_complex((R, wl.n_particles, 60), 70 + R)
+    z32 = make_ctx(wl, M, mlfma.C64)
+    z64 = make_ctx(wl, M, mlfma.C128)
+    Z = z32.precondition(to_dev(X, z32)).cpu().numpy()
+    ref = z64.precondition(to_dev(X, z64)).cpu().numpy()
+    worst = max(rel_err(Z[r, p], ref[r, p]) for r in range(R) for p in range(wl.n_particles))
+    note(f"preconditioner, {R} RHS: largest per-particle rel. difference to FP64 {worst:.2e}")
+    assert worst < 1e-4
