@@ -100,6 +100,19 @@ def kernel_table(stages, gemm_rows=(4, 4), R=1, multi_class=True):
     return groups
 
 
+def kernel_roofline(g):
+    """Achieved rate of one kernel group against the peak that bounds it."""
+    secs = g["total_ms"] * 1e-3
+    if secs <= 0:
+        return None
+    if g["bound"] == "mfma":
+        a = g["flops"] / secs / 1e12
+        return {"bound": "mfma", "achieved": round(a, 2), "unit": "TFLOP/s",
+                "frac": round(a * 1e12 / FP32_MFMA_PEAK, 4)}
+    a = g["bytes"] / secs / 1e9
+    return {"bound": "hbm", "achieved": round(a, 1), "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4)}
+
+
 def measured_traffic(sym, workload, R):
     """HBM bytes per launch of kernel `sym` from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs of this workload, or None when they are
@@ -619,6 +632,8 @@ def main():
         "hbm_roofline_product_ms": None,
         "stages_us": {s_["name"]: round(1e3 * s_["total_ms"] / s_["launches"], 2) for s_ in stages},
         "kernels_us": {g["kernel"]: round(1e3 * g["total_ms"] / g["launches"], 2) for g in groups.values()},
+        # every kernel against its own roofline (algorithmic bytes or flops over its event time)
+        "kernel_rooflines": {g["kernel"]: kernel_roofline(g) for g in groups.values()},
         "setup_s": setup_s,
         "tuning": tuning,
     }

@@ -37,26 +37,29 @@ def _basis(wl):
     return Ms
 
 
-@pytest.mark.parametrize("case,prec", [("holes", mlfma.C64), ("holes", mlfma.C128), ("lens", mlfma.C64),
-                                       ("lens", mlfma.C64_BF16)])
-def test_noalloc_matches_matvec_two_calls(case, prec):
+@pytest.mark.parametrize("case,prec,ra,rb", [("holes", mlfma.C64, 3, 1), ("holes", mlfma.C128, 3, 1),
+                                             ("lens", mlfma.C64, 3, 1), ("lens", mlfma.C64_BF16, 3, 1),
+                                             ("lens", mlfma.C64, 16, 4)])
+def test_noalloc_matches_matvec_two_calls(case, prec, ra, rb):
+    """ra then rb right-hand sides; 16 and 4 RHS take the LDS-staged GEMMs
+    (class-pair near partials in the scratch)."""
     wl = _cylinders_with_holes() if case == "holes" else _lens()
     ctx = make_ctx(wl, _basis(wl), prec)
     ctx.prepare()
     n = 2 * (wl.n_perp + wl.n_par)
-    xa = to_dev(w.random_complex((3, wl.n_particles, n), 11), ctx)
-    xb = to_dev(w.random_complex((1, wl.n_particles, n), 12), ctx)
+    xa = to_dev(w.random_complex((ra, wl.n_particles, n), 11), ctx)
+    xb = to_dev(w.random_complex((rb, wl.n_particles, n), 12), ctx)
     ya_ref, yb_ref = ctx.matvec(xa), ctx.matvec(xb)
     ya, yb = torch.empty_like(xa), torch.empty_like(xb)
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
-    ctx.matvec_noalloc(xa, ya)            # 3 RHS
-    ctx.matvec_noalloc(xb, yb)            # then 1 RHS in the same scratch
+    ctx.matvec_noalloc(xa, ya)            # ra RHS
+    ctx.matvec_noalloc(xb, yb)            # then rb RHS in the same scratch
     torch.cuda.synchronize()
     free1 = torch.cuda.mem_get_info()[0]
     ea = rel_err(ya.cpu().numpy(), ya_ref.cpu().numpy())
     eb = rel_err(yb.cpu().numpy(), yb_ref.cpu().numpy())
-    note(f"{case} precision={prec}: rel. difference to mlfma_matvec {ea:.1e} (3 RHS), {eb:.1e} (1 RHS); "
+    note(f"{case} precision={prec}: rel. difference to mlfma_matvec {ea:.1e} ({ra} RHS), {eb:.1e} ({rb} RHS); "
          f"free device memory {free0} -> {free1}")
     # the same kernels on the same inputs in the same order: equal bit for bit
     assert torch.equal(ya, ya_ref) and torch.equal(yb, yb_ref)
