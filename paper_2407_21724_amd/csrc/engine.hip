@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 #include <chrono>
 #include <cxxabi.h>
@@ -61,6 +62,15 @@ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
 template <typename T>
 __device__ __forceinline__ C2<T> cmul_conj_a(C2<T> a, C2<T> b) {
   return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+// Element i of the array at p, its byte offset formed in 32 bits: with p
+// uniform over the wave the access takes the scalar-base form of a global
+// load or store (one shift per access instead of a 64-bit address sum).
+// The caller guarantees i * sizeof(U) < 2^32.
+template <typename U>
+__device__ __forceinline__ U& at32(U* p, unsigned i) {
+  using B = typename std::conditional<std::is_const<U>::value, const char, char>::type;
+  return *reinterpret_cast<U*>(reinterpret_cast<B*>(p) + i * (unsigned)sizeof(U));
 }
 
 // Short symbol of a kernel (name and template arguments, without namespace,
@@ -945,7 +955,7 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   auto fetch = [&](int e) {
     const int ro = uni(A.vrow)[e] * A.npc;
 #pragma unroll
-    for (int k = 0; k < KS; ++k) nxt[k] = srcr[so[k] + ((zmask >> k) & 1 ? 0 : ro)];
+    for (int k = 0; k < KS; ++k) nxt[k] = at32(srcr, so[k] + ((zmask >> k) & 1 ? 0 : ro));
   };
   fetch(e0);
   C2<T> win[4][ORD];
@@ -953,7 +963,8 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int a = 0; a < ORD; ++a) win[q][a] = C2<T>{0, 0};
-  C2<T>* __restrict__ out = A.dst + (((size_t)r * nbp + pb) * 2 + comp) * Kp + j;
+  C2<T>* __restrict__ outb = A.dst + ((size_t)r * nbp + pb) * 2 * Kp;  // this parent box's patterns
+  const int oofs = comp * Kp + j;
   int pn = p0;
   // one extended row; row e0 + n * ORD + PH goes to window slot PH, so the
   // window (oldest row first) is slots PH + 1, ..., PH + ORD (mod ORD) and
@@ -970,9 +981,9 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       const int pu = min(pn + u, p1 - 1);
-      const size_t sidx = (size_t)pu * A.npp + j;
-      ea1[u] = A.E[sidx];
-      ea2[u] = A.E[(size_t)Kp + sidx];
+      const int sidx = pu * A.npp + j;
+      ea1[u] = at32(A.E, sidx);
+      ea2[u] = at32(A.E, Kp + sidx);
     }
     if (e + 1 < e1) fetch(e + 1);
     __syncthreads();
@@ -1024,7 +1035,7 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       C2<T> o;
       o.x = a1.x * (v[3].x + v[0].x) - a1.y * (v[3].y - v[0].y) + a2.x * (v[1].x + v[2].x) - a2.y * (v[1].y - v[2].y);
       o.y = a1.x * (v[3].y + v[0].y) + a1.y * (v[3].x - v[0].x) + a2.x * (v[1].y + v[2].y) + a2.y * (v[1].x - v[2].x);
-      if (valid) out[(size_t)pu * A.npp] = o;
+      if (valid) at32(outb, oofs + pu * A.npp) = o;
       ++nemit;
     }
     pn += nemit;
@@ -1126,9 +1137,9 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
     const int ro = p * A.npp;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-      ng[k] = gpr[sgo[k] + ro];
-      ne1[k] = A.E[ro + scol[k]];
-      ne2[k] = A.E[Kp + ro + scol[k]];
+      ng[k] = at32(gpr, sgo[k] + ro);
+      ne1[k] = at32(A.E, ro + scol[k]);
+      ne2[k] = at32(A.E, Kp + ro + scol[k]);
     }
   };
   fetch(pfirst);
@@ -1145,7 +1156,7 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
   auto load_pend = [&]() {
     const int o = uni(A.vrow)[min(ew, nvr - 1)] * A.npc;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) pend[q] = dstr[co[q] + o];
+    for (int q = 0; q < 4; ++q) pend[q] = at32(dstr, co[q] + o);
   };
   load_pend();
   // adds the oldest held row to its child row (if this chunk owns it) and
@@ -1155,7 +1166,7 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
       const int o = uni(A.vrow)[ew] * A.npc;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if ((cmask >> q) & 1) dstr[co[q] + o] = {pend[q].x + acc[q][0].x, pend[q].y + acc[q][0].y};
+        if ((cmask >> q) & 1) at32(dstr, co[q] + o) = C2<T>{pend[q].x + acc[q][0].x, pend[q].y + acc[q][0].y};
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1437,13 +1448,15 @@ __host__ __device__ constexpr bool tr_in_list(int rx, int ry, int dx, int dy) {
 // Sources are visited row by row, column by column, which keeps every
 // receiver's terms in the order of its interaction list (dy outer, dx inner).
 // The terms a source row adds to the tile's receivers:
+// (CHECK: skip the source columns outside the grid; an interior tile has none)
+template <bool CHECK>
 __device__ __forceinline__ void tr_reg_row(C2<float> (&acc)[kTrRegTile * kTrRegTile], const C2<float> (&t)[7][7],
-                                           const C2<float>* sv, int hy, bool ok_row, int bx0, int nx) {
+                                           const C2<float>* sv, int hy, int bx0, int nx) {
   constexpr int TT = kTrRegTile, H = TT + 6;
 #pragma unroll
   for (int hx = 0; hx < H; ++hx) {
     const int gx = bx0 - 3 + hx;
-    if (!ok_row || gx < 0 || gx >= nx) continue;
+    if (CHECK && (gx < 0 || gx >= nx)) continue;
 #pragma unroll
     for (int ry = 0; ry < TT; ++ry)
 #pragma unroll
@@ -1457,10 +1470,13 @@ __device__ __forceinline__ void tr_reg_row(C2<float> (&acc)[kTrRegTile * kTrRegT
 // INTERIOR: the 10 x 10 source window lies inside the grid.  Its rows are
 // loaded DEPTH rows ahead of the row being summed, with no bounds test
 // between a load and its use (a load inside a conditional block makes the
-// compiler wait for every outstanding load there); a scheduling barrier
-// after each row keeps the compiler from hoisting further.
-template <bool INTERIOR, int DEPTH>
-__device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2<float>* __restrict__ Gr,
+// compiler wait for every outstanding load there).  CHK (a slower variant
+// kept for measurement): a column test per source, a branch the compiler
+// cannot remove, with a scheduling barrier after each row, holds the loads
+// to that schedule; without it the compiler is free to issue all of a
+// component's source loads at the top.
+template <bool INTERIOR, int DEPTH, bool CHK>
+__device__ __forceinline__ void tr_reg_tile(const C2<float>* Sr, C2<float>* __restrict__ Gr,
                                             const C2<float> (&t)[7][7], int bx0, int by0, int nx, int ny, int K,
                                             bool live) {
   constexpr int TT = kTrRegTile, H = TT + 6;
@@ -1469,7 +1485,7 @@ __device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2
     C2<float> acc[TT * TT];
 #pragma unroll
     for (int b = 0; b < TT * TT; ++b) acc[b] = C2<float>{0.f, 0.f};
-    const C2<float>* __restrict__ Sc = Sr + (size_t)comp * K;
+    const C2<float>* Sc = Sr + (size_t)comp * K;
     if constexpr (INTERIOR) {
       // rows DEPTH ahead of the one being summed, in a ring of DEPTH + 1
       C2<float> rb[DEPTH + 1][H];
@@ -1483,7 +1499,7 @@ __device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2
 #pragma unroll
       for (int hy = 0; hy < H; ++hy) {
         if (hy + DEPTH < H) load_row(hy + DEPTH, rb[(hy + DEPTH) % (DEPTH + 1)]);
-        tr_reg_row(acc, t, rb[hy % (DEPTH + 1)], hy, true, bx0, nx);
+        tr_reg_row<CHK>(acc, t, rb[hy % (DEPTH + 1)], hy, bx0, nx);
         __builtin_amdgcn_sched_barrier(0);
       }
     } else {
@@ -1498,7 +1514,7 @@ __device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2
           const int gx = bx0 - 3 + hx;
           sv[hx] = (gx >= 0 && gx < nx) ? row[(ptrdiff_t)hx * 2 * K] : C2<float>{0.f, 0.f};
         }
-        tr_reg_row(acc, t, sv, hy, true, bx0, nx);
+        tr_reg_row<true>(acc, t, sv, hy, bx0, nx);
       }
     }
     if (live) {
@@ -1513,7 +1529,7 @@ __device__ __forceinline__ void tr_reg_tile(const C2<float>* __restrict__ Sr, C2
     }
   }
 }
-template <int DEPTH>
+template <int DEPTH, bool CHK>
 __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) {
   constexpr int TT = kTrRegTile, H = TT + 6;
   const int gb = xcd_block(blockIdx.x, L.total);
@@ -1521,6 +1537,10 @@ __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) 
   const TrLevel<float>& V = L.lv[tr_level(L, gb)];
   const int nx = V.nx, ny = V.ny, K = V.K, lb = gb - V.start;
   const int tx = (nx + TT - 1) / TT, ntile = tx * ((ny + TT - 1) / TT);
+  // tile fastest, then sample chunk, then RHS (consecutive blocks of one tile
+  // read neighbouring samples of the same boxes; ordering the RHS before the
+  // chunks, so that one chunk of operators is read by the 16 RHS together,
+  // measured 2% slower on the 200 x 200 lens)
   const int nch = (K + 63) / 64;
   const int tile = lb % ntile, rest = lb / ntile;
   const int ch = rest % nch, r = rest / nch;
@@ -1544,7 +1564,7 @@ __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) 
   const bool live = s < K;
   const int sl = live ? s : K - 1;
   const size_t nb = (size_t)nx * ny;
-  const C2<float>* __restrict__ Sr = V.S + (size_t)r * nb * 2 * K + sl;
+  const C2<float>* Sr = V.S + (size_t)r * nb * 2 * K + sl;
   C2<float>* __restrict__ Gr = V.G + (size_t)r * nb * 2 * K + sl;
   C2<float> t[7][7];
 #pragma unroll
@@ -1558,9 +1578,9 @@ __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) 
   // the loads of later sources stay in flight (a load inside a conditional
   // block makes the compiler wait for every outstanding load there)
   if (bx0 >= 3 && by0 >= 3 && bx0 + TT + 3 <= nx && by0 + TT + 3 <= ny)
-    tr_reg_tile<true, DEPTH>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
+    tr_reg_tile<true, DEPTH, CHK>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
   else
-    tr_reg_tile<false, DEPTH>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
+    tr_reg_tile<false, DEPTH, CHK>(Sr, Gr, t, bx0, by0, nx, ny, K, live);
 }
 
 // ----------------------------------------------------------------- fields --
@@ -2532,6 +2552,13 @@ class EngineT final : public Engine {
       err = "interpolation: odd phi sample counts at level " + std::to_string(l);
       return -1;
     }
+    // the streamed kernels address one RHS's patterns of a level with 32-bit
+    // byte offsets
+    for (const Lvl* V : {&C, &Pp})
+      if ((double)V->nx * V->ny * 2.0 * V->K * sizeof(C2<T>) >= 4294967296.0) {
+        err = "interpolation: one RHS's patterns exceed 4 GiB at level " + std::to_string(l);
+        return -1;
+      }
     // theta: the stencils on the extended rows must be the recorded taps
     for (int p = 0; p < Pp.nt; ++p)
       for (int a = 0; a < ORD; ++a) {
@@ -3009,13 +3036,15 @@ class EngineT final : public Engine {
           flops += 16.0 * R * (double)pairs_[l] * L.K;
         }
         auto pr = begin("translate", bytes, flops);
-        // source rows of interior tiles loaded 0 (mode 5), 1 (mode 6), 2 (mode 4,
-        // the default) or 3 (mode 7) rows ahead of the row being summed
+        // mode 4 (the default): no column tests in interior tiles; modes 5-8:
+        // column tests, source rows of interior tiles loaded 0, 1, 3 or 2 rows
+        // ahead of the row being summed
         const dim3 g(xcd_grid(reg.total)), b(64);
-        if (tr_force_ == 5) launch(pr, k_translate_reg<0>, g, b, 0u, st, reg, R);
-        else if (tr_force_ == 6) launch(pr, k_translate_reg<1>, g, b, 0u, st, reg, R);
-        else if (tr_force_ == 7) launch(pr, k_translate_reg<3>, g, b, 0u, st, reg, R);
-        else launch(pr, k_translate_reg<2>, g, b, 0u, st, reg, R);
+        if (tr_force_ == 5) launch(pr, k_translate_reg<0, true>, g, b, 0u, st, reg, R);
+        else if (tr_force_ == 6) launch(pr, k_translate_reg<1, true>, g, b, 0u, st, reg, R);
+        else if (tr_force_ == 7) launch(pr, k_translate_reg<3, true>, g, b, 0u, st, reg, R);
+        else if (tr_force_ == 8) launch(pr, k_translate_reg<2, true>, g, b, 0u, st, reg, R);
+        else launch(pr, k_translate_reg<2, false>, g, b, 0u, st, reg, R);
         return;
       }
     }
@@ -3594,13 +3623,14 @@ class EngineT final : public Engine {
   bool mfma_ = false, near_uniform_ = false;
   int tr_rpb_ = 1;  // RHS per block of the tiled translation (16 measured slower on the full-scale lens)
   // translation kernel forced on every level: 0 = gathered lists, 1/2/3 = LDS
-  // tiles of 4x4 / 8x4 / 8x8 boxes, 4 = register tiles (FP32); -1 = the
+  // tiles of 4x4 / 8x4 / 8x8 boxes, 4 = register tiles (FP32), 5-8 = register
+  // tiles with column tests (FP32, rows loaded 0, 1, 3, 2 ahead); -1 = the
   // default (register tiles in FP32; in FP64 LDS tiles of 4x4 on grids of at
   // least 8 x 8 boxes or with 4 or more RHS, gathered lists otherwise)
   int tr_force_ = [] {
     const char* e = std::getenv("MLFMA_TRANSLATE");
     const int m = e ? std::atoi(e) : -1;
-    return m >= 0 && m <= (std::is_same<T, float>::value ? 7 : 3) ? m : -1;
+    return m >= 0 && m <= (std::is_same<T, float>::value ? 8 : 3) ? m : -1;
   }();
   DevMem A_proj_, A_recv_, A_near_, iota_;
   DevMem A_proj_h_, A_proj_l_, A_recv_h_, A_recv_l_, A_near_h_, A_near_l_;  // BF16-split copies

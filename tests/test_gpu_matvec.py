@@ -180,9 +180,9 @@ def test_interpolation_chunks_do_not_change_the_product(prec):
 @pytest.mark.parametrize("prec", [mlfma.C64, mlfma.C128])
 def test_tiled_translation_matches_gathered_lists(prec):
     """The LDS-tiled translation (4x4, 8x4 and 8x8 box tiles) and, in FP32,
-    the register-tiled one (4x4 boxes, the FP32 default; an interior tile's
-    source rows are loaded 2 (mode 4), 0 (mode 5), 1 (mode 6) or 3 (mode 7)
-    rows ahead) add the same terms in the same order as the kernel that gathers
+    the register-tiled one (4x4 boxes, the FP32 default, mode 4; modes 5-8
+    test each source column of an interior tile and load its rows 0, 1, 3 or
+    2 rows ahead) add the same terms in the same order as the kernel that gathers
     each box's interaction list, on the 13 x 11 grid (ragged against every
     tile size, with one interior tile at the finest level) with two RHS.
     Only the compiler's choice of fused multiply-adds inside a complex
@@ -193,7 +193,7 @@ def test_tiled_translation_matches_gathered_lists(prec):
     M, _ = mlfma.static_modes(v, t, e, wl.n_perp, wl.n_par)
     x = w.random_complex((2, wl.n_particles, 60), 5)
     ys = {}
-    modes = ("0", "1", "2", "3", "4", "5", "6", "7") if prec == mlfma.C64 else ("0", "1", "2", "3")
+    modes = ("0", "1", "2", "3", "4", "5", "6", "7", "8") if prec == mlfma.C64 else ("0", "1", "2", "3")
     for mode in modes:
         os.environ["MLFMA_TRANSLATE"] = mode
         try:
