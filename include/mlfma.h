@@ -105,6 +105,10 @@ typedef struct {
   int32_t precision;     /* MLFMA_C64, MLFMA_C128 or MLFMA_C64_BF16          */
   int32_t outer_levels;  /* subdivision levels of the outer triangle in the
                             singular (touching-pair) quadrature (2)         */
+  int32_t near_rule;     /* which pairs take the direct (near) blocks: 0 =
+                            the particles in adjacent finest-level boxes,
+                            the 3 x 3 block of boxes around a particle's
+                            own (Sec. IV); the only rule (EINVAL otherwise) */
 } mlfma_tree_params;
 
 typedef struct {
@@ -127,7 +131,7 @@ typedef struct {
 } mlfma_solve_stats;
 
 /* Fill *tp with the defaults: leaf 0.5, L_leaf 11, rule 0, digits 3,
- * interp_order 6, MLFMA_C64, outer_levels 2. */
+ * interp_order 6, MLFMA_C64, outer_levels 2, near_rule 0. */
 void mlfma_default_params(mlfma_tree_params* tp);
 
 /* Build the quadtree, interaction lists and sphere grids for a particle

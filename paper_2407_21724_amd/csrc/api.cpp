@@ -314,6 +314,7 @@ void mlfma_default_params(mlfma_tree_params* tp) {
   tp->interp_order = 6;
   tp->precision = MLFMA_C64;
   tp->outer_levels = 2;
+  tp->near_rule = 0;
 }
 
 int mlfma_build_tree(const mlfma_problem* pb, const mlfma_tree_params* tp, mlfma_ctx** out) {
@@ -329,7 +330,8 @@ int mlfma_build_tree(const mlfma_problem* pb, const mlfma_tree_params* tp, mlfma
     return MLFMA_EINVAL;
   if (tp->precision != MLFMA_C64 && tp->precision != MLFMA_C128 && tp->precision != MLFMA_C64_BF16)
     return MLFMA_EINVAL;
-  if (tp->outer_levels < 0 || tp->outer_levels > 5 || !(tp->digits > 0) || (tp->L_rule != 0 && tp->L_rule != 1))
+  if (tp->outer_levels < 0 || tp->outer_levels > 5 || !(tp->digits > 0) || (tp->L_rule != 0 && tp->L_rule != 1) ||
+      tp->near_rule != 0)
     return MLFMA_EINVAL;
   ctx->tp = *tp;
   if (!std::isfinite(pb->eps_bg_re) || !std::isfinite(pb->eps_bg_im)) return MLFMA_ENONFINITE;

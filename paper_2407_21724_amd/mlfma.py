@@ -39,7 +39,7 @@ class Problem(C.Structure):
 class TreeParams(C.Structure):
     _fields_ = [("leaf_size", C.c_double), ("L_leaf", C.c_int32), ("L_rule", C.c_int32),
                 ("digits", C.c_double), ("interp_order", C.c_int32), ("precision", C.c_int32),
-                ("outer_levels", C.c_int32)]
+                ("outer_levels", C.c_int32), ("near_rule", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -37,7 +37,8 @@ def _problem(centers, cls, ncls=1, **kw):
 
 
 @pytest.mark.parametrize("case", ["off_lattice", "duplicate", "non_planar", "bad_class", "nan", "bad_order",
-                                  "bad_precision", "lossy_background", "negative_background", "nan_background"])
+                                  "bad_precision", "bad_near_rule", "lossy_background", "negative_background",
+                                  "nan_background"])
 def test_build_tree_rejects(case):
     cen = w.lattice(3, 3, 0.5)
     cls = np.zeros(9, np.int32)
@@ -58,6 +59,8 @@ def test_build_tree_rejects(case):
         kw["interp_order"] = 5
     elif case == "bad_precision":
         kw["precision"] = 7
+    elif case == "bad_near_rule":
+        kw["near_rule"] = 1
     with pytest.raises(mlfma.MlfmaError):
         mlfma.Context(cen, cls, 1, mlfma.default_params(**kw), eps_bg=eps_bg)
 
