@@ -37,6 +37,11 @@ template <typename T>
 struct alignas(2 * sizeof(T)) C2 {
   T x, y;
 };
+// two complex values loaded together (one 16-byte load in FP32)
+template <typename T>
+struct alignas(4 * sizeof(T)) CP {
+  C2<T> a, b;
+};
 
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -863,7 +868,7 @@ template <typename T>
 struct InterpArgs {
   const C2<T>* src;          // aggregation: child patterns; disaggregation: parent patterns
   C2<T>* dst;                // aggregation: parent patterns; disaggregation: child patterns (+=)
-  const C2<T>* E;            // [2][K_p] exp(+jk khat . d) for child offsets d = (+a/2, +a/2), (+a/2, -a/2)
+  const CP<T>* E;            // [K_p] exp(+jk khat . d) for the child offsets d = (+a/2, +a/2), (+a/2, -a/2)
   const int* chunk;          // aggregation: parent rows; disaggregation: extended child rows [nch + 1]
   const int* chunk_p;        // disaggregation: parent rows of each chunk [nch][2]
   const int* s0;             // [nt_p] first extended child row of each parent row's theta stencil
@@ -890,8 +895,11 @@ __device__ __forceinline__ const __attribute__((address_space(4))) U* uni(const 
   return (const __attribute__((address_space(4))) U*)p;
 }
 
-// S_P = sum over the children q of phase_q . (Theta Phi S_q)
-template <typename T, int ORD, int SW>
+// S_P = sum over the children q of phase_q . (Theta Phi S_q).  NE: the most
+// parent rows whose theta stencil ends at one extended child row (2 on the
+// excess-bandwidth grids, at most 3), the candidates whose phases each row
+// loads ahead.
+template <typename T, int ORD, int SW, int NE>
 __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   constexpr int G = kIStrip / SW;  // components per wave
   extern __shared__ unsigned char smem_raw[];
@@ -977,13 +985,13 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
     for (int k = 0; k < KS; ++k) buf[lane + 64 * k] = (zmask >> k) & 1 ? C2<T>{0, 0} : nxt[k];
     // the phases of the parent rows this extended row finishes (loaded before
     // the next row's values, so that using them waits for these only)
-    C2<T> ea1[3], ea2[3];
+    C2<T> ea1[NE], ea2[NE];
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
+    for (int u = 0; u < NE; ++u) {
       const int pu = min(pn + u, p1 - 1);
-      const int sidx = pu * A.npp + j;
-      ea1[u] = at32(A.E, sidx);
-      ea2[u] = at32(A.E, Kp + sidx);
+      const CP<T> e = at32(A.E, pu * A.npp + j);
+      ea1[u] = e.a;
+      ea2[u] = e.b;
     }
     if (e + 1 < e1) fetch(e + 1);
     __syncthreads();
@@ -1006,14 +1014,14 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) win[q][PH] = f[q];
-    // parent rows whose theta stencil ends at this extended row (at most 3,
+    // parent rows whose theta stencil ends at this extended row (at most NE,
     // in order); the test is uniform over the wave, so only the rows that
-    // end here are formed (their phases were loaded for all three
-    // candidates, unconditionally, ahead of the next row's values)
+    // end here are formed (their phases were loaded for all NE candidates,
+    // unconditionally, ahead of the next row's values)
     int nemit = 0;
     pn = __builtin_amdgcn_readfirstlane(pn);  // uniform: the tests below branch on the scalar unit
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
+    for (int u = 0; u < NE; ++u) {
       const int pu = min(pn + u, p1 - 1);
       const bool ends = pn + u < p1 && uni(A.s0)[pn + u] + ORD - 1 == e;
       if (!ends) break;
@@ -1138,8 +1146,9 @@ __global__ __launch_bounds__(64) void k_dis_stream(InterpArgs<T> A) {
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       ng[k] = at32(gpr, sgo[k] + ro);
-      ne1[k] = at32(A.E, ro + scol[k]);
-      ne2[k] = at32(A.E, Kp + ro + scol[k]);
+      const CP<T> e = at32(A.E, ro + scol[k]);
+      ne1[k] = e.a;
+      ne2[k] = e.b;
     }
   };
   fetch(pfirst);
@@ -2191,6 +2200,7 @@ class EngineT final : public Engine {
     int order = 0;
     int a_nst = 0, a_wlen = 0, d_nst = 0, d_wlen = 0, d_ntap = 0;
     int a_sw = kIStrip, d_sw = kIStrip;         // strip widths (16: two components per wave)
+    int a_ends = 3;                              // most parent rows ending at one extended child row
     int a_rows = 0, d_rows = 0;                 // rows per chunk set by the tuner (0: planner)
     int a_nch[8] = {}, d_nch[8] = {};           // chunks per batch-size bucket
     int a_coff[8] = {}, d_coff[8] = {};         // offsets of the buckets' chunk tables
@@ -2571,11 +2581,14 @@ class EngineT final : public Engine {
       }
     {
       std::vector<int> ends(nvr, 0);
-      for (int p = 0; p < Pp.nt; ++p)
+      I.a_ends = 1;
+      for (int p = 0; p < Pp.nt; ++p) {
         if (++ends[T0.th_s0[p] + ORD - 1] > 3) {
           err = "interpolation: more than 3 parent rows end at one child row at level " + std::to_string(l);
           return -1;
         }
+        I.a_ends = std::max(I.a_ends, ends[T0.th_s0[p] + ORD - 1]);
+      }
       if (C.nt < ORD) {
         err = "interpolation: fewer child rows than stencil points at level " + std::to_string(l);
         return -1;
@@ -2710,10 +2723,10 @@ class EngineT final : public Engine {
       }
     }
     std::vector<int> vflip(T0.vflip.begin(), T0.vflip.end());
-    std::vector<cd> E((size_t)2 * Pp.K);
+    std::vector<cd> E((size_t)2 * Pp.K);  // pairs, one per parent sample
     for (int s2 = 0; s2 < Pp.K; ++s2) {
-      E[s2] = T0.phase[(size_t)3 * Pp.K + s2];           // child offset (+a/2, +a/2)
-      E[(size_t)Pp.K + s2] = T0.phase[(size_t)1 * Pp.K + s2];  // (+a/2, -a/2)
+      E[(size_t)2 * s2] = T0.phase[(size_t)3 * Pp.K + s2];      // child offset (+a/2, +a/2)
+      E[(size_t)2 * s2 + 1] = T0.phase[(size_t)1 * Pp.K + s2];  // (+a/2, -a/2)
     }
     if (int rc = put_i(I.s0, T0.th_s0, err)) return rc;
     if (int rc = put_i(I.vrow, T0.vrow, err)) return rc;
@@ -3187,7 +3200,7 @@ class EngineT final : public Engine {
     InterpArgs<T> A{};
     A.src = agg ? pS_[l - 1] : pG_[l];
     A.dst = agg ? pS_[l] : pG_[l - 1];
-    A.E = I.E.template as<CT>();
+    A.E = I.E.template as<CP<T>>();
     A.chunk = (agg ? I.chunk_a.template as<int>() : I.chunk_d.template as<int>()) + (agg ? I.a_coff[bk] : I.d_coff[bk]);
     A.chunk_p = agg ? nullptr : I.chunkp_d.template as<int>() + 2 * (I.d_coff[bk] - bk);
     A.s0 = I.s0.template as<int>();
@@ -3285,10 +3298,12 @@ class EngineT final : public Engine {
         const uint32_t sh = (uint32_t)(2 * 64 * (I.a_sw == kIStrip ? kIStage / 2 : 3 * kIStage / 4) * sizeof(CT));
         const dim3 g(xcd_grid(items)), b64(64);
         const bool two = I.a_sw != kIStrip;
-        if (I.order == 6)
-          launch(pr, two ? k_agg_stream<T, 6, 16> : k_agg_stream<T, 6, 32>, g, b64, sh, st, A);
+        if (I.order == 6 && I.a_ends <= 2)
+          launch(pr, two ? k_agg_stream<T, 6, 16, 2> : k_agg_stream<T, 6, 32, 2>, g, b64, sh, st, A);
+        else if (I.order == 6)
+          launch(pr, two ? k_agg_stream<T, 6, 16, 3> : k_agg_stream<T, 6, 32, 3>, g, b64, sh, st, A);
         else
-          launch(pr, two ? k_agg_stream<T, 4, 16> : k_agg_stream<T, 4, 32>, g, b64, sh, st, A);
+          launch(pr, two ? k_agg_stream<T, 4, 16, 3> : k_agg_stream<T, 4, 32, 3>, g, b64, sh, st, A);
       }
       launch_translations(R, st, cb);
       for (int l = ntl_ - 2; l >= 0; --l) {

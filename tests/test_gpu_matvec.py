@@ -97,6 +97,48 @@ def test_single_particle_is_self_block(c1):
     assert rel_err(y, c1["prob"].block(0, 0) @ x[0, 0]) < 1e-13
 
 
+def test_matvec_rejects_bad_arguments(c1):
+    """mlfma_matvec through the raw C ABI: no right-hand sides, x and y the
+    same or overlapping buffers, misaligned pointers and a part mask out of
+    range are EINVAL with a message, and leave y untouched; a class in use
+    without static modes is ENOTREADY."""
+    import ctypes as C
+    L = mlfma.lib()
+    ctx = make_ctx(c1["wl"], c1["pc"].M, mlfma.C64)
+    x = to_dev(c1["x"], ctx)
+    P, n = x.shape[1], x.shape[2]
+    buf = torch.zeros(2, P, n, dtype=x.dtype, device="cuda")
+    y = buf[1]
+    xp, yp = C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())
+    cases = {
+        "R = 0": L.mlfma_matvec(ctx._h, xp, yp, 0, None),
+        "x is y": L.mlfma_matvec(ctx._h, yp, yp, 1, None),
+        "x overlaps y": L.mlfma_matvec(ctx._h, C.c_void_p(buf.data_ptr() + 8 * 16), yp, 1, None),
+        "misaligned y": L.mlfma_matvec(ctx._h, xp, C.c_void_p(y.data_ptr() + 8), 1, None),
+        "part mask 4": L.mlfma_matvec_parts(ctx._h, xp, yp, 1, 4, None),
+    }
+    torch.cuda.synchronize()
+    for what, rc in cases.items():
+        msg = L.mlfma_last_error(ctx._h)
+        note(f"  {what}: rc {rc}")
+        assert rc == mlfma.EINVAL, what
+        assert msg, what
+    assert not torch.any(buf != 0)
+    # the same call with valid arguments goes through
+    assert L.mlfma_matvec(ctx._h, xp, yp, 1, None) == mlfma.OK
+    torch.cuda.synchronize()
+    assert rel_err(y.cpu().numpy(), c1["y"]) < TOL
+    # two classes in use, modes for one only
+    wl = c1["wl"]
+    cls = np.zeros(wl.n_particles, np.int32)
+    cls[1] = 1
+    two = w.Workload("two", wl.centers, cls, [wl.meshes[0], wl.meshes[0]], wl.eps_r, wl.n_perp, wl.n_par)
+    ctx2 = make_ctx(two, {0: c1["pc"].M}, mlfma.C64)
+    rc = L.mlfma_matvec(ctx2._h, xp, yp, 1, None)
+    note(f"  class 1 without modes: rc {rc}, {L.mlfma_last_error(ctx2._h)}")
+    assert rc == mlfma.ENOTREADY
+
+
 def test_far_pair_block_error(c1):
     """Two spheres two sites apart (the middle site empty): the product is
     the self blocks plus one far block through one translation level; its
