@@ -932,18 +932,24 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   if (off < 0) off += A.npc;
   const int lofs = ((g * 4) * 2 + h) * wl + off;  // + q * 2 * wl + buffer * nbuf
   // staging: value v of a row goes to buffer slot v = ((g * 4 + q) * 2 + hh) * wl + c;
-  // its source as an offset into this RHS's child patterns (-1: no child)
+  // its source as an offset into this RHS's child patterns.  With 32-column
+  // strips the windows start at even columns and have even lengths, so a
+  // lane stages two neighbouring columns with one 16-byte load (PR = 2
+  // values per load; a pair never wraps round in phi, since the column
+  // count is even)
   constexpr int KS = SW == kIStrip ? kIStage / 2 : 3 * kIStage / 4;
+  constexpr int PR = SW == kIStrip ? 2 : 1, KL = KS / PR;  // values per load, loads per row
+  using V = typename std::conditional<PR == 2, CP<T>, C2<T>>::type;
   const int PI = pb % A.nxp, PJ = pb / A.nxp;
   const C2<T>* __restrict__ srcr = A.src + (size_t)r * nbc * 2 * Kc;
-  // (every lane loads and stores KS values: a missing child or a slot past
-  // the windows reads a valid address and stores zero, so that no load is
-  // conditional and the next row's loads stay in flight)
-  int so[KS];
+  // (every lane loads and stores KL loads' values: a missing child or a slot
+  // past the windows reads a valid address and stores zero, so that no load
+  // is conditional and the next row's loads stay in flight)
+  int so[KL];
   unsigned zmask = 0;
 #pragma unroll
-  for (int k = 0; k < KS; ++k) {
-    const int v = lane + 64 * k;
+  for (int k = 0; k < KL; ++k) {
+    const int v = PR * (lane + 64 * k);
     so[k] = 0;
     bool live = false;
     if (v < nbuf) {
@@ -951,7 +957,7 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
       const int ci = 2 * PI + (q & 1), cj = 2 * PJ + (q >> 1);
       const int col = (uni(A.wlo)[st * 2 + hh] + c) % A.npc;
       if (ci < A.nxc && cj < A.nyc) {
-        so[k] = ((cj * A.nxc + ci) * 2 + comp0 + gg) * Kc + col;
+        so[k] = (((cj * A.nxc + ci) * 2 + comp0 + gg) * Kc + col) / PR;  // even when PR = 2
         live = true;
       }
     }
@@ -959,11 +965,12 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   }
   const int p0 = uni(A.chunk)[ch], p1 = uni(A.chunk)[ch + 1];
   const int e0 = uni(A.s0)[p0], e1 = uni(A.s0)[p1 - 1] + ORD;
-  C2<T> nxt[KS];
+  const V* __restrict__ srcv = reinterpret_cast<const V*>(srcr);
+  V nxt[KL];
   auto fetch = [&](int e) {
-    const int ro = uni(A.vrow)[e] * A.npc;
+    const int ro = uni(A.vrow)[e] * A.npc / PR;
 #pragma unroll
-    for (int k = 0; k < KS; ++k) nxt[k] = at32(srcr, so[k] + ((zmask >> k) & 1 ? 0 : ro));
+    for (int k = 0; k < KL; ++k) nxt[k] = at32(srcv, so[k] + ((zmask >> k) & 1 ? 0 : ro));
   };
   fetch(e0);
   C2<T> win[4][ORD];
@@ -981,8 +988,9 @@ __global__ __launch_bounds__(64) void k_agg_stream(InterpArgs<T> A) {
   auto row = [&](auto phase, int e) {
     constexpr int PH = decltype(phase)::value;
     C2<T>* buf = lds + (e & 1) * 64 * KS;
+    V* bufv = reinterpret_cast<V*>(buf);
 #pragma unroll
-    for (int k = 0; k < KS; ++k) buf[lane + 64 * k] = (zmask >> k) & 1 ? C2<T>{0, 0} : nxt[k];
+    for (int k = 0; k < KL; ++k) bufv[lane + 64 * k] = (zmask >> k) & 1 ? V{} : nxt[k];
     // the phases of the parent rows this extended row finishes (loaded before
     // the next row's values, so that using them waits for these only)
     C2<T> ea1[NE], ea2[NE];
@@ -2652,24 +2660,28 @@ class EngineT final : public Engine {
         colw_d[(size_t)c * ntap + k] = dense[c][(colb_d[c] + k) % Pp.np] * (double)C.np / (double)Pp.np;
     // windows of the half-waves: strips of sw output columns (16 where half a
     // row fits, so that a wave takes both components)
+    // (pairs: windows start at even columns and have even lengths, for the
+    // aggregation's paired staging loads on 32-column strips)
     auto windows = [](int nout, int nin, const std::vector<int>& colb, int taps, std::vector<int>& wlo, int& nst,
-                      int& sw) {
+                      int& sw, bool pairs) {
       const int ho = nout / 2;
       sw = ho <= kIStrip / 2 ? kIStrip / 2 : kIStrip;
+      pairs = pairs && sw == kIStrip;
       nst = (ho + sw - 1) / sw;
       wlo.assign((size_t)2 * nst, 0);
       int wl = 0;
       for (int st = 0; st < nst; ++st)
         for (int h = 0; h < 2; ++h) {
           const int j0 = st * sw + h * ho, j1 = std::min(st * sw + sw, ho) - 1 + h * ho;
-          wlo[(size_t)st * 2 + h] = colb[j0];
-          wl = std::max(wl, (colb[j1] - colb[j0] + nin) % nin + taps);
+          const int w0 = pairs ? colb[j0] & ~1 : colb[j0];
+          wlo[(size_t)st * 2 + h] = w0;
+          wl = std::max(wl, (colb[j1] - w0 + nin) % nin + taps);
         }
-      return wl;
+      return pairs ? wl + (wl & 1) : wl;
     };
     std::vector<int> wlo_a, wlo_d;
-    I.a_wlen = windows(Pp.np, C.np, colb_a, ORD, wlo_a, I.a_nst, I.a_sw);
-    I.d_wlen = windows(C.np, Pp.np, colb_d, ntap, wlo_d, I.d_nst, I.d_sw);
+    I.a_wlen = windows(Pp.np, C.np, colb_a, ORD, wlo_a, I.a_nst, I.a_sw, true);
+    I.d_wlen = windows(C.np, Pp.np, colb_d, ntap, wlo_d, I.d_nst, I.d_sw, false);
     I.d_ntap = ntap;
     // staged values per lane and row: the aggregation's four children (4, or
     // 6 with two components per wave), the disaggregation's parent (3)
