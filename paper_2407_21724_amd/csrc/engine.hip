@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 #include <cstdint>
 #include <chrono>
 #include <cxxabi.h>
@@ -1275,7 +1276,20 @@ struct TrLevel {
   const C2<T>* TL;
   const int *il_cnt, *il_src, *il_off;
   int nx, ny, K, start;
+  const CP<T>* TLp;  // FP32 register tiles: the 40 far offsets' operators in pairs, [20][K]
 };
+// The n-th of the 40 offsets (dx, dy) with |dx| or |dy| >= 2 in the 7 x 7
+// block, in row order (dy outer, dx inner), as the index (dy + 3) * 7 + dx + 3
+__host__ __device__ constexpr int tr_far_offset(int n) {
+  for (int i = 0, m = 0; i < 49; ++i) {
+    const int dx = i % 7 - 3, dy = i / 7 - 3;
+    if (dx < -1 || dx > 1 || dy < -1 || dy > 1) {
+      if (m == n) return i;
+      ++m;
+    }
+  }
+  return -1;
+}
 constexpr int kMaxTrLv = 12;
 template <typename T>
 struct TrLevels {
@@ -1546,6 +1560,20 @@ __device__ __forceinline__ void tr_reg_tile(const C2<float>* Sr, C2<float>* __re
     }
   }
 }
+// operator pair Q of the far offsets into t (indices fixed at compile time,
+// so that t stays in registers)
+template <int Q>
+__device__ __forceinline__ void tr_put_pair(C2<float> (&t)[7][7], CP<float> e) {
+  constexpr int i0 = tr_far_offset(2 * Q), i1 = tr_far_offset(2 * Q + 1);
+  t[i0 / 7][i0 % 7] = e.a;
+  t[i1 / 7][i1 % 7] = e.b;
+}
+template <int... Q>
+__device__ __forceinline__ void tr_load_ops(C2<float> (&t)[7][7], const CP<float>* p, int K,
+                                            std::integer_sequence<int, Q...>) {
+  const CP<float> e[] = {p[(size_t)Q * K]...};
+  (tr_put_pair<Q>(t, e[Q]), ...);
+}
 template <int DEPTH, bool CHK>
 __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) {
   constexpr int TT = kTrRegTile, H = TT + 6;
@@ -1583,13 +1611,13 @@ __global__ __launch_bounds__(64) void k_translate_reg(TrLevels<float> L, int R) 
   const size_t nb = (size_t)nx * ny;
   const C2<float>* Sr = V.S + (size_t)r * nb * 2 * K + sl;
   C2<float>* __restrict__ Gr = V.G + (size_t)r * nb * 2 * K + sl;
+  // the 40 operators of this sample, two per 16-byte load
   C2<float> t[7][7];
 #pragma unroll
-  for (int dy = -3; dy <= 3; ++dy)
+  for (int dy = 0; dy < 7; ++dy)
 #pragma unroll
-    for (int dx = -3; dx <= 3; ++dx)
-      t[dy + 3][dx + 3] = (dx < -1 || dx > 1 || dy < -1 || dy > 1) ? V.TL[(size_t)((dy + 3) * 7 + dx + 3) * K + sl]
-                                                                  : C2<float>{0.f, 0.f};
+    for (int dx = 0; dx < 7; ++dx) t[dy][dx] = C2<float>{0.f, 0.f};
+  tr_load_ops(t, V.TLp + sl, K, std::make_integer_sequence<int, 20>{});
   // tiles whose 10 x 10 source window lies inside the grid take a path with
   // no bounds tests, so that no branch separates a load from its use and
   // the loads of later sources stay in flight (a load inside a conditional
@@ -2196,7 +2224,7 @@ class EngineT final : public Engine {
   };
   struct Lvl {
     int nx, ny, nt, np, K;
-    DevMem TL;
+    DevMem TL, TLp;  // TLp: FP32 only, the far offsets' operators in pairs
     DevMem il_cnt, il_src, il_off;  // interaction lists
     DevMem S, G;  // pattern buffers, sized for R_alloc
   };
@@ -2248,6 +2276,14 @@ class EngineT final : public Engine {
       L.np = g.np;
       L.K = g.K;
       if (int rc = put_c(L.TL, tr.TL[l], err)) return rc;
+      if constexpr (std::is_same<T, float>::value) {
+        std::vector<cd> tlp((size_t)40 * L.K);
+        for (int q = 0; q < 20; ++q)
+          for (int s2 = 0; s2 < L.K; ++s2)
+            for (int h = 0; h < 2; ++h)
+              tlp[((size_t)q * L.K + s2) * 2 + h] = tr.TL[l][(size_t)tr_far_offset(2 * q + h) * L.K + s2];
+        if (int rc = put_c(L.TLp, tlp, err)) return rc;
+      }
       // interaction lists: children of the parent's neighbours that are not
       // neighbours themselves
       std::vector<int> cnt(L.nx * L.ny, 0), src((size_t)L.nx * L.ny * kMaxIL, 0), off((size_t)L.nx * L.ny * kMaxIL, 0);
@@ -3053,8 +3089,8 @@ class EngineT final : public Engine {
         for (int l = 0; l < ntl_; ++l) {
           const Lvl& L = lv_[l];
           TrLevel<float>& V = reg.lv[reg.n++];
-          V = TrLevel<float>{pS_[l], pG_[l], L.TL.template as<CT>(), nullptr, nullptr, nullptr, L.nx, L.ny, L.K,
-                             reg.total};
+          V = TrLevel<float>{pS_[l], pG_[l],     L.TL.template as<CT>(), nullptr, nullptr, nullptr, L.nx,
+                             L.ny,   L.K,    reg.total,                  L.TLp.template as<CP<float>>()};
           reg.total += ((L.nx + kTrRegTile - 1) / kTrRegTile) * ((L.ny + kTrRegTile - 1) / kTrRegTile) *
                        ((L.K + 63) / 64) * R;
           bytes += cb * (4.0 * R * L.nx * L.ny * L.K + 40.0 * L.K);
@@ -3492,7 +3528,7 @@ class EngineT final : public Engine {
 
   long long device_bytes() const override {
     long long s = 0;
-    for (auto& L : lv_) s += L.TL.bytes + L.S.bytes + L.G.bytes;
+    for (auto& L : lv_) s += L.TL.bytes + L.TLp.bytes + L.S.bytes + L.G.bytes;
     for (auto& I : it_)
       s += I.s0.bytes + I.vrow.bytes + I.vflip.bytes + I.thw_a.bytes + I.thw_d.bytes + I.colb_a.bytes +
            I.colw_a.bytes + I.colb_d.bytes + I.colw_d.bytes + I.wlo_a.bytes + I.wlo_d.bytes + I.E.bytes +
