@@ -2685,7 +2685,8 @@ class EngineT final : public Engine {
       cnt_d[c] = cnt;
       ntap = std::max(ntap, cnt);
     }
-    ntap = ntap <= 8 ? 8 : ntap <= 12 ? 12 : ntap <= 16 ? 16 : -1;
+    // (10 taps, the finest levels' count with 6-point stencils, only with those)
+    ntap = ntap <= 8 ? 8 : ntap <= 10 && ORD == 6 ? 10 : ntap <= 12 ? 12 : ntap <= 16 ? 16 : -1;
     if (ntap < 0) {
       err = "interpolation: more than 16 transposed phi taps at level " + std::to_string(l);
       return -1;
@@ -3231,6 +3232,7 @@ class EngineT final : public Engine {
                   const InterpArgs<T>& A) {
     if (order == 6) {
       if (ntap == 8) launch_dis_nt<6, 8>(pr, two, g, sh, st, A);
+      else if (ntap == 10) launch_dis_nt<6, 10>(pr, two, g, sh, st, A);
       else if (ntap == 12) launch_dis_nt<6, 12>(pr, two, g, sh, st, A);
       else launch_dis_nt<6, 16>(pr, two, g, sh, st, A);
     } else {
