@@ -337,6 +337,14 @@ int mlfma_debug_pair_block_device(mlfma_ctx* ctx, int32_t cp, int32_t cq, int32_
 int mlfma_debug_leaf_pattern(mlfma_ctx* ctx, int32_t c, double* out);
 int mlfma_debug_level_grid(mlfma_ctx* ctx, int32_t level, double* khat, double* w);
 int mlfma_debug_translation(mlfma_ctx* ctx, int32_t level, int32_t dx, int32_t dy, double* out);
+/* The separable Lagrange interpolation of aggregation (Sec. IV: a pattern
+ * sampled at level l - 1 resampled on the finer grid of level l, before
+ * the phase shift to the parent centre), applied on the host in FP64 with
+ * the stencil tables the kernels use: in [K_{l-1}][2] and out [K_l][2]
+ * (theta, phi components; interleaved complex; sample index row * np + col).
+ * A stencil tap across a pole reads the row at phi + pi with both transverse
+ * components negated.  1 <= level < n_levels.  Host-only. */
+int mlfma_debug_interpolate(mlfma_ctx* ctx, int32_t level, const double* in, double* out);
 
 /* ------------------------------------------------ learned initial guess --
  * A fully connected ReLU network, trained on solutions the method itself

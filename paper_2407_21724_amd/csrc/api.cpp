@@ -807,6 +807,36 @@ int mlfma_debug_level_grid(mlfma_ctx* ctx, int32_t level, double* khat, double* 
   return MLFMA_OK;
 }
 
+int mlfma_debug_interpolate(mlfma_ctx* ctx, int32_t level, const double* in, double* out) {
+  if (!ctx || !in || !out) return MLFMA_EINVAL;
+  return guarded(ctx, [&]() -> int {
+    if (level < 1 || level >= ctx->tree.ntl) return fail(ctx, MLFMA_EINVAL, "level out of range");
+    const LevelGrid &c = ctx->tree.lv[level - 1], &p = ctx->tree.lv[level];
+    const InterpTables& T = ctx->tree.it[level];
+    const int ord = T.order;
+    const cd* u = reinterpret_cast<const cd*>(in);
+    cd* v = reinterpret_cast<cd*>(out);
+    for (int it = 0; it < p.nt; ++it)
+      for (int ip = 0; ip < p.np; ++ip)
+        for (int comp = 0; comp < 2; ++comp) {
+          cd acc = 0;
+          for (int a = 0; a < ord; ++a) {
+            const size_t ta = (size_t)it * ord + a;
+            const int row = T.th_row[ta], shift = T.th_flip[ta] ? c.np / 2 : 0;
+            cd rs = 0;
+            for (int b = 0; b < ord; ++b) {
+              const size_t pb = (size_t)ip * ord + b;
+              const int col = (T.ph_col[pb] + shift) % c.np;
+              rs += T.ph_w[pb] * u[((size_t)row * c.np + col) * 2 + comp];
+            }
+            acc += T.th_w[ta] * rs;
+          }
+          v[((size_t)it * p.np + ip) * 2 + comp] = acc;
+        }
+    return MLFMA_OK;
+  });
+}
+
 int mlfma_debug_translation(mlfma_ctx* ctx, int32_t level, int32_t dx, int32_t dy, double* out) {
   if (!ctx || !out) return MLFMA_EINVAL;
   return guarded(ctx, [&]() -> int {

@@ -69,7 +69,7 @@ EXPORTS = [
     "mlfma_prepare", "mlfma_plane_wave_rhs", "mlfma_matvec", "mlfma_matvec_parts", "mlfma_matvec_noalloc",
     "mlfma_precondition", "mlfma_gmres_solve", "mlfma_fields", "mlfma_info", "mlfma_destroy", "mlfma_last_error",
     "mlfma_debug_near_block", "mlfma_debug_pair_block_device", "mlfma_debug_leaf_pattern", "mlfma_debug_level_grid",
-    "mlfma_debug_translation", "mlfma_profile", "mlfma_profile_read", "mlfma_share_setup",
+    "mlfma_debug_translation", "mlfma_debug_interpolate", "mlfma_profile", "mlfma_profile_read", "mlfma_share_setup",
     "mlfma_mlp_create", "mlfma_mlp_destroy", "mlfma_mlp_last_error", "mlfma_mlp_num_params",
     "mlfma_mlp_get_params", "mlfma_mlp_set_params", "mlfma_mlp_forward", "mlfma_mlp_loss_grad",
     "mlfma_mlp_train_step", "mlfma_learned_guess", "mlfma_guess_features", "mlfma_set_tuning",
@@ -108,6 +108,7 @@ def load_library(path: str = _LIB_PATH):
         "mlfma_debug_leaf_pattern": (C.c_int, [ctxp, C.c_int32, dp]),
         "mlfma_debug_level_grid": (C.c_int, [ctxp, C.c_int32, dp, dp]),
         "mlfma_debug_translation": (C.c_int, [ctxp, C.c_int32, C.c_int32, C.c_int32, dp]),
+        "mlfma_debug_interpolate": (C.c_int, [ctxp, C.c_int32, dp, dp]),
         "mlfma_share_setup": (C.c_int, [ctxp, ctxp]),
         "mlfma_set_tuning": (C.c_int, [ctxp, C.POINTER(Tuning)]),
         "mlfma_get_tuning": (C.c_int, [ctxp, C.POINTER(Tuning)]),
@@ -421,6 +422,17 @@ class Context:
         w = np.zeros(K)
         self._check(lib().mlfma_debug_level_grid(self._h, level, _dptr(kh), _dptr(w)), "debug_level_grid")
         return kh, w
+
+    def debug_interpolate(self, level, pattern):
+        """pattern: [K_{level-1}][2] complex (theta, phi) -> [K_level][2]."""
+        K = self.info()["K"]
+        u = np.ascontiguousarray(pattern, complex)
+        if u.shape != (K[level - 1], 2):
+            raise ValueError(f"expected a pattern of shape {(K[level - 1], 2)}")
+        out = np.zeros((K[level], 2), complex)
+        self._check(lib().mlfma_debug_interpolate(self._h, level, u.ctypes.data_as(C.POINTER(C.c_double)),
+                                                  out.ctypes.data_as(C.POINTER(C.c_double))), "debug_interpolate")
+        return out
 
     def debug_translation(self, level, dx, dy):
         K = self.info()["K"][level]

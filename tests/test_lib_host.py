@@ -179,6 +179,65 @@ def test_translation_tables_reproduce_greens_function(level):
     assert np.median(errs) < 2e-3
 
 
+def _transverse_basis(kh):
+    th = np.arccos(np.clip(kh[:, 2], -1, 1))
+    phi = np.arctan2(kh[:, 1], kh[:, 0])
+    th_hat = np.stack([np.cos(th) * np.cos(phi), np.cos(th) * np.sin(phi), -np.sin(th)], -1)
+    ph_hat = np.stack([-np.sin(phi), np.cos(phi), 0 * phi], -1)
+    return th_hat, ph_hat
+
+
+def _source_pattern(kh, r0, p):
+    """Transverse far pattern of a point current p at r0 (closed form):
+    exp(+jk khat . r0) (p . theta_hat, p . phi_hat)."""
+    th_hat, ph_hat = _transverse_basis(kh)
+    e = np.exp(1j * 2 * np.pi * (kh @ r0))
+    return np.stack([e * (th_hat @ p), e * (ph_hat @ p)], 1)
+
+
+def test_interpolation_tables_resample_source_patterns():
+    """Aggregation's interpolation (Sec. IV: Lagrange stencils in theta and
+    phi between the level grids, a pole crossing read at phi + pi with both
+    transverse components negated), applied by the host in FP64 with the
+    kernels' tables, against closed forms: the pattern of a point current in
+    a child box, sampled on the child grid and resampled on the parent grid,
+    equals the same closed form at the parent directions.  The error falls
+    with the stencil order (4 to 6) and as the source nears the box centre
+    (narrower band), and is as small on the rows next to the poles as
+    elsewhere (a wrong pole convention gives errors of order one there).
+    Rows whose stencils reach no pole reflection reproduce constant
+    components exactly (partition of unity)."""
+    cen = w.lattice(40, 40, 0.5)
+    p = np.array([0.3, -0.5, 0.8])
+    err = {}
+    for order in (4, 6):
+        ctx = mlfma.Context(cen, np.zeros(len(cen), np.int32), 1, mlfma.default_params(interp_order=order))
+        inf = ctx.info()
+        assert inf["n_levels"] == 5
+        for lev in range(1, inf["n_levels"]):
+            khc, _ = ctx.debug_level_grid(lev - 1)
+            khp, wp = ctx.debug_level_grid(lev)
+            a_c = 0.5 * 2 ** (lev - 1)
+            npp, ntp = 2 * inf["L"][lev], inf["L"][lev]
+            for frac in (0.5, 0.25):            # a child box corner, and halfway to the centre
+                r0 = np.array([frac, frac, 0.0]) * a_c
+                out = ctx.debug_interpolate(lev, _source_pattern(khc, r0, p))
+                ex = _source_pattern(khp, r0, p)
+                d = np.abs(out - ex)
+                e2 = math.sqrt((wp[:, None] * d ** 2).sum() / (wp[:, None] * np.abs(ex) ** 2).sum())
+                pole = np.r_[0:3 * npp, (ntp - 3) * npp:ntp * npp]
+                err[order, lev, frac] = (e2, d[pole].max() / np.abs(ex).max())
+            const = np.tile([1.0 + 0.5j, -0.25 + 2j], (len(khc), 1))
+            mid = ctx.debug_interpolate(lev, const)[(ntp // 3) * npp:(2 * ntp // 3) * npp]
+            assert np.abs(mid - const[0]).max() < 1e-12, (order, lev)
+    for lev in range(1, 5):
+        e6, p6 = err[6, lev, 0.5]
+        e4, _ = err[4, lev, 0.5]
+        assert e6 < 3e-3 and p6 < 2e-2, (lev, e6, p6)
+        assert e6 < e4 / 2, (lev, e6, e4)
+        assert err[6, lev, 0.25][0] < e6 / 4, lev
+
+
 def test_set_static_modes_rejects_bad_input(sphere_setup):
     wl, Mo, _ = sphere_setup
     v, t, e = wl.meshes[0]
