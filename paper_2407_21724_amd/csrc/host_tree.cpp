@@ -107,7 +107,6 @@ static void build_interp(const LevelGrid& c, const LevelGrid& p, int order, doub
   T.th_row.assign((size_t)p.nt * order, 0);
   T.th_w.assign((size_t)p.nt * order, 0.0);
   T.th_flip.assign((size_t)p.nt * order, 0);
-  std::vector<double> dense_direct((size_t)c.nt * p.nt, 0.0), dense_flip((size_t)c.nt * p.nt, 0.0);
   for (int it = 0; it < p.nt; ++it) {
     const double th = p.theta[it];
     int j0 = (int)(std::upper_bound(ext.begin(), ext.end(), th) - ext.begin()) - 1;
@@ -122,13 +121,11 @@ static void build_interp(const LevelGrid& c, const LevelGrid& p, int order, doub
       T.th_row[(size_t)it * order + a] = ext_row[e];
       T.th_w[(size_t)it * order + a] = sw;
       T.th_flip[(size_t)it * order + a] = (uint8_t)ext_flip[e];
-      (ext_flip[e] ? dense_flip : dense_direct)[(size_t)ext_row[e] * p.nt + it] += sw;
     }
   }
   const double dpc = 2.0 * kPi / c.np;
   T.ph_col.assign((size_t)p.np * order, 0);
   T.ph_w.assign((size_t)p.np * order, 0.0);
-  std::vector<double> dense_phi((size_t)c.np * p.np, 0.0);
   for (int ip = 0; ip < p.np; ++ip) {
     const double ph = ip * 2.0 * kPi / p.np;
     int i0 = (int)std::floor(ph / dpc + 1e-12);
@@ -139,56 +136,8 @@ static void build_interp(const LevelGrid& c, const LevelGrid& p, int order, doub
       int col = ((i0 - half + 1 + b) % c.np + c.np) % c.np;
       T.ph_col[(size_t)ip * order + b] = col;
       T.ph_w[(size_t)ip * order + b] = wts[b];
-      dense_phi[(size_t)col * p.np + ip] += wts[b];
     }
   }
-  // transposed theta with weights wtheta_p / wtheta_c
-  T.tmax = 0;
-  std::vector<std::vector<std::array<double, 3>>> lists(c.nt);
-  for (int ic = 0; ic < c.nt; ++ic)
-    for (int it = 0; it < p.nt; ++it) {
-      double wd = dense_direct[(size_t)ic * p.nt + it], wf = dense_flip[(size_t)ic * p.nt + it];
-      double sc = p.wtheta[it] / c.wtheta[ic];
-      if (wd != 0.0) lists[ic].push_back({(double)it, wd * sc, 0.0});
-      if (wf != 0.0) lists[ic].push_back({(double)it, wf * sc, 1.0});
-    }
-  for (auto& l : lists) T.tmax = std::max<int>(T.tmax, (int)l.size());
-  T.tth_row.assign((size_t)c.nt * T.tmax, 0);
-  T.tth_w.assign((size_t)c.nt * T.tmax, 0.0);
-  T.tth_flip.assign((size_t)c.nt * T.tmax, 0);
-  T.tth_lo.assign(c.nt, 0);
-  T.tth_hi.assign(c.nt, 0);
-  for (int ic = 0; ic < c.nt; ++ic) {
-    int lo = p.nt, hi = -1;
-    for (size_t e = 0; e < lists[ic].size(); ++e) {
-      int row = (int)lists[ic][e][0];
-      T.tth_row[(size_t)ic * T.tmax + e] = row;
-      T.tth_w[(size_t)ic * T.tmax + e] = lists[ic][e][1];
-      T.tth_flip[(size_t)ic * T.tmax + e] = (uint8_t)lists[ic][e][2];
-      lo = std::min(lo, row);
-      hi = std::max(hi, row);
-    }
-    if (hi < 0) lo = hi = 0;
-    for (size_t e = lists[ic].size(); e < (size_t)T.tmax; ++e) T.tth_row[(size_t)ic * T.tmax + e] = lo;
-    T.tth_lo[ic] = lo;
-    T.tth_hi[ic] = hi;
-  }
-  // transposed phi with weight np_c / np_p
-  T.pmax = 0;
-  std::vector<std::vector<std::pair<int, double>>> pl(c.np);
-  for (int ic = 0; ic < c.np; ++ic)
-    for (int ip = 0; ip < p.np; ++ip) {
-      double wv = dense_phi[(size_t)ic * p.np + ip];
-      if (wv != 0.0) pl[ic].push_back({ip, wv * (double)c.np / (double)p.np});
-    }
-  for (auto& l : pl) T.pmax = std::max<int>(T.pmax, (int)l.size());
-  T.tph_col.assign((size_t)c.np * T.pmax, 0);
-  T.tph_w.assign((size_t)c.np * T.pmax, 0.0);
-  for (int ic = 0; ic < c.np; ++ic)
-    for (size_t e = 0; e < pl[ic].size(); ++e) {
-      T.tph_col[(size_t)ic * T.pmax + e] = pl[ic][e].first;
-      T.tph_w[(size_t)ic * T.pmax + e] = pl[ic][e].second;
-    }
   // phases for the four child quadrants
   T.phase.assign((size_t)4 * p.K, 0.0);
   for (int q = 0; q < 4; ++q) {

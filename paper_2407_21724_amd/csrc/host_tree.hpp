@@ -21,8 +21,9 @@ struct LevelGrid {
   std::vector<V3> khat, th_hat, ph_hat;
 };
 
-// Separable Lagrange interpolation from child level (l-1) to parent (l),
-// its quadrature-weighted transpose, and the child-to-parent phase shifts.
+// Separable Lagrange interpolation from child level (l-1) to parent (l) and
+// the child-to-parent phase shifts (the kernels' anterpolation, its
+// quadrature-weighted transpose, is built from these tables by the engine).
 struct InterpTables {
   int order = 4;
   // forward theta: for each parent row, `order` (child row, signed weight,
@@ -40,18 +41,6 @@ struct InterpTables {
   // forward phi: for each parent column, `order` (child column, weight)
   std::vector<int> ph_col;
   std::vector<double> ph_w;
-  // transposed theta (anterpolation): for each child row, tmax entries
-  // (parent row, weight * wtheta_p/wtheta_c, flip); padded with weight 0
-  int tmax = 0;
-  std::vector<int> tth_row;
-  std::vector<double> tth_w;
-  std::vector<uint8_t> tth_flip;
-  std::vector<int> tth_lo, tth_hi;  // per child row: parent row range used
-  // transposed phi: for each child column, pmax entries (parent column,
-  // weight * np_c/np_p); padded with weight 0
-  int pmax = 0;
-  std::vector<int> tph_col;
-  std::vector<double> tph_w;
   // exp(+j k khat . d_q) at the parent samples for child quadrant q =
   // 2*by + bx, d_q = ((bx - 1/2) a_c, (by - 1/2) a_c, 0): [4][K_p]
   std::vector<cd> phase;
