@@ -65,3 +65,24 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
+    """bench.py reports counter traffic for a kernel only from a digest
+    taken on the same engine source: the bytes per launch while the hash
+    matches, None once the source has changed or the digest is missing."""
+    rec = {"workload": "c5", "source_sha256": "abc", "calibration": {"fetch_scale": 2.0, "write_scale": 1.0},
+           "kernels": {"k_translate_reg<2, false>": {"dispatches": 12, "fetch_bytes_per_launch": 3.0e9,
+                                                    "write_bytes_per_launch": 1.0e9,
+                                                    "traffic_bytes_per_launch": 4.0e9}}}
+    path = tmp_path / "pmc_traffic_c5_r16.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "traffic_file", lambda workload, R: str(path))
+    monkeypatch.setattr(bench, "source_digest", lambda: "abc")
+    assert bench.measured_traffic("k_translate_reg<2, false>", "c5", 16) == pytest.approx(4.0e9)
+    assert bench.measured_traffic("k_agg_stream<float, 6, 32, 2>", "c5", 16) is None
+    monkeypatch.setattr(bench, "source_digest", lambda: "def")
+    assert bench.measured_traffic("k_translate_reg<2, false>", "c5", 16) is None
+    monkeypatch.setattr(bench, "traffic_file", lambda workload, R: str(tmp_path / "missing.json"))
+    monkeypatch.setattr(bench, "source_digest", lambda: "abc")
+    assert bench.measured_traffic("k_translate_reg<2, false>", "c5", 16) is None
